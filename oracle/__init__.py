@@ -1,0 +1,271 @@
+"""CPU oracle for the SPH pack / interact / unpack path.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke entry and the benchmark's CPU
+baseline leg are the only callers.  The product package never imports it.
+
+Wraps ``sph_oracle.c`` (plain C, FP64, OpenMP brute force) through ctypes.
+``build()`` compiles it with gcc; ``lib()`` loads it (building when missing).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "sph_oracle.c")
+SO = os.path.join(HERE, "liboracle.so")
+
+LOOPS = {"density": 0, "gradient": 1, "force": 2}
+LAYOUTS = ["AOS", "AOS_RANDOM", "SAOS_GRAD", "SAOS_FORCE", "SAOS_SHARED", "SAOS_GRAD_TYPE",
+           "SAOS_FORCE_TYPE", "SAOS_SHARED_TYPE", "SOA"]
+FIELD_IDS = {"x": 0, "v": 1, "a": 2, "mass": 3, "h": 4, "u": 5, "u_dt": 6, "rho": 7, "rho_dh": 8,
+             "wcount": 9, "div_v": 10, "rot_v": 11, "lap_u": 12, "v_sig": 13, "alpha_v": 14,
+             "alpha_d": 15, "time_bin": 16, "id": 17, "cold": 18}
+PACK_PLANES = {0: (4, 1), 1: (4, 4, 2), 2: (4, 4, 4, 4, 1)}   # floats per plane
+RESULT_PLANES = {0: 3, 1: 6, 2: 4}
+#: dense host representation of each field: (numpy dtype, components)
+FIELD_TYPES = {"x": ("<f8", 3), "v": ("<f4", 3), "a": ("<f4", 3), "mass": ("<f4", 1),
+               "h": ("<f4", 1), "u": ("<f4", 1), "u_dt": ("<f4", 1), "rho": ("<f4", 1),
+               "rho_dh": ("<f4", 1), "wcount": ("<f4", 1), "div_v": ("<f4", 1),
+               "rot_v": ("<f4", 3), "lap_u": ("<f4", 1), "v_sig": ("<f4", 1),
+               "alpha_v": ("<f4", 1), "alpha_d": ("<f4", 1), "time_bin": ("<i1", 1),
+               "id": ("<i8", 1), "cold": ("<u8", 5)}
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC",
+           "-std=c11", "-Wall", "-o", SO, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return SO
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(SO) or os.path.getmtime(SO) < os.path.getmtime(SRC):
+        build()
+    L = C.CDLL(SO)
+    d, i32, i64, vp, sz = C.c_double, C.c_int32, C.c_int64, C.c_void_p, C.c_size_t
+    for name in ("or_w", "or_dw", "or_gamma_k"):
+        getattr(L, name).restype = d
+    L.or_w.argtypes = [d]
+    L.or_dw.argtypes = [d]
+    for name in ("or_W", "or_dWdh", "or_F"):
+        getattr(L, name).restype = d
+        getattr(L, name).argtypes = [d, d]
+    L.or_density.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
+    L.or_gradient.argtypes = [i64, vp, vp, vp, vp, vp, vp, d, d, i64, vp, vp, vp, vp, vp, vp, vp]
+    L.or_force.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, d, d, i64, vp,
+                           vp, vp, vp, vp]
+    L.or_balsara.argtypes = [i64, vp, vp, vp, vp, vp, vp, d, d, vp]
+    L.or_layout_info.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(sz)]
+    L.or_field_location.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(sz),
+                                    C.POINTER(sz)]
+    L.or_store_put.argtypes = [C.c_int, i64, vp, C.c_int, vp]
+    L.or_store_get.argtypes = [C.c_int, i64, vp, C.c_int, vp]
+    L.or_pack.argtypes = [C.c_int, C.c_int, i64, vp, vp, vp, i32, i32, vp]
+    L.or_pack_cells.argtypes = [C.c_int, C.c_int, i64, vp, vp, i32, vp]
+    L.or_unpack.argtypes = [C.c_int, C.c_int, i64, vp, vp, vp, i32, i32, vp]
+    L.or_unpack_cells.argtypes = [C.c_int, C.c_int, i64, vp, vp]
+    L.or_zero_outputs.argtypes = [C.c_int, C.c_int, i64, vp]
+    L.or_range_slots.argtypes = [vp, vp, i32, i32]
+    L.or_range_slots.restype = i64
+    _lib = L
+    return L
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+# --------------------------------------------------------------------------
+# interaction loops
+# --------------------------------------------------------------------------
+GAMMA_AD = 5.0 / 3.0
+BETA_VISC = 3.0
+BALSARA_EPS = 1e-4
+
+
+def density(x, m, h, rows=None) -> Dict[str, np.ndarray]:
+    L = lib()
+    x = _c(x, np.float64); m = _c(m, np.float32); h = _c(h, np.float32)
+    n = x.shape[0]
+    rows = None if rows is None else _c(rows, np.int64)
+    nr = n if rows is None else rows.size
+    out = {k: np.zeros(nr) for k in ("rho", "rho_dh", "wcount")}
+    S = np.zeros((nr, 3)); cnt = np.zeros(nr, np.int32)
+    L.or_density(n, _p(x), _p(m), _p(h), nr, _p(rows), _p(out["rho"]), _p(out["rho_dh"]),
+                 _p(out["wcount"]), _p(S), _p(cnt))
+    out["S"] = S
+    out["count"] = cnt
+    return out
+
+
+def gradient(x, v, m, h, u, rho, rows=None, gamma=GAMMA_AD, beta=BETA_VISC) -> Dict[str, np.ndarray]:
+    L = lib()
+    x = _c(x, np.float64); v = _c(v, np.float32); m = _c(m, np.float32); h = _c(h, np.float32)
+    u = _c(u, np.float32); rho = _c(rho, np.float64)
+    n = x.shape[0]
+    rows = None if rows is None else _c(rows, np.int64)
+    nr = n if rows is None else rows.size
+    D = np.zeros(nr); R = np.zeros((nr, 3)); Lp = np.zeros(nr); V = np.zeros(nr)
+    S = np.zeros((nr, 5)); cnt = np.zeros(nr, np.int32)
+    L.or_gradient(n, _p(x), _p(v), _p(m), _p(h), _p(u), _p(rho), gamma, beta, nr, _p(rows),
+                  _p(D), _p(R), _p(Lp), _p(V), _p(S), _p(cnt))
+    return {"div_v": D, "rot_v": R, "lap_u": Lp, "v_sig": V, "S": S, "count": cnt}
+
+
+def force(x, v, m, h, u, rho, rho_dh, D, R, alpha_v, alpha_d, atilde=None, rows=None,
+          gamma=GAMMA_AD, beta=BETA_VISC, eps=BALSARA_EPS) -> Dict[str, np.ndarray]:
+    L = lib()
+    x = _c(x, np.float64); v = _c(v, np.float32); m = _c(m, np.float32); h = _c(h, np.float32)
+    u = _c(u, np.float32); rho = _c(rho, np.float64); rho_dh = _c(rho_dh, np.float64)
+    D = _c(D, np.float64); R = _c(R, np.float64)
+    alpha_v = _c(alpha_v, np.float32); alpha_d = _c(alpha_d, np.float32)
+    atilde = None if atilde is None else _c(atilde, np.float64)
+    n = x.shape[0]
+    rows = None if rows is None else _c(rows, np.int64)
+    nr = n if rows is None else rows.size
+    a = np.zeros((nr, 3)); udt = np.zeros(nr); S = np.zeros((nr, 4)); cnt = np.zeros(nr, np.int32)
+    L.or_force(n, _p(x), _p(v), _p(m), _p(h), _p(u), _p(rho), _p(rho_dh), _p(D), _p(R),
+               _p(alpha_v), _p(alpha_d), _p(atilde), gamma, beta, eps, nr, _p(rows),
+               _p(a), _p(udt), _p(S), _p(cnt))
+    return {"a": a, "u_dt": udt, "S": S, "count": cnt}
+
+
+def balsara(h, u, rho, D, R, alpha_v, gamma=GAMMA_AD, eps=BALSARA_EPS) -> np.ndarray:
+    L = lib()
+    h = _c(h, np.float32); u = _c(u, np.float32); rho = _c(rho, np.float64)
+    D = _c(D, np.float64); R = _c(R, np.float64); alpha_v = _c(alpha_v, np.float32)
+    out = np.zeros(h.size)
+    L.or_balsara(h.size, _p(h), _p(u), _p(rho), _p(D), _p(R), _p(alpha_v), gamma, eps, _p(out))
+    return out
+
+
+def full_chain(f: Dict[str, np.ndarray]) -> Dict[str, np.ndarray]:
+    """FP64 density -> gradient -> force on the logical fields of a particle set."""
+    d = density(f["x"], f["mass"], f["h"])
+    g = gradient(f["x"], f["v"], f["mass"], f["h"], f["u"], d["rho"])
+    fo = force(f["x"], f["v"], f["mass"], f["h"], f["u"], d["rho"], d["rho_dh"], g["div_v"],
+               g["rot_v"], f["alpha_v"], f["alpha_d"])
+    return {"density": d, "gradient": g, "force": fo}
+
+
+# --------------------------------------------------------------------------
+# layouts, store, pack / unpack
+# --------------------------------------------------------------------------
+def layout_info(layout: int):
+    L = lib()
+    ns = C.c_int()
+    sb = (C.c_size_t * 32)()
+    if L.or_layout_info(layout, C.byref(ns), sb):
+        raise ValueError(layout)
+    return [int(sb[i]) for i in range(ns.value)]
+
+
+def field_location(layout: int, field: int, comp: int):
+    L = lib()
+    s, o, st = C.c_int(), C.c_size_t(), C.c_size_t()
+    if L.or_field_location(layout, field, comp, C.byref(s), C.byref(o), C.byref(st)):
+        raise ValueError((layout, field, comp))
+    return s.value, o.value, st.value
+
+
+class HostStore:
+    """A particle store in host memory, laid out by the oracle's own tables."""
+
+    def __init__(self, layout: int, n: int, fill: int = 0):
+        self.layout, self.n = layout, n
+        self.sub_bytes = layout_info(layout)
+        self.subs = [np.full(n * b, fill, np.uint8) for b in self.sub_bytes]
+        self._ptrs = (C.c_void_p * 32)(*[s.ctypes.data for s in self.subs])
+
+    @property
+    def ptrs(self):
+        return self._ptrs
+
+    def put(self, name: str, arr: np.ndarray):
+        dt, nc = FIELD_TYPES[name]
+        a = np.ascontiguousarray(arr, dtype=dt)
+        assert a.size == self.n * nc
+        if lib().or_store_put(self.layout, self.n, self._ptrs, FIELD_IDS[name], a.ctypes.data):
+            raise ValueError(name)
+
+    def get(self, name: str) -> np.ndarray:
+        dt, nc = FIELD_TYPES[name]
+        a = np.zeros((self.n, nc) if nc > 1 else (self.n,), dt)
+        if lib().or_store_get(self.layout, self.n, self._ptrs, FIELD_IDS[name], a.ctypes.data):
+            raise ValueError(name)
+        return a
+
+    def put_all(self, fields: Dict[str, np.ndarray]):
+        for k, v in fields.items():
+            self.put(k, v)
+
+    def raw(self) -> bytes:
+        return b"".join(s.tobytes() for s in self.subs)
+
+
+def round_slots(nslot: int) -> int:
+    return (nslot + 63) // 64 * 64
+
+
+def range_slots(cells, tasks, t0, t1) -> int:
+    c = _c(cells, cells.dtype); t = _c(tasks, tasks.dtype)
+    return int(lib().or_range_slots(c.ctypes.data, t.ctypes.data, t0, t1))
+
+
+def pack_bytes(loop: int, nslot: int) -> int:
+    return round_slots(nslot) * 4 * sum(PACK_PLANES[loop])
+
+
+def result_bytes(loop: int, nslot: int) -> int:
+    return round_slots(nslot) * 4 * RESULT_PLANES[loop]
+
+
+def pack(store: HostStore, loop: int, cells, tasks, t0, t1) -> np.ndarray:
+    c = _c(cells, cells.dtype); t = _c(tasks, tasks.dtype)
+    ns = range_slots(c, t, t0, t1)
+    buf = np.zeros(pack_bytes(loop, ns), np.uint8)
+    if lib().or_pack(store.layout, loop, store.n, store.ptrs, c.ctypes.data, t.ctypes.data, t0, t1,
+                     buf.ctypes.data):
+        raise ValueError("pack")
+    return buf
+
+
+def pack_cells(store: HostStore, loop: int, cells) -> np.ndarray:
+    c = _c(cells, cells.dtype)
+    buf = np.zeros(pack_bytes(loop, store.n), np.uint8)
+    if lib().or_pack_cells(store.layout, loop, store.n, store.ptrs, c.ctypes.data, c.size, buf.ctypes.data):
+        raise ValueError("pack_cells")
+    return buf
+
+
+def unpack(store: HostStore, loop: int, cells, tasks, t0, t1, res: np.ndarray):
+    c = _c(cells, cells.dtype); t = _c(tasks, tasks.dtype)
+    r = np.ascontiguousarray(res)
+    if lib().or_unpack(store.layout, loop, store.n, store.ptrs, c.ctypes.data, t.ctypes.data, t0, t1,
+                       r.ctypes.data):
+        raise ValueError("unpack")
+
+
+def unpack_cells(store: HostStore, loop: int, res: np.ndarray):
+    r = np.ascontiguousarray(res)
+    if lib().or_unpack_cells(store.layout, loop, store.n, store.ptrs, r.ctypes.data):
+        raise ValueError("unpack_cells")
+
+
+def zero_outputs(store: HostStore, loop: int):
+    if lib().or_zero_outputs(store.layout, loop, store.n, store.ptrs):
+        raise ValueError("zero")
