@@ -1,0 +1,296 @@
+/*
+ * sph.h -- C-ABI of libsph, the MI355X (gfx950) pack / interact / unpack path
+ * for smoothed particle hydrodynamics.
+ *
+ * The paper this follows ("Memory Layouts for GPU-Data Transfer Buffering in
+ * SPH") offloads SPH interaction loops in bundles of cell tasks: each task's
+ * particle attributes are *packed* into a compact buffer, the interactions are
+ * computed on the GPU (the *launch*), and the results are *unpacked* with
+ * reductions back into the particles (Sec. 2.3).  Three loops run per step --
+ * density, gradient and force -- each reading and writing its own attribute
+ * set (Sec. 2.1, Table 1).  The particle store may be laid out as AoS, a
+ * randomly ordered AoS, split AoS grouped by access pattern (pack-gradient,
+ * pack-force, pack-shared), the same split again by data type, or SoA
+ * (Sec. 3.1), hidden behind getters and setters (Sec. 3.2, Algorithm 1).
+ *
+ * Conventions shared by every call
+ *  - Every call returns sph_status; nothing throws across the ABI.  On an
+ *    error nothing has been enqueued and no memory has been written.
+ *  - Device pointers are HIP device (or host-mapped) addresses owned by the
+ *    caller; the library never frees caller memory.  Store substruct arrays
+ *    and buffers must be 256-byte aligned.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    asynchronously on it; faults inside kernels surface at the caller's next
+ *    synchronisation.  HIP errors map to SPH_E_HIP, detail in sph_last_error().
+ *  - Plans are library-owned and immutable after creation; one plan may be used
+ *    from several threads and streams at once.  No call keeps global mutable
+ *    state besides the thread-local error text.
+ *  - Floating point: pack and unpack are bit-exact data movement (one FP64
+ *    subtraction rounded once to FP32 for positions; FP32 additions in a fixed
+ *    order for reductions).  Interaction sums are FP32.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sph_status {
+    SPH_OK = 0,
+    SPH_E_ARG = -1,         /* null / misaligned pointer, bad enum, bad range        */
+    SPH_E_LAYOUT = -2,      /* store does not match the layout's substruct count     */
+    SPH_E_CAPACITY = -3,    /* a caller buffer is smaller than the call needs        */
+    SPH_E_PLAN = -4,        /* cells / tasks inconsistent (index out of range, ...)  */
+    SPH_E_HIP = -5,         /* a HIP runtime call failed                             */
+    SPH_E_UNSUPPORTED = -6  /* valid request the plan cannot serve                   */
+} sph_status;
+
+/* Particle layouts (Sec. 3.1).  The substructs of each, member order and byte
+ * offsets are fixed by the library and reported by sph_layout_info() and
+ * sph_field_location(); see those calls for the exact tables. */
+typedef enum sph_layout {
+    SPH_AOS = 0,              /* one 160-byte record, members in usage order      */
+    SPH_AOS_RANDOM = 1,       /* the same members in a fixed shuffled order        */
+    SPH_SAOS_GRAD = 2,        /* gradient-pack set in one substruct                */
+    SPH_SAOS_FORCE = 3,       /* force-pack set in one substruct                   */
+    SPH_SAOS_SHARED = 4,      /* {x, m, h} shared by all loops in its own substruct */
+    SPH_SAOS_GRAD_TYPE = 5,   /* SAOS_GRAD split again by data type                */
+    SPH_SAOS_FORCE_TYPE = 6,  /* SAOS_FORCE split again by data type               */
+    SPH_SAOS_SHARED_TYPE = 7, /* SAOS_SHARED split again by data type              */
+    SPH_SOA = 8,              /* one array per scalar component                    */
+    SPH_NLAYOUTS = 9
+} sph_layout;
+
+typedef enum sph_loop { SPH_DENSITY = 0, SPH_GRADIENT = 1, SPH_FORCE = 2 } sph_loop;
+
+/* Logical particle fields (Table 1 plus the outputs the loops produce).
+ * Component type: X float64[3]; V, A, ROT float32[3]; TIME_BIN int8;
+ * ID int64; COLD 40 opaque bytes (5 x uint64) no loop touches; the rest float32. */
+typedef enum sph_field {
+    SPH_F_X = 0, SPH_F_V, SPH_F_A, SPH_F_MASS, SPH_F_H, SPH_F_U, SPH_F_U_DT, SPH_F_RHO,
+    SPH_F_RHO_DH, SPH_F_WCOUNT, SPH_F_DIV, SPH_F_ROT, SPH_F_LAP, SPH_F_VSIG, SPH_F_ALPHA_V,
+    SPH_F_ALPHA_D, SPH_F_TIME_BIN, SPH_F_ID, SPH_F_COLD, SPH_NFIELDS
+} sph_field;
+
+#define SPH_MAX_SUB 32
+
+/* A particle store: `nsub` caller-owned substruct arrays, each holding n
+ * records of sph_layout_info()'s sub_bytes[s] bytes.  256-byte aligned. */
+typedef struct sph_store {
+    int32_t layout;
+    int32_t nsub;
+    int64_t n;
+    void *sub[SPH_MAX_SUB];
+} sph_store;
+
+/* A cell (octree leaf or grid cell, Sec. 2.2): particles [first, first+count)
+ * of the store, all inside the cube [loc, loc + width). 48 bytes. */
+typedef struct sph_cell {
+    double loc[3];
+    double width;
+    int64_t first;
+    int32_t count;
+    int32_t pad;
+} sph_cell;
+
+/* A task (Sec. 2.2): a self task (ci == cj, shift = 0) or a pair task whose
+ * cj particles are used at x + shift (the periodic image next to ci). 40 bytes. */
+typedef struct sph_task {
+    int32_t ci, cj;
+    int32_t pad[2];
+    double shift[3];
+} sph_task;
+
+/* Physics constants (defaults 5/3, 3, 1e-4). */
+typedef struct sph_params {
+    float gamma_ad;
+    float beta_visc;
+    float balsara_eps;
+    float pad;
+} sph_params;
+
+/* Launch parameters of the batched form (sph_tuning_default fills them). */
+typedef struct sph_tuning {
+    int32_t blocks_per_cu;   /* persistent grid = blocks_per_cu x CU count (1..64)  */
+    int32_t window[3];       /* candidate window per wave for density, gradient and
+                                force: 64, 128, 256 or 512 candidates              */
+    int32_t pack_waves;      /* waves per block in pack / unpack kernels (1..8)     */
+    int32_t queue;           /* 1 = device work queue, 0 = static stride            */
+    int32_t reserved[2];
+} sph_tuning;
+
+typedef struct sph_plan sph_plan; /* library-owned, opaque */
+
+/* Plan statistics. */
+typedef struct sph_plan_info {
+    int64_t n;            /* particles                                         */
+    int32_t ncell, ntask;
+    int64_t nslot;        /* slots over all tasks (a particle per task side)    */
+    int64_t nchunk;       /* 64-slot chunks over all tasks                      */
+    int32_t ntile;        /* 64-particle tiles over all cells                   */
+    int32_t max_cell;     /* largest cell                                        */
+    int32_t max_nbr;      /* most neighbour cells of one cell (incl. itself)     */
+    int32_t batched_ok;   /* cells tile the store in order (batched form usable) */
+} sph_plan_info;
+
+/* ---------------------------------------------------------------------- */
+/* Error text and layout queries (host only, no GPU needed).               */
+/* ---------------------------------------------------------------------- */
+const char *sph_status_str(sph_status s);
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *sph_last_error(void);
+
+/* Substruct count and record bytes of a layout (Sec. 3.1).  sub_bytes must
+ * hold SPH_MAX_SUB entries.  Members sit at natural alignment in the listed
+ * order, each record padded to 8 bytes (SoA: one array per scalar component,
+ * element size = component size). */
+sph_status sph_layout_info(sph_layout layout, int32_t *nsub, size_t *sub_bytes);
+
+/* Where component `comp` of `field` lives: substruct index, byte offset in the
+ * record and record stride (the getter/setter mapping of Algorithm 1). */
+sph_status sph_field_location(sph_layout layout, sph_field field, int32_t comp, int32_t *sub,
+                              size_t *offset, size_t *stride);
+
+/* Components and bytes per component of a field. */
+sph_status sph_field_info(sph_field field, int32_t *ncomp, int32_t *comp_bytes);
+
+/* Packed record of a loop (Table 1): planes of float32, plane k holding
+ * plane_floats[k] floats per slot.  A buffer for P slots stores plane k at
+ * byte offset P * 4 * (sum of plane_floats before k), slot s of plane k at
+ * s * 4 * plane_floats[k] inside it:
+ *   density : [dx dy dz h] [m]
+ *   gradient: [dx dy dz h] [vx vy vz m] [u rho]
+ *   force   : [dx dy dz h] [vx vy vz m] [u rho rho_dh D] [R0 R1 R2 alpha_v] [alpha_d]
+ * (dx,dy,dz) = float32(x - o) computed in float64 and rounded once to nearest,
+ * o = loc(ci) for ci's particles and loc(ci) - shift for cj's (the periodic
+ * pre-processing of Sec. 2.3).  Results are float planes per slot:
+ *   density [rho rho_dh wcount]; gradient [D R0 R1 R2 L V]; force [a0 a1 a2 u_dt]. */
+sph_status sph_pack_layout(sph_loop loop, int32_t *nplane, int32_t *plane_floats, int32_t *result_planes);
+
+/* ---------------------------------------------------------------------- */
+/* Store access: the getter / setter analogue (Sec. 3.2, Algorithm 1).      */
+/* ---------------------------------------------------------------------- */
+/* Copy a dense device array src[n][ncomp] of the field's type into the store. */
+sph_status sph_store_put(const sph_store *store, sph_field field, const void *src, void *stream);
+/* Copy a field out of the store into a dense device array dst[n][ncomp]. */
+sph_status sph_store_get(const sph_store *store, sph_field field, void *dst, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Plan: cells and tasks of one step (Sec. 2.2).                            */
+/* ---------------------------------------------------------------------- */
+/* Validate host arrays cells[ncell], tasks[ntask] over n particles and upload
+ * them with derived tables to the current device.  Every task's cells must be
+ * in range, self tasks must carry a zero shift, cells must lie inside [0, n).
+ * Errors: SPH_E_ARG (null / negative sizes), SPH_E_PLAN, SPH_E_HIP. */
+sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task *tasks,
+                           int32_t ntask, int64_t n, sph_plan **out);
+void sph_plan_destroy(sph_plan *plan);
+sph_status sph_plan_get_info(const sph_plan *plan, sph_plan_info *info);
+/* Slots of tasks [t0, t1) and the bytes a pack / result buffer for that range
+ * needs (planes hold P = nslot rounded up to 64 slots; the pack buffer also
+ * carries 32 bytes of tile bounds per 64-slot chunk after the planes). */
+sph_status sph_plan_buffer_bytes(const sph_plan *plan, sph_loop loop, int32_t t0, int32_t t1,
+                                 int64_t *nslot, size_t *pack_bytes, size_t *result_bytes);
+
+/* ---------------------------------------------------------------------- */
+/* Per-task / bundled path: any task range [t0, t1) is one bundle.          */
+/* ---------------------------------------------------------------------- */
+/* Set the loop's outputs in the store to +0.0f (before the first unpack). */
+sph_status sph_zero_outputs(const sph_plan *plan, sph_loop loop, const sph_store *store, void *stream);
+
+/* Pack the slots of tasks [t0, t1) in task order -- ci's particles, then cj's,
+ * each in store order -- into pack_buf (pack_bytes from sph_plan_buffer_bytes). */
+sph_status sph_pack(const sph_plan *plan, sph_loop loop, const sph_store *store, int32_t t0,
+                    int32_t t1, void *pack_buf, size_t pack_bytes, void *stream);
+
+/* Interaction loops over a packed range (Sec. 2.1).  For every slot i of a
+ * task, sum over the slots j of the other cell of the task (the same cell for
+ * a self task) and write the slot's partial results to res_buf:
+ *   density : j with r < H_i, i itself included
+ *   gradient: j != i with r < H_i
+ *   force   : j != i with r < max(H_i, H_j)
+ * H = sqrt(10/3) h.  counts (optional, int32 per slot) receives the number of
+ * interacting j.  pack_bytes / res_bytes are the caller's buffer sizes. */
+sph_status sph_density(const sph_plan *plan, const void *pack_buf, size_t pack_bytes, int32_t t0,
+                       int32_t t1, const sph_params *params, void *res_buf, size_t res_bytes,
+                       int32_t *counts, void *stream);
+sph_status sph_gradient(const sph_plan *plan, const void *pack_buf, size_t pack_bytes, int32_t t0,
+                        int32_t t1, const sph_params *params, void *res_buf, size_t res_bytes,
+                        int32_t *counts, void *stream);
+sph_status sph_force(const sph_plan *plan, const void *pack_buf, size_t pack_bytes, int32_t t0,
+                     int32_t t1, const sph_params *params, void *res_buf, size_t res_bytes,
+                     int32_t *counts, void *stream);
+
+/* Reduce the partial results of tasks [t0, t1) into the store in ascending
+ * task order (ci's slots, then cj's): FP32 additions, and the larger value for
+ * the signal velocity V (Sec. 2.3, unpacking with reductions). */
+sph_status sph_unpack(const sph_plan *plan, sph_loop loop, const void *res_buf, size_t res_bytes,
+                      int32_t t0, int32_t t1, const sph_store *store, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Batched form: all tasks of a step per launch (the paper's bundling of    */
+/* ready tasks, Sec. 2.3, taken to one bundle per step).  Each cell is      */
+/* packed once (slot = particle index, origin = the cell's own loc), every  */
+/* particle gathers over all its neighbour cells in one work item pulled    */
+/* from a device queue, and unpack writes each result once.  Requires cells */
+/* that tile the store in order (sph_plan_info.batched_ok).                 */
+/* ---------------------------------------------------------------------- */
+void sph_tuning_default(sph_tuning *t);
+/* Workspace for sph_step_batched / sph_graph_capture. */
+sph_status sph_batched_ws_bytes(const sph_plan *plan, size_t *bytes);
+/* Individual stages (buffers as for the per-task path with P = n rounded up). */
+sph_status sph_pack_cells(const sph_plan *plan, sph_loop loop, const sph_store *store, void *pack_buf,
+                          size_t pack_bytes, const sph_tuning *tuning, void *stream);
+/* ws: at least 256 bytes of device memory for the queue counter. */
+sph_status sph_interact_cells(const sph_plan *plan, sph_loop loop, const void *pack_buf,
+                              size_t pack_bytes, const sph_params *params, const sph_tuning *tuning,
+                              void *res_buf, size_t res_bytes, int32_t *counts, void *ws,
+                              void *stream);
+/* out = +0.0f + result (V: the larger of +0.0f and the result). */
+sph_status sph_unpack_cells(const sph_plan *plan, sph_loop loop, const void *res_buf, size_t res_bytes,
+                            const sph_store *store, const sph_tuning *tuning, void *stream);
+/* density -> gradient -> force, each pack -> interact -> unpack. */
+sph_status sph_step_batched(const sph_plan *plan, const sph_store *store, const sph_params *params,
+                            const sph_tuning *tuning, void *ws, size_t ws_bytes, void *stream);
+/* Capture sph_step_batched into an executable HIP graph (*graph_exec). */
+sph_status sph_graph_capture(const sph_plan *plan, const sph_store *store, const sph_params *params,
+                             const sph_tuning *tuning, void *ws, size_t ws_bytes, void **graph_exec);
+sph_status sph_graph_launch(void *graph_exec, void *stream);
+void sph_graph_destroy(void *graph_exec);
+
+/* ---------------------------------------------------------------------- */
+/* Adjoint of L = sum_i |a_i|^2 through density and force (hand-written).   */
+/* The artificial-viscosity switch alpha~ = alpha_v B and alpha_d are held  */
+/* fixed; h and u are constants.  Density is recomputed in backward.        */
+/* Inputs are per-particle device arrays in store order:                    */
+/*   x float64[n][3], v float32[n][3], m, h, u, atilde, alpha_d float32[n].  */
+/* ---------------------------------------------------------------------- */
+/* Forward: rho, rho_dh (float32[n]) and a (float32[n][3]), u_dt (float32[n]). */
+sph_status sph_adjoint_forward(const sph_plan *plan, const double *x, const float *v, const float *m,
+                               const float *h, const float *u, const float *atilde,
+                               const float *alpha_d, const sph_params *params, float *rho,
+                               float *rho_dh, float *a, float *u_dt, void *ws, size_t ws_bytes,
+                               void *stream);
+/* Backward of force: given a_bar = dL/da (float32[n][3]), writes dL/dx,
+ * dL/dv, dL/dm contributions (float32, overwritten) and rho_bar, rhodh_bar. */
+sph_status sph_force_adjoint(const sph_plan *plan, const double *x, const float *v, const float *m,
+                             const float *h, const float *u, const float *atilde,
+                             const float *alpha_d, const float *rho, const float *rho_dh,
+                             const sph_params *params, const float *a_bar, float *x_bar, float *v_bar,
+                             float *m_bar, float *rho_bar, float *rhodh_bar, void *ws,
+                             size_t ws_bytes, void *stream);
+/* Backward of density: accumulates (+=) dL/dx and dL/dm from rho_bar, rhodh_bar. */
+sph_status sph_density_adjoint(const sph_plan *plan, const double *x, const float *m, const float *h,
+                               const float *rho_bar, const float *rhodh_bar, float *x_bar,
+                               float *m_bar, void *ws, size_t ws_bytes, void *stream);
+/* Workspace of the three adjoint calls. */
+sph_status sph_adjoint_ws_bytes(const sph_plan *plan, size_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPH_H */

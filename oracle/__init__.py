@@ -57,7 +57,7 @@ def lib():
         getattr(L, name).restype = d
     L.or_w.argtypes = [d]
     L.or_dw.argtypes = [d]
-    for name in ("or_W", "or_dWdh", "or_F"):
+    for name in ("or_W", "or_dWdh", "or_F", "or_dWdr", "or_d2Wdhdr", "or_dFdr"):
         getattr(L, name).restype = d
         getattr(L, name).argtypes = [d, d]
     L.or_density.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]

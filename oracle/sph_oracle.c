@@ -75,6 +75,34 @@ double or_F(double r, double h)
     return 8.0 / OR_PI / (H * H * H * H * H) * wq;
 }
 
+/* Derivatives used only by the error scale (first-order condition bound). */
+double or_dWdr(double r, double h) /* dW/dr = (8/pi) H^-4 w'(q) */
+{
+    double H = OR_GAMMA_K * h;
+    return 8.0 / OR_PI / (H * H * H * H) * or_dw(r / H);
+}
+
+static double or_d2w(double q)
+{
+    if (q < 0.5) return -12.0 + 36.0 * q;
+    if (q < 1.0) return 12.0 * (1.0 - q);
+    return 0.0;
+}
+
+double or_d2Wdhdr(double r, double h) /* d/dr of dW/dh = -gamma_k (8/pi) H^-5 (4 w' + q w'') */
+{
+    double H = OR_GAMMA_K * h, q = r / H;
+    return -OR_GAMMA_K * 8.0 / OR_PI / (H * H * H * H * H) * (4.0 * or_dw(q) + q * or_d2w(q));
+}
+
+double or_dFdr(double r, double h) /* dF/dr with F = (8/pi) H^-5 w'(q)/q */
+{
+    double H = OR_GAMMA_K * h, q = r / H;
+    if (q >= 1.0) return 0.0;
+    double fp = (q < 0.5) ? 18.0 : 6.0 * (1.0 - q) * (1.0 + q) / (q * q);
+    return 8.0 / OR_PI / (H * H * H * H * H * H) * fp;
+}
+
 /* minimum-image separation in the periodic unit box; x in [0,1) */
 static inline double mi(double d)
 {
@@ -87,7 +115,9 @@ static inline double mi(double d)
 /* Density loop: over all j including i with r < H_i                         */
 /*   rho_i = sum m_j W(r, h_i);  rho_dh_i = sum m_j dW/dh(r, h_i);            */
 /*   wcount_i = sum W(r, h_i).                                               */
-/* S holds, per output, the sum of |term| (for the scaled error measure).    */
+/* S holds, per output, the error scale of the sum: for every term, the sum  */
+/* of |elementary products| plus |r| times a bound on |d term / d r_ij|       */
+/* (the first-order condition of the sum under rounding of its inputs).      */
 /* ------------------------------------------------------------------------ */
 void or_density(int64_t n, const double *x, const float *m, const float *h,
                 int64_t nrow, const int64_t *rows,
@@ -98,7 +128,7 @@ void or_density(int64_t n, const double *x, const float *m, const float *h,
     for (int64_t k = 0; k < nr; k++) {
         int64_t i = rows ? rows[k] : k;
         double H = OR_GAMMA_K * (double)h[i];
-        double sr = 0, sd = 0, sw = 0, ad = 0;
+        double sr = 0, sd = 0, sw = 0, s0 = 0, s1 = 0, s2 = 0;
         int32_t c = 0;
         for (int64_t j = 0; j < n; j++) {
             double dx = mi(x[3 * i] - x[3 * j]);
@@ -108,14 +138,18 @@ void or_density(int64_t n, const double *x, const float *m, const float *h,
             if (!(r < H)) continue;
             double W = or_W(r, h[i]);
             double Wh = or_dWdh(r, h[i]);
-            sr += (double)m[j] * W;
-            sd += (double)m[j] * Wh;
-            ad += fabs((double)m[j] * Wh);
+            double mj = m[j];
+            sr += mj * W;
+            sd += mj * Wh;
             sw += W;
+            double Wr = fabs(or_dWdr(r, h[i])) * r;
+            s0 += mj * W + mj * Wr;
+            s1 += fabs(mj * Wh) + mj * fabs(or_d2Wdhdr(r, h[i])) * r;
+            s2 += W + Wr;
             c++;
         }
         rho[k] = sr; rho_dh[k] = sd; wcount[k] = sw;
-        if (S) { S[3 * k] = sr; S[3 * k + 1] = ad; S[3 * k + 2] = sw; }
+        if (S) { S[3 * k] = s0; S[3 * k + 1] = s1; S[3 * k + 2] = s2; }
         if (cnt) cnt[k] = c;
     }
 }
@@ -163,7 +197,15 @@ void or_gradient(int64_t n, const double *x, const float *v, const float *m, con
             double t2 = mj * (vx * gy - vy * gx);
             double tl = 2.0 * (mj / rhoj[j]) * ((double)u[i] - (double)u[j]) * F;
             d += td; r0 += t0; r1 += t1; r2 += t2; l += tl;
-            ad += fabs(td); ar0 += fabs(t0); ar1 += fabs(t1); ar2 += fabs(t2); al += fabs(tl);
+            /* error scale: componentwise products + r |d/dr_ij| bound */
+            double aF = fabs(F), aFp = fabs(or_dFdr(r, h[i])) * r;
+            double vn = sqrt(vx * vx + vy * vy + vz * vz);
+            double vrr = fabs(vx * rx + vy * ry + vz * rz);
+            ad += mj * aF * (fabs(vx * rx) + fabs(vy * ry) + fabs(vz * rz)) + mj * (aFp * vrr + aF * r * vn);
+            ar0 += mj * aF * (fabs(vy * rz) + fabs(vz * ry)) + mj * (aFp * fabs(vy * rz - vz * ry) + aF * r * vn);
+            ar1 += mj * aF * (fabs(vz * rx) + fabs(vx * rz)) + mj * (aFp * fabs(vz * rx - vx * rz) + aF * r * vn);
+            ar2 += mj * aF * (fabs(vx * ry) + fabs(vy * rx)) + mj * (aFp * fabs(vx * ry - vy * rx) + aF * r * vn);
+            al += fabs(tl) + 2.0 * (mj / rhoj[j]) * fabs((double)u[i] - (double)u[j]) * aFp;
             double vr = (r > 0) ? (vx * rx + vy * ry + vz * rz) / r : 0.0;
             double mu = vr < 0 ? vr : 0.0;
             double sig = ci + sound_speed(gam, u[j]) - beta * mu;
@@ -281,15 +323,28 @@ void or_force(int64_t n, const double *x, const float *v, const float *m, const 
             double p0y = -mj * pi.A * Giy, p1y = -mj * pj.A * Gjy, p2y = -mj * Pi * Gby;
             double p0z = -mj * pi.A * Giz, p1z = -mj * pj.A * Gjz, p2z = -mj * Pi * Gbz;
             a0 += p0x + p1x + p2x; a1 += p0y + p1y + p2y; a2 += p0z + p1z + p2z;
-            s0 += fabs(p0x) + fabs(p1x) + fabs(p2x);
-            s1 += fabs(p0y) + fabs(p1y) + fabs(p2y);
-            s2 += fabs(p0z) + fabs(p1z) + fabs(p2z);
             double e0 = mj * pi.A * (vx * Gix + vy * Giy + vz * Giz);
             double e1 = mj * 0.5 * Pi * (vx * Gbx + vy * Gby + vz * Gbz);
             double e2 = mj * 0.5 * (pi.ad + pj.ad) * fabs(vr) * (pi.u - pj.u) *
                         (ex * Gbx + ey * Gby + ez * Gbz) / rhobar;
             du += e0 + e1 + e2;
-            sd += fabs(e0) + fabs(e1) + fabs(e2);
+            /* error scale: |elementary products| + r |d/dr_ij| bounds */
+            double Fip = (r < pi.H) ? fabs(or_dFdr(r, h[i])) : 0.0;
+            double Fjp = (r < pj.H) ? fabs(or_dFdr(r, h[j])) : 0.0;
+            double X = fabs(pi.A * Fi) + fabs(pj.A * Fj) + fabs(Pi * Fbar);
+            double Xp = fabs(pi.A) * Fip + fabs(pj.A) * Fjp + fabs(Pi) * 0.5 * (Fip + Fjp);
+            double vn = sqrt(vx * vx + vy * vy + vz * vz);
+            double dPi = 0.5 * aij * (pi.c + pj.c + 2.0 * beta * fabs(mu)) / rhobar; /* |dPi/dmu| */
+            double rs = Xp * r + fabs(Fbar) * dPi * vn;                            /* r |grad s| */
+            s0 += mj * (X * fabs(rx) + rs * fabs(rx) + X * r);
+            s1 += mj * (X * fabs(ry) + rs * fabs(ry) + X * r);
+            s2 += mj * (X * fabs(rz) + rs * fabs(rz) + X * r);
+            double cvr = fabs(vx * rx) + fabs(vy * ry) + fabs(vz * rz), dvr = fabs(vx * rx + vy * ry + vz * rz);
+            double Fbp = 0.5 * (Fip + Fjp), adb = 0.5 * (pi.ad + pj.ad), du_ = fabs(pi.u - pj.u);
+            sd += mj * fabs(pi.A * Fi) * cvr + mj * fabs(pi.A) * (Fip * r * dvr + fabs(Fi) * r * vn);
+            sd += 0.5 * mj * (fabs(Pi * Fbar) * cvr + fabs(Pi) * (Fbp * r * dvr + fabs(Fbar) * r * vn) +
+                              fabs(Fbar) * dvr * dPi * vn);
+            sd += mj * adb * du_ / rhobar * (fabs(Fbar) * cvr + Fbp * r * dvr + fabs(Fbar) * r * vn);
             c++;
         }
         acc[3 * k] = a0; acc[3 * k + 1] = a1; acc[3 * k + 2] = a2; udt[k] = du;

@@ -1,0 +1,753 @@
+// libsph C-ABI: validation, plan construction, layout queries, store access,
+// and the per-task / batched entry points (the kernels live in sph_pack.hip
+// and sph_interact.hip).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "sph_internal.hpp"
+
+namespace sph {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+sph_status fail(sph_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+sph_status hip_fail(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return SPH_E_HIP;
+}
+
+static bool aligned256(const void *p) { return ((uintptr_t)p & 255u) == 0; }
+
+sph_status check_loop(int loop)
+{
+    if (loop < 0 || loop > 2) return fail(SPH_E_ARG, "loop must be SPH_DENSITY, SPH_GRADIENT or SPH_FORCE");
+    return SPH_OK;
+}
+
+sph_status check_store(const sph_store *s)
+{
+    if (!s) return fail(SPH_E_ARG, "store is null");
+    if (s->layout < 0 || s->layout >= kNLayouts) return fail(SPH_E_LAYOUT, "unknown layout");
+    if (s->nsub != kLayouts[s->layout].nsub)
+        return fail(SPH_E_LAYOUT, "store nsub " + std::to_string(s->nsub) + " != layout's " +
+                                      std::to_string(kLayouts[s->layout].nsub));
+    if (s->n < 0) return fail(SPH_E_ARG, "negative particle count");
+    if (s->n > 0)
+        for (int i = 0; i < s->nsub; ++i) {
+            if (!s->sub[i]) return fail(SPH_E_ARG, "store substruct " + std::to_string(i) + " is null");
+            if (!aligned256(s->sub[i]))
+                return fail(SPH_E_ARG, "store substruct " + std::to_string(i) + " is not 256-byte aligned");
+        }
+    return SPH_OK;
+}
+
+sph_status check_range(const sph_plan *p, int32_t t0, int32_t t1)
+{
+    if (t0 < 0 || t1 < t0 || t1 > p->ntask)
+        return fail(SPH_E_ARG, "task range [" + std::to_string(t0) + ", " + std::to_string(t1) +
+                                   ") outside [0, " + std::to_string(p->ntask) + ")");
+    return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// generic field copy / zero (runtime descriptors; not on the hot path)
+// ---------------------------------------------------------------------------
+struct CompDesc {
+    char *base;
+    int64_t stride;
+};
+struct FieldDesc {
+    CompDesc c[6];
+    int ncomp;
+    int csize;
+};
+
+static FieldDesc field_desc(const sph_store *s, int f)
+{
+    const LayoutDesc &d = kLayouts[s->layout];
+    FieldDesc fd{};
+    fd.ncomp = kNComp[f];
+    fd.csize = kCompBytes[f];
+    for (int c = 0; c < kNComp[f]; ++c) {
+        const int sb = d.sub[f][c];
+        fd.c[c].base = (char *)s->sub[sb] + d.off[f][c];
+        fd.c[c].stride = d.sub_bytes[sb];
+    }
+    return fd;
+}
+
+__global__ void k_field_copy(FieldDesc d, int64_t n, const char *src, char *dst, int to_store)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * d.ncomp) return;
+    const int64_t p = i / d.ncomp;
+    const int c = (int)(i - p * d.ncomp);
+    char *sp = d.c[c].base + p * d.c[c].stride;
+    const size_t b = (size_t)d.csize;
+    if (to_store) {
+        const char *q = src + i * b;
+        if (b == 8) *(uint64_t *)sp = *(const uint64_t *)q;
+        else if (b == 4) *(uint32_t *)sp = *(const uint32_t *)q;
+        else *sp = *q;
+    } else {
+        char *q = dst + i * b;
+        if (b == 8) *(uint64_t *)q = *(const uint64_t *)sp;
+        else if (b == 4) *(uint32_t *)q = *(const uint32_t *)sp;
+        else *q = *sp;
+    }
+}
+
+__global__ void k_zero_fields(FieldDesc d, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * d.ncomp) return;
+    const int64_t p = i / d.ncomp;
+    const int c = (int)(i - p * d.ncomp);
+    *(float *)(d.c[c].base + p * d.c[c].stride) = 0.0f;
+}
+
+// outputs of each loop (Table 1's u- columns plus the gradient loop's products)
+static const int kOutField[3][6] = {{FRHO, FRHODH, FWCOUNT}, {FDIV, FROT, FROT, FROT, FLAP, FVSIG},
+                                    {FA, FA, FA, FUDT}};
+static const int kOutComp[3][6] = {{0, 0, 0}, {0, 0, 1, 2, 0, 0}, {0, 1, 2, 0}};
+
+sph_status launch_zero(const sph_plan *p, int loop, const sph_store *s, hipStream_t st)
+{
+    (void)p;
+    FieldDesc fd{};
+    const LayoutDesc &d = kLayouts[s->layout];
+    fd.ncomp = kResPlanes[loop];
+    fd.csize = 4;
+    for (int k = 0; k < fd.ncomp; ++k) {
+        const int f = kOutField[loop][k], c = kOutComp[loop][k];
+        const int sb = d.sub[f][c];
+        fd.c[k].base = (char *)s->sub[sb] + d.off[f][c];
+        fd.c[k].stride = d.sub_bytes[sb];
+    }
+    const int64_t tot = s->n * fd.ncomp;
+    if (tot == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_zero_fields, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, fd, s->n);
+    SPH_CHECK_LAUNCH("zero_outputs launch");
+    return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-particle slot lists for multi-task unpack (host build, once per plan)
+// ---------------------------------------------------------------------------
+sph_status ensure_csr(sph_plan *p)
+{
+    std::lock_guard<std::mutex> g(p->csr_mu);
+    if (p->csr_built) return SPH_OK;
+    std::vector<int64_t> cnt(p->n + 1, 0);
+    for (int32_t t = 0; t < p->ntask; ++t) {
+        const sph_task &tk = p->tasks[t];
+        const sph_cell &a = p->cells[tk.ci];
+        for (int32_t k = 0; k < a.count; ++k) cnt[a.first + k + 1]++;
+        if (tk.ci != tk.cj) {
+            const sph_cell &b = p->cells[tk.cj];
+            for (int32_t k = 0; k < b.count; ++k) cnt[b.first + k + 1]++;
+        }
+    }
+    for (int64_t i = 0; i < p->n; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int64_t> lst(p->nslot), pos(cnt.begin(), cnt.end() - 1);
+    int64_t slot = 0;
+    for (int32_t t = 0; t < p->ntask; ++t) {
+        const sph_task &tk = p->tasks[t];
+        const sph_cell &a = p->cells[tk.ci];
+        for (int32_t k = 0; k < a.count; ++k) lst[pos[a.first + k]++] = slot++;
+        if (tk.ci != tk.cj) {
+            const sph_cell &b = p->cells[tk.cj];
+            for (int32_t k = 0; k < b.count; ++k) lst[pos[b.first + k]++] = slot++;
+        }
+    }
+    SPH_HIP(hipSetDevice(p->device));
+    SPH_HIP(hipMalloc(&p->d_csr_off, sizeof(int64_t) * (p->n + 1)));
+    SPH_HIP(hipMalloc(&p->d_csr, sizeof(int64_t) * std::max<int64_t>(1, p->nslot)));
+    SPH_HIP(hipMemcpy(p->d_csr_off, cnt.data(), sizeof(int64_t) * (p->n + 1), hipMemcpyHostToDevice));
+    if (p->nslot)
+        SPH_HIP(hipMemcpy(p->d_csr, lst.data(), sizeof(int64_t) * p->nslot, hipMemcpyHostToDevice));
+    p->csr_built = true;
+    return SPH_OK;
+}
+
+template <class T>
+static sph_status upload(T **dst, const std::vector<T> &v)
+{
+    const size_t b = sizeof(T) * std::max<size_t>(1, v.size());
+    SPH_HIP(hipMalloc((void **)dst, b));
+    if (!v.empty()) SPH_HIP(hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return SPH_OK;
+}
+
+}  // namespace sph
+
+using namespace sph;
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+const char *sph_status_str(sph_status s)
+{
+    switch (s) {
+    case SPH_OK: return "ok";
+    case SPH_E_ARG: return "invalid argument";
+    case SPH_E_LAYOUT: return "layout mismatch";
+    case SPH_E_CAPACITY: return "buffer too small";
+    case SPH_E_PLAN: return "inconsistent plan";
+    case SPH_E_HIP: return "HIP runtime error";
+    case SPH_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *sph_last_error(void) { return g_err.c_str(); }
+
+sph_status sph_layout_info(sph_layout layout, int32_t *nsub, size_t *sub_bytes)
+{
+    if ((int)layout < 0 || (int)layout >= kNLayouts) return fail(SPH_E_LAYOUT, "unknown layout");
+    if (!nsub || !sub_bytes) return fail(SPH_E_ARG, "null output");
+    const LayoutDesc &d = kLayouts[layout];
+    *nsub = d.nsub;
+    for (int i = 0; i < kMaxSub; ++i) sub_bytes[i] = i < d.nsub ? (size_t)d.sub_bytes[i] : 0;
+    return SPH_OK;
+}
+
+sph_status sph_field_location(sph_layout layout, sph_field field, int32_t comp, int32_t *sub,
+                              size_t *offset, size_t *stride)
+{
+    if ((int)layout < 0 || (int)layout >= kNLayouts) return fail(SPH_E_LAYOUT, "unknown layout");
+    if ((int)field < 0 || (int)field >= NFIELD) return fail(SPH_E_ARG, "unknown field");
+    if (comp < 0 || comp >= kNComp[field]) return fail(SPH_E_ARG, "component out of range");
+    if (!sub || !offset || !stride) return fail(SPH_E_ARG, "null output");
+    const LayoutDesc &d = kLayouts[layout];
+    *sub = d.sub[field][comp];
+    *offset = (size_t)d.off[field][comp];
+    *stride = (size_t)d.sub_bytes[*sub];
+    return SPH_OK;
+}
+
+sph_status sph_field_info(sph_field field, int32_t *ncomp, int32_t *comp_bytes)
+{
+    if ((int)field < 0 || (int)field >= NFIELD) return fail(SPH_E_ARG, "unknown field");
+    if (!ncomp || !comp_bytes) return fail(SPH_E_ARG, "null output");
+    *ncomp = kNComp[field];
+    *comp_bytes = kCompBytes[field];
+    return SPH_OK;
+}
+
+sph_status sph_pack_layout(sph_loop loop, int32_t *nplane, int32_t *plane_floats, int32_t *result_planes)
+{
+    sph_status s = check_loop(loop);
+    if (s) return s;
+    if (!nplane || !plane_floats || !result_planes) return fail(SPH_E_ARG, "null output");
+    *nplane = kPackPlanes[loop];
+    for (int k = 0; k < 5; ++k) plane_floats[k] = k < kPackPlanes[loop] ? kPlaneFloats[loop][k] : 0;
+    *result_planes = kResPlanes[loop];
+    return SPH_OK;
+}
+
+static sph_status store_copy(const sph_store *store, sph_field field, const void *src, void *dst,
+                             void *stream)
+{
+    sph_status s = check_store(store);
+    if (s) return s;
+    if ((int)field < 0 || (int)field >= NFIELD) return fail(SPH_E_ARG, "unknown field");
+    if (store->n == 0) return SPH_OK;
+    if (src == nullptr && dst == nullptr) return fail(SPH_E_ARG, "null data pointer");
+    FieldDesc fd = field_desc(store, field);
+    const int64_t tot = store->n * fd.ncomp;
+    hipLaunchKernelGGL(k_field_copy, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, fd, store->n, (const char *)src, (char *)dst, src ? 1 : 0);
+    SPH_CHECK_LAUNCH("store copy launch");
+    return SPH_OK;
+}
+
+sph_status sph_store_put(const sph_store *store, sph_field field, const void *src, void *stream)
+{
+    if (!src) return fail(SPH_E_ARG, "src is null");
+    return store_copy(store, field, src, nullptr, stream);
+}
+
+sph_status sph_store_get(const sph_store *store, sph_field field, void *dst, void *stream)
+{
+    if (!dst) return fail(SPH_E_ARG, "dst is null");
+    return store_copy(store, field, nullptr, dst, stream);
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task *tasks, int32_t ntask,
+                           int64_t n, sph_plan **out)
+{
+    if (!out) return fail(SPH_E_ARG, "out is null");
+    *out = nullptr;
+    if (ncell < 0 || ntask < 0 || n < 0) return fail(SPH_E_ARG, "negative size");
+    if ((ncell > 0 && !cells) || (ntask > 0 && !tasks)) return fail(SPH_E_ARG, "null cells or tasks");
+    for (int32_t c = 0; c < ncell; ++c) {
+        const sph_cell &e = cells[c];
+        if (e.count < 0 || e.first < 0 || e.first + e.count > n)
+            return fail(SPH_E_PLAN, "cell " + std::to_string(c) + " outside [0, n)");
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(e.loc[d])) return fail(SPH_E_PLAN, "cell loc not finite");
+    }
+    for (int32_t t = 0; t < ntask; ++t) {
+        const sph_task &k = tasks[t];
+        if (k.ci < 0 || k.ci >= ncell || k.cj < 0 || k.cj >= ncell)
+            return fail(SPH_E_PLAN, "task " + std::to_string(t) + " names a cell out of range");
+        if (k.ci == k.cj && (k.shift[0] != 0 || k.shift[1] != 0 || k.shift[2] != 0))
+            return fail(SPH_E_PLAN, "self task " + std::to_string(t) + " has a shift");
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(k.shift[d])) return fail(SPH_E_PLAN, "task shift not finite");
+    }
+
+    sph_plan *p = new sph_plan();
+    p->n = n;
+    p->ncell = ncell;
+    p->ntask = ntask;
+    p->cells.assign(cells, cells + ncell);
+    p->tasks.assign(tasks, tasks + ntask);
+    p->slot_off.assign(ntask + 1, 0);
+    p->chunk_off.assign(ntask + 1, 0);
+    auto nch = [](int32_t c) { return (int64_t)((c + 63) / 64); };
+    for (int32_t t = 0; t < ntask; ++t) {
+        const sph_task &k = tasks[t];
+        const bool pair = k.ci != k.cj;
+        p->slot_off[t + 1] = p->slot_off[t] + cells[k.ci].count + (pair ? cells[k.cj].count : 0);
+        p->chunk_off[t + 1] = p->chunk_off[t] + nch(cells[k.ci].count) + (pair ? nch(cells[k.cj].count) : 0);
+    }
+    p->nslot = p->slot_off[ntask];
+    p->nchunk = p->chunk_off[ntask];
+    std::vector<Chunk> ch((size_t)p->nchunk);
+    for (int32_t t = 0; t < ntask; ++t) {
+        const sph_task &k = tasks[t];
+        const bool pair = k.ci != k.cj;
+        const sph_cell &a = cells[k.ci];
+        const sph_cell &b = cells[k.cj];
+        int64_t ci_ch = nch(a.count);
+        int64_t q = p->chunk_off[t];
+        for (int64_t j = 0; j < ci_ch; ++j) {
+            Chunk &c = ch[q++];
+            c.part0 = a.first + 64 * j;
+            c.slot0 = p->slot_off[t] + 64 * j;
+            c.n = (int32_t)std::min<int64_t>(64, a.count - 64 * j);
+            c.cell = k.ci;
+            c.task = t;
+            c.side = 0;
+            c.jslot0 = pair ? p->slot_off[t] + a.count : p->slot_off[t];
+            c.jn = pair ? b.count : a.count;
+            c.jchunk0 = (int32_t)(pair ? p->chunk_off[t] + ci_ch : p->chunk_off[t]);
+        }
+        if (pair)
+            for (int64_t j = 0; j < nch(b.count); ++j) {
+                Chunk &c = ch[q++];
+                c.part0 = b.first + 64 * j;
+                c.slot0 = p->slot_off[t] + a.count + 64 * j;
+                c.n = (int32_t)std::min<int64_t>(64, b.count - 64 * j);
+                c.cell = k.ci;
+                c.task = t;
+                c.side = 1;
+                c.jslot0 = p->slot_off[t];
+                c.jn = a.count;
+                c.jchunk0 = (int32_t)p->chunk_off[t];
+            }
+    }
+    if (p->nchunk > INT32_MAX) {
+        delete p;
+        return fail(SPH_E_UNSUPPORTED, "more than 2^31 chunks");
+    }
+
+    // batched form: cells must tile the store in order
+    bool ok = true;
+    int64_t acc = 0;
+    for (int32_t c = 0; c < ncell; ++c) {
+        if (cells[c].first != acc) ok = false;
+        acc += cells[c].count;
+        p->max_cell = std::max(p->max_cell, cells[c].count);
+    }
+    if (acc != n) ok = false;
+    p->batched_ok = ok;
+    std::vector<Chunk> tiles;
+    std::vector<CellRange> cr(ncell);
+    std::vector<int32_t> nbr_off(ncell + 1, 0);
+    std::vector<Nbr> nbr;
+    std::vector<int32_t> items;
+    if (ok) {
+        for (int32_t c = 0; c < ncell; ++c) {
+            cr[c].first = cells[c].first;
+            cr[c].count = cells[c].count;
+            cr[c].tile0 = (int32_t)tiles.size();
+            for (int32_t j = 0; j < (cells[c].count + 63) / 64; ++j) {
+                Chunk t{};
+                t.part0 = cells[c].first + 64 * j;
+                t.slot0 = t.part0;
+                t.n = std::min(64, cells[c].count - 64 * j);
+                t.cell = c;
+                t.task = -1;
+                tiles.push_back(t);
+            }
+        }
+        std::vector<int32_t> deg(ncell, 0);
+        for (const sph_task &k : p->tasks) {
+            deg[k.ci]++;
+            if (k.ci != k.cj) deg[k.cj]++;
+        }
+        for (int32_t c = 0; c < ncell; ++c) nbr_off[c + 1] = nbr_off[c] + deg[c];
+        nbr.resize(nbr_off[ncell]);
+        std::vector<int32_t> fillp(nbr_off.begin(), nbr_off.end() - 1);
+        for (const sph_task &k : p->tasks) {
+            const sph_cell &a = cells[k.ci];
+            const sph_cell &b = cells[k.cj];
+            if (k.ci == k.cj) {
+                nbr[fillp[k.ci]++] = Nbr{k.ci, 0.f, 0.f, 0.f};
+                continue;
+            }
+            nbr[fillp[k.ci]++] = Nbr{k.cj, (float)(b.loc[0] + k.shift[0] - a.loc[0]),
+                                     (float)(b.loc[1] + k.shift[1] - a.loc[1]),
+                                     (float)(b.loc[2] + k.shift[2] - a.loc[2])};
+            nbr[fillp[k.cj]++] = Nbr{k.ci, (float)(a.loc[0] - k.shift[0] - b.loc[0]),
+                                     (float)(a.loc[1] - k.shift[1] - b.loc[1]),
+                                     (float)(a.loc[2] - k.shift[2] - b.loc[2])};
+        }
+        for (int32_t c = 0; c < ncell; ++c) p->max_nbr = std::max(p->max_nbr, deg[c]);
+        // work items: tiles by descending candidate count (longest first)
+        std::vector<int64_t> cost(tiles.size());
+        for (size_t i = 0; i < tiles.size(); ++i) {
+            int64_t s = 0;
+            const int32_t c = tiles[i].cell;
+            for (int32_t e = nbr_off[c]; e < nbr_off[c + 1]; ++e) s += cells[nbr[e].cell].count;
+            cost[i] = s * tiles[i].n;
+        }
+        items.resize(tiles.size());
+        std::iota(items.begin(), items.end(), 0);
+        std::stable_sort(items.begin(), items.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+        p->ntile = (int32_t)tiles.size();
+    }
+
+    sph_status st;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        delete p;
+        return fail(SPH_E_HIP, "no HIP device");
+    }
+    p->device = dev;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+        p->num_cu = ncu;
+    if ((st = upload(&p->d_cells, p->cells)) || (st = upload(&p->d_tasks, p->tasks)) ||
+        (st = upload(&p->d_chunks, ch)) || (st = upload(&p->d_tiles, tiles)) || (st = upload(&p->d_cellr, cr)) ||
+        (st = upload(&p->d_nbr, nbr)) || (st = upload(&p->d_nbr_off, nbr_off)) || (st = upload(&p->d_items, items))) {
+        sph_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return SPH_OK;
+}
+
+void sph_plan_destroy(sph_plan *p)
+{
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    void *ptrs[] = {p->d_cells, p->d_tasks, p->d_chunks, p->d_tiles, p->d_cellr, p->d_nbr,
+                    p->d_nbr_off, p->d_items, p->d_csr_off, p->d_csr};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    delete p;
+}
+
+sph_status sph_plan_get_info(const sph_plan *p, sph_plan_info *info)
+{
+    if (!p || !info) return fail(SPH_E_ARG, "null argument");
+    info->n = p->n;
+    info->ncell = p->ncell;
+    info->ntask = p->ntask;
+    info->nslot = p->nslot;
+    info->nchunk = p->nchunk;
+    info->ntile = p->ntile;
+    info->max_cell = p->max_cell;
+    info->max_nbr = p->max_nbr;
+    info->batched_ok = p->batched_ok ? 1 : 0;
+    return SPH_OK;
+}
+
+sph_status sph_plan_buffer_bytes(const sph_plan *p, sph_loop loop, int32_t t0, int32_t t1, int64_t *nslot,
+                                 size_t *pack_bytes, size_t *result_bytes)
+{
+    if (!p) return fail(SPH_E_ARG, "plan is null");
+    sph_status s;
+    if ((s = check_loop(loop)) || (s = check_range(p, t0, t1))) return s;
+    const int64_t ns = p->slot_off[t1] - p->slot_off[t0];
+    const int64_t nc = p->chunk_off[t1] - p->chunk_off[t0];
+    if (nslot) *nslot = ns;
+    if (pack_bytes) *pack_bytes = pack_bytes_for(loop, ns, nc);
+    if (result_bytes) *result_bytes = result_bytes_for(loop, ns);
+    return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-task / bundled path
+// ---------------------------------------------------------------------------
+sph_status sph_zero_outputs(const sph_plan *p, sph_loop loop, const sph_store *store, void *stream)
+{
+    if (!p) return fail(SPH_E_ARG, "plan is null");
+    sph_status s;
+    if ((s = check_loop(loop)) || (s = check_store(store))) return s;
+    if (store->n != p->n) return fail(SPH_E_ARG, "store size differs from the plan's");
+    return launch_zero(p, loop, store, (hipStream_t)stream);
+}
+
+sph_status sph_pack(const sph_plan *p, sph_loop loop, const sph_store *store, int32_t t0, int32_t t1,
+                    void *pack_buf, size_t pack_bytes, void *stream)
+{
+    if (!p) return fail(SPH_E_ARG, "plan is null");
+    sph_status s;
+    if ((s = check_loop(loop)) || (s = check_store(store)) || (s = check_range(p, t0, t1))) return s;
+    if (store->n != p->n) return fail(SPH_E_ARG, "store size differs from the plan's");
+    const int64_t ns = p->slot_off[t1] - p->slot_off[t0];
+    if (ns == 0) return SPH_OK;
+    const size_t need = pack_bytes_for(loop, ns, p->chunk_off[t1] - p->chunk_off[t0]);
+    if (!pack_buf) return fail(SPH_E_ARG, "pack buffer is null");
+    if (!aligned256(pack_buf)) return fail(SPH_E_ARG, "pack buffer is not 256-byte aligned");
+    if (pack_bytes < need) return fail(SPH_E_CAPACITY, "pack buffer needs " + std::to_string(need) + " bytes");
+    return launch_pack(p, loop, store, false, t0, t1, pack_buf, 4, (hipStream_t)stream);
+}
+
+static sph_status interact_checked(const sph_plan *p, int loop, const void *pack_buf, size_t pack_bytes,
+                                   int32_t t0, int32_t t1, const sph_params *prm, void *res_buf,
+                                   size_t res_bytes, int32_t *counts, void *stream)
+{
+    if (!p) return fail(SPH_E_ARG, "plan is null");
+    sph_status s;
+    if ((s = check_range(p, t0, t1))) return s;
+    if (!prm) return fail(SPH_E_ARG, "params is null");
+    const int64_t ns = p->slot_off[t1] - p->slot_off[t0];
+    if (ns == 0) return SPH_OK;
+    if (!pack_buf || !res_buf) return fail(SPH_E_ARG, "null buffer");
+    if (!aligned256(pack_buf) || !aligned256(res_buf)) return fail(SPH_E_ARG, "buffer not 256-byte aligned");
+    if (pack_bytes < pack_bytes_for(loop, ns, p->chunk_off[t1] - p->chunk_off[t0]))
+        return fail(SPH_E_CAPACITY, "pack buffer too small for the range");
+    if (res_bytes < result_bytes_for(loop, ns)) return fail(SPH_E_CAPACITY, "result buffer too small");
+    return launch_interact(p, loop, false, t0, t1, pack_buf, prm, nullptr, res_buf, counts, nullptr,
+                           (hipStream_t)stream);
+}
+
+sph_status sph_density(const sph_plan *p, const void *pack_buf, size_t pack_bytes, int32_t t0, int32_t t1,
+                       const sph_params *prm, void *res_buf, size_t res_bytes, int32_t *counts, void *stream)
+{
+    return interact_checked(p, 0, pack_buf, pack_bytes, t0, t1, prm, res_buf, res_bytes, counts, stream);
+}
+sph_status sph_gradient(const sph_plan *p, const void *pack_buf, size_t pack_bytes, int32_t t0, int32_t t1,
+                        const sph_params *prm, void *res_buf, size_t res_bytes, int32_t *counts, void *stream)
+{
+    return interact_checked(p, 1, pack_buf, pack_bytes, t0, t1, prm, res_buf, res_bytes, counts, stream);
+}
+sph_status sph_force(const sph_plan *p, const void *pack_buf, size_t pack_bytes, int32_t t0, int32_t t1,
+                     const sph_params *prm, void *res_buf, size_t res_bytes, int32_t *counts, void *stream)
+{
+    return interact_checked(p, 2, pack_buf, pack_bytes, t0, t1, prm, res_buf, res_bytes, counts, stream);
+}
+
+sph_status sph_unpack(const sph_plan *p, sph_loop loop, const void *res_buf, size_t res_bytes, int32_t t0,
+                      int32_t t1, const sph_store *store, void *stream)
+{
+    if (!p) return fail(SPH_E_ARG, "plan is null");
+    sph_status s;
+    if ((s = check_loop(loop)) || (s = check_store(store)) || (s = check_range(p, t0, t1))) return s;
+    if (store->n != p->n) return fail(SPH_E_ARG, "store size differs from the plan's");
+    const int64_t ns = p->slot_off[t1] - p->slot_off[t0];
+    if (ns == 0) return SPH_OK;
+    if (!res_buf) return fail(SPH_E_ARG, "result buffer is null");
+    if (!aligned256(res_buf)) return fail(SPH_E_ARG, "result buffer not 256-byte aligned");
+    if (res_bytes < result_bytes_for(loop, ns)) return fail(SPH_E_CAPACITY, "result buffer too small");
+    sph_plan *mp = const_cast<sph_plan *>(p);
+    if (t1 - t0 > 1 && (s = ensure_csr(mp))) return s;
+    return launch_unpack(mp, loop, res_buf, false, t0, t1, store, 4, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// batched form
+// ---------------------------------------------------------------------------
+void sph_tuning_default(sph_tuning *t)
+{
+    if (!t) return;
+    std::memset(t, 0, sizeof(*t));
+    t->blocks_per_cu = 8;
+    t->window[0] = 256;
+    t->window[1] = 256;
+    t->window[2] = 128;
+    t->pack_waves = 4;
+    t->queue = 1;
+}
+
+static sph_status check_tuning(const sph_tuning *t)
+{
+    if (!t) return SPH_OK;
+    if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return fail(SPH_E_ARG, "blocks_per_cu outside 1..64");
+    for (int k = 0; k < 3; ++k)
+        if (t->window[k] != 64 && t->window[k] != 128 && t->window[k] != 256 && t->window[k] != 512)
+            return fail(SPH_E_ARG, "window must be 64, 128, 256 or 512");
+    if (t->pack_waves < 1 || t->pack_waves > 8) return fail(SPH_E_ARG, "pack_waves outside 1..8");
+    return SPH_OK;
+}
+
+static sph_status batched_checks(const sph_plan *p, int loop)
+{
+    if (!p) return fail(SPH_E_ARG, "plan is null");
+    sph_status s;
+    if ((s = check_loop(loop))) return s;
+    if (!p->batched_ok) return fail(SPH_E_UNSUPPORTED, "cells do not tile the store in order");
+    return SPH_OK;
+}
+
+sph_status sph_batched_ws_bytes(const sph_plan *p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(SPH_E_ARG, "null argument");
+    // queue counters + the largest pack buffer + the largest result buffer
+    *bytes = 256 + pack_bytes_for(2, p->n, p->ntile) + result_bytes_for(1, p->n);
+    return SPH_OK;
+}
+
+sph_status sph_pack_cells(const sph_plan *p, sph_loop loop, const sph_store *store, void *pack_buf,
+                          size_t pack_bytes, const sph_tuning *tn, void *stream)
+{
+    sph_status s;
+    if ((s = batched_checks(p, loop)) || (s = check_store(store)) || (s = check_tuning(tn))) return s;
+    if (store->n != p->n) return fail(SPH_E_ARG, "store size differs from the plan's");
+    if (p->n == 0) return SPH_OK;
+    if (!pack_buf || !aligned256(pack_buf)) return fail(SPH_E_ARG, "pack buffer null or misaligned");
+    if (pack_bytes < pack_bytes_for(loop, p->n, p->ntile)) return fail(SPH_E_CAPACITY, "pack buffer too small");
+    return launch_pack(p, loop, store, true, 0, 0, pack_buf, tn ? tn->pack_waves : 4, (hipStream_t)stream);
+}
+
+sph_status sph_interact_cells(const sph_plan *p, sph_loop loop, const void *pack_buf, size_t pack_bytes,
+                              const sph_params *prm, const sph_tuning *tn, void *res_buf, size_t res_bytes,
+                              int32_t *counts, void *ws, void *stream)
+{
+    sph_status s;
+    if ((s = batched_checks(p, loop)) || (s = check_tuning(tn))) return s;
+    if (!prm) return fail(SPH_E_ARG, "params is null");
+    if (p->n == 0) return SPH_OK;
+    if (!pack_buf || !res_buf || !ws) return fail(SPH_E_ARG, "null buffer or workspace");
+    if (!aligned256(pack_buf) || !aligned256(res_buf) || !aligned256(ws))
+        return fail(SPH_E_ARG, "buffer not 256-byte aligned");
+    if (pack_bytes < pack_bytes_for(loop, p->n, p->ntile)) return fail(SPH_E_CAPACITY, "pack buffer too small");
+    if (res_bytes < result_bytes_for(loop, p->n)) return fail(SPH_E_CAPACITY, "result buffer too small");
+    sph_tuning def;
+    sph_tuning_default(&def);
+    return launch_interact(p, loop, true, 0, p->ntask, pack_buf, prm, tn ? tn : &def, res_buf, counts, ws,
+                           (hipStream_t)stream);
+}
+
+sph_status sph_unpack_cells(const sph_plan *p, sph_loop loop, const void *res_buf, size_t res_bytes,
+                            const sph_store *store, const sph_tuning *tn, void *stream)
+{
+    sph_status s;
+    if ((s = batched_checks(p, loop)) || (s = check_store(store)) || (s = check_tuning(tn))) return s;
+    if (store->n != p->n) return fail(SPH_E_ARG, "store size differs from the plan's");
+    if (p->n == 0) return SPH_OK;
+    if (!res_buf || !aligned256(res_buf)) return fail(SPH_E_ARG, "result buffer null or misaligned");
+    if (res_bytes < result_bytes_for(loop, p->n)) return fail(SPH_E_CAPACITY, "result buffer too small");
+    return launch_unpack(const_cast<sph_plan *>(p), loop, res_buf, true, 0, 0, store, tn ? tn->pack_waves : 4,
+                         (hipStream_t)stream);
+}
+
+static sph_status step_batched(const sph_plan *p, const sph_store *store, const sph_params *prm,
+                               const sph_tuning *tn, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    sph_status s;
+    if ((s = batched_checks(p, 0)) || (s = check_store(store)) || (s = check_tuning(tn))) return s;
+    if (!prm) return fail(SPH_E_ARG, "params is null");
+    if (store->n != p->n) return fail(SPH_E_ARG, "store size differs from the plan's");
+    size_t need = 0;
+    sph_batched_ws_bytes(p, &need);
+    if (!ws || !aligned256(ws)) return fail(SPH_E_ARG, "workspace null or misaligned");
+    if (ws_bytes < need) return fail(SPH_E_CAPACITY, "workspace needs " + std::to_string(need) + " bytes");
+    if (p->n == 0) return SPH_OK;
+    sph_tuning def;
+    sph_tuning_default(&def);
+    if (!tn) tn = &def;
+    char *base = (char *)ws;
+    void *q = base;
+    void *pack = base + 256;
+    void *res = base + 256 + pack_bytes_for(2, p->n, p->ntile);
+    for (int loop = 0; loop < 3; ++loop) {
+        if ((s = launch_pack(p, loop, store, true, 0, 0, pack, tn->pack_waves, st))) return s;
+        if ((s = launch_interact(p, loop, true, 0, p->ntask, pack, prm, tn, res, nullptr, q, st))) return s;
+        if ((s = launch_unpack(const_cast<sph_plan *>(p), loop, res, true, 0, 0, store, tn->pack_waves, st)))
+            return s;
+    }
+    return SPH_OK;
+}
+
+sph_status sph_step_batched(const sph_plan *p, const sph_store *store, const sph_params *prm,
+                            const sph_tuning *tn, void *ws, size_t ws_bytes, void *stream)
+{
+    return step_batched(p, store, prm, tn, ws, ws_bytes, (hipStream_t)stream);
+}
+
+struct GraphHandle {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+sph_status sph_graph_capture(const sph_plan *p, const sph_store *store, const sph_params *prm,
+                             const sph_tuning *tn, void *ws, size_t ws_bytes, void **graph_exec)
+{
+    if (!graph_exec) return fail(SPH_E_ARG, "graph_exec is null");
+    *graph_exec = nullptr;
+    hipStream_t cs;
+    SPH_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    sph_status s = step_batched(p, store, prm, tn, ws, ws_bytes, cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (s) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t ex;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    *graph_exec = new GraphHandle{g, ex};
+    return SPH_OK;
+}
+
+sph_status sph_graph_launch(void *graph_exec, void *stream)
+{
+    if (!graph_exec) return fail(SPH_E_ARG, "graph_exec is null");
+    GraphHandle *h = (GraphHandle *)graph_exec;
+    SPH_HIP(hipGraphLaunch(h->exec, (hipStream_t)stream));
+    return SPH_OK;
+}
+
+void sph_graph_destroy(void *graph_exec)
+{
+    if (!graph_exec) return;
+    GraphHandle *h = (GraphHandle *)graph_exec;
+    (void)hipGraphExecDestroy(h->exec);
+    (void)hipGraphDestroy(h->graph);
+    delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,149 @@
+// Shared internals of libsph: plan tables, launch-argument structs, error
+// reporting and wave-level helpers for gfx950 (wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sph.h"
+#include "sph_layouts.hpp"
+
+namespace sph {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+sph_status fail(sph_status s, const std::string &msg);
+sph_status hip_fail(hipError_t e, const char *what);
+
+#define SPH_HIP(call)                                        \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return ::sph::hip_fail(e_, #call); \
+    } while (0)
+
+#define SPH_CHECK_LAUNCH(what)                               \
+    do {                                                     \
+        hipError_t e_ = hipGetLastError();                   \
+        if (e_ != hipSuccess) return ::sph::hip_fail(e_, what); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// plan tables (device copies are plain arrays of these)
+// ---------------------------------------------------------------------------
+// A chunk: up to 64 consecutive slots of one side of one task, or up to 64
+// particles of one cell (a tile of the batched form; task = -1).
+struct Chunk {
+    int64_t part0;   // first particle
+    int64_t slot0;   // first slot (absolute over all tasks; = part0 for tiles)
+    int64_t jslot0;  // per-task: first slot of the partner side
+    int32_t n;       // particles in the chunk (1..64)
+    int32_t jn;      // per-task: slots of the partner side
+    int32_t cell;    // origin cell (ci of the task; the tile's own cell)
+    int32_t task;    // task index, -1 for a cell tile
+    int32_t side;    // 0: ci side, 1: cj side
+    int32_t jchunk0; // per-task: first chunk of the partner side
+};
+static_assert(sizeof(Chunk) == 48, "chunk layout");
+
+// A neighbour entry of a cell: cell j and the float32 translation that moves
+// j's cell-relative offsets into this cell's frame.
+struct Nbr {
+    int32_t cell;
+    float dx, dy, dz;
+};
+
+struct CellRange {
+    int64_t first;
+    int32_t count;
+    int32_t tile0;  // first tile of the cell
+};
+
+}  // namespace sph
+
+struct sph_plan {
+    int64_t n = 0;
+    int32_t ncell = 0, ntask = 0;
+    int device = 0;
+    int num_cu = 256;
+    std::vector<sph_cell> cells;
+    std::vector<sph_task> tasks;
+    std::vector<int64_t> slot_off;   // ntask + 1
+    std::vector<int64_t> chunk_off;  // ntask + 1
+    int64_t nslot = 0, nchunk = 0;
+    int32_t ntile = 0, max_cell = 0, max_nbr = 0;
+    bool batched_ok = false;
+    // device tables
+    sph_cell *d_cells = nullptr;
+    sph_task *d_tasks = nullptr;
+    sph::Chunk *d_chunks = nullptr;
+    sph::Chunk *d_tiles = nullptr;
+    sph::CellRange *d_cellr = nullptr;
+    sph::Nbr *d_nbr = nullptr;
+    int32_t *d_nbr_off = nullptr;
+    int32_t *d_items = nullptr;      // tiles in descending cost order
+    // per-particle slot lists, built on the first multi-task unpack
+    std::mutex csr_mu;
+    bool csr_built = false;
+    int64_t *d_csr_off = nullptr;
+    int64_t *d_csr = nullptr;
+};
+
+namespace sph {
+
+inline int64_t round_slots(int64_t n) { return (n + 63) / 64 * 64; }
+
+// floats per slot in each pack plane, per loop
+constexpr int kPackPlanes[3] = {2, 3, 5};
+constexpr int kPlaneFloats[3][5] = {{4, 1, 0, 0, 0}, {4, 4, 2, 0, 0}, {4, 4, 4, 4, 1}};
+constexpr int kPackFloats[3] = {5, 10, 17};
+constexpr int kResPlanes[3] = {3, 6, 4};
+constexpr size_t kBoundsBytes = 32;  // per chunk: float4 lo {x y z Hmax}, float4 hi
+
+// H = gamma_k h for the cubic spline (support radius over smoothing length).
+constexpr float kGammaK = 1.8257418583505538f;
+constexpr float kC3 = 2.5464790894703255f;  // 8 / pi
+
+struct StoreArg {
+    void *sub[kMaxSub];
+};
+
+inline StoreArg store_arg(const sph_store *s)
+{
+    StoreArg a;
+    for (int i = 0; i < kMaxSub; ++i) a.sub[i] = s->sub[i];
+    return a;
+}
+
+sph_status check_store(const sph_store *s);
+sph_status check_loop(int loop);
+sph_status check_range(const sph_plan *p, int32_t t0, int32_t t1);
+sph_status ensure_csr(sph_plan *p);
+
+// byte sizes of a range's buffers
+inline size_t pack_bytes_for(int loop, int64_t nslot, int64_t nchunk)
+{
+    return (size_t)round_slots(nslot) * 4 * kPackFloats[loop] + (size_t)nchunk * kBoundsBytes;
+}
+inline size_t result_bytes_for(int loop, int64_t nslot)
+{
+    return (size_t)round_slots(nslot) * 4 * kResPlanes[loop];
+}
+
+// ---------------------------------------------------------------------------
+// launchers implemented in the .hip files
+// ---------------------------------------------------------------------------
+sph_status launch_pack(const sph_plan *p, int loop, const sph_store *s, bool cells, int32_t t0, int32_t t1,
+                       void *buf, int waves, hipStream_t st);
+sph_status launch_unpack(sph_plan *p, int loop, const void *res, bool cells, int32_t t0, int32_t t1,
+                         const sph_store *s, int waves, hipStream_t st);
+sph_status launch_zero(const sph_plan *p, int loop, const sph_store *s, hipStream_t st);
+sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, int32_t t1,
+                           const void *pack, const sph_params *prm, const sph_tuning *tn, void *res,
+                           int32_t *counts, void *ws, hipStream_t st);
+
+}  // namespace sph

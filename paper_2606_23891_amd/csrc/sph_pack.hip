@@ -1,0 +1,316 @@
+// Pack and unpack kernels (paper Sec. 2.3, Table 1).
+//
+// One wave64 handles one chunk of up to 64 consecutive particles of one cell
+// (one side of a task, or a tile of the batched form).  Lanes walk
+// consecutive particles, so every field load of a substruct is a coalesced
+// strided access whose stride is the substruct's record size: an AoS record
+// drags its whole cache lines, a split substruct only the fields the loop
+// needs -- the paper's point, now at HBM instead of host memory.
+// Layout, loop and field offsets are template parameters, so each load folds
+// to base + p * stride + constant.
+//
+// Pack: positions become float32 offsets from the task origin, computed in
+// float64 and rounded once; every other field is copied bit for bit.  The
+// wave also emits its chunk's bounding box and largest support radius, used
+// by the interaction kernels to skip far tiles.
+// Unpack: per-task results are added (float32, fixed slot order) into the
+// store; the signal velocity keeps the larger value.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "sph_internal.hpp"
+
+namespace sph {
+
+template <int I, int N, class Fn>
+__device__ __forceinline__ void static_for(Fn &&fn)
+{
+    if constexpr (I < N) {
+        fn(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(fn);
+    }
+}
+
+template <int L, int F, int C>
+__device__ __forceinline__ char *field_ptr(const StoreArg &s, int64_t p)
+{
+    constexpr int sb = kLayouts[L].sub[F][C];
+    constexpr int off = kLayouts[L].off[F][C];
+    constexpr int stride = kLayouts[L].sub_bytes[sb];
+    char *base = (char *)__builtin_assume_aligned(s.sub[sb], 256);
+    return base + p * stride + off;
+}
+
+template <int L, int F, int C, typename T>
+__device__ __forceinline__ T ld(const StoreArg &s, int64_t p)
+{
+    return *reinterpret_cast<const T *>(field_ptr<L, F, C>(s, p));
+}
+
+template <int L, int F, int C, typename T>
+__device__ __forceinline__ void st(const StoreArg &s, int64_t p, T v)
+{
+    *reinterpret_cast<T *>(field_ptr<L, F, C>(s, p)) = v;
+}
+
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+struct PackArgs {
+    StoreArg store;
+    const Chunk *chunks;
+    const sph_cell *cells;
+    const sph_task *tasks;
+    int64_t chunk_base;
+    int64_t nchunk;
+    int64_t slot_base;
+    int64_t P;      // slots per plane
+    char *buf;
+    float4 *bounds; // 2 per chunk
+};
+
+template <int L, int LOOP>
+__global__ __launch_bounds__(512) void k_pack(PackArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t c = __builtin_amdgcn_readfirstlane((int)((int64_t)blockIdx.x * (blockDim.x >> 6) +
+                                                           (threadIdx.x >> 6)));
+    if (c >= a.nchunk) return;
+    const Chunk ch = a.chunks[a.chunk_base + c];
+    const sph_cell &oc = a.cells[ch.cell];
+    double o0 = oc.loc[0], o1 = oc.loc[1], o2 = oc.loc[2];
+    if (ch.side) {
+        const sph_task &t = a.tasks[ch.task];
+        o0 = o0 - t.shift[0];
+        o1 = o1 - t.shift[1];
+        o2 = o2 - t.shift[2];
+    }
+    const bool valid = lane < ch.n;
+    const int64_t p = ch.part0 + lane;
+    const int64_t slot = ch.slot0 - a.slot_base + lane;
+    const StoreArg &s = a.store;
+    const int64_t P = a.P;
+    float dx = 0.f, dy = 0.f, dz = 0.f, hh = 0.f;
+    if (valid) {
+        dx = (float)(ld<L, FX, 0, double>(s, p) - o0);
+        dy = (float)(ld<L, FX, 1, double>(s, p) - o1);
+        dz = (float)(ld<L, FX, 2, double>(s, p) - o2);
+        hh = ld<L, FH, 0, float>(s, p);
+        float4 *pl0 = (float4 *)a.buf;
+        pl0[slot] = make_float4(dx, dy, dz, hh);
+        if constexpr (LOOP == 0) {
+            float *pl1 = (float *)(a.buf + P * 16);
+            pl1[slot] = ld<L, FMASS, 0, float>(s, p);
+        } else {
+            float4 *pl1 = (float4 *)(a.buf + P * 16);
+            pl1[slot] = make_float4(ld<L, FV, 0, float>(s, p), ld<L, FV, 1, float>(s, p),
+                                    ld<L, FV, 2, float>(s, p), ld<L, FMASS, 0, float>(s, p));
+            if constexpr (LOOP == 1) {
+                float2 *pl2 = (float2 *)(a.buf + P * 32);
+                pl2[slot] = make_float2(ld<L, FU, 0, float>(s, p), ld<L, FRHO, 0, float>(s, p));
+            } else {
+                float4 *pl2 = (float4 *)(a.buf + P * 32);
+                pl2[slot] = make_float4(ld<L, FU, 0, float>(s, p), ld<L, FRHO, 0, float>(s, p),
+                                        ld<L, FRHODH, 0, float>(s, p), ld<L, FDIV, 0, float>(s, p));
+                float4 *pl3 = (float4 *)(a.buf + P * 48);
+                pl3[slot] = make_float4(ld<L, FROT, 0, float>(s, p), ld<L, FROT, 1, float>(s, p),
+                                        ld<L, FROT, 2, float>(s, p), ld<L, FAV, 0, float>(s, p));
+                float *pl4 = (float *)(a.buf + P * 64);
+                pl4[slot] = ld<L, FAD, 0, float>(s, p);
+            }
+        }
+    }
+    const float inf = __builtin_huge_valf();
+    const float lx = wave_min(valid ? dx : inf), ly = wave_min(valid ? dy : inf), lz = wave_min(valid ? dz : inf);
+    const float hx = wave_max(valid ? dx : -inf), hy = wave_max(valid ? dy : -inf), hz = wave_max(valid ? dz : -inf);
+    const float hm = wave_max(valid ? kGammaK * hh : 0.f);
+    if (lane == 0) {
+        a.bounds[2 * c] = make_float4(lx, ly, lz, hm);
+        a.bounds[2 * c + 1] = make_float4(hx, hy, hz, 0.f);
+    }
+}
+
+// loop outputs: (field, component) per result plane
+constexpr int kOutF[3][6] = {{FRHO, FRHODH, FWCOUNT}, {FDIV, FROT, FROT, FROT, FLAP, FVSIG}, {FA, FA, FA, FUDT}};
+constexpr int kOutC[3][6] = {{0, 0, 0}, {0, 0, 1, 2, 0, 0}, {0, 1, 2, 0}};
+
+// the reduction of one result into one output value
+template <int LOOP, int K>
+__device__ __forceinline__ float reduce_one(float cur, float r)
+{
+    if constexpr (LOOP == 1 && K == 5) return (r > cur) ? r : cur;  // signal velocity: maximum
+    else return cur + r;
+}
+
+struct UnpackArgs {
+    StoreArg store;
+    const Chunk *chunks;
+    int64_t chunk_base;
+    int64_t nchunk;
+    int64_t slot_base;
+    int64_t P;
+    const float *res;
+    const int64_t *csr_off;
+    const int64_t *csr;
+    int64_t slot_lo, slot_hi;  // absolute slots of the range (CSR path)
+    int64_t n;
+};
+
+// One chunk per wave.  CELLS: per-particle results, out = +0 (+) r; else one
+// task's partials added into the current value (slots of one task touch
+// distinct particles, so lanes never collide).
+template <int L, int LOOP, bool CELLS>
+__global__ __launch_bounds__(512) void k_unpack_chunks(UnpackArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t c = __builtin_amdgcn_readfirstlane((int)((int64_t)blockIdx.x * (blockDim.x >> 6) +
+                                                           (threadIdx.x >> 6)));
+    if (c >= a.nchunk) return;
+    const Chunk ch = a.chunks[a.chunk_base + c];
+    if (lane >= ch.n) return;
+    const int64_t p = ch.part0 + lane;
+    const int64_t slot = ch.slot0 - a.slot_base + lane;
+    static_for<0, kResPlanes[LOOP]>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int F = kOutF[LOOP][k], C = kOutC[LOOP][k];
+        const float r = a.res[k * a.P + slot];
+        const float cur = CELLS ? 0.0f : ld<L, F, C, float>(a.store, p);
+        st<L, F, C, float>(a.store, p, reduce_one<LOOP, k>(cur, r));
+    });
+}
+
+// Several tasks: one thread per particle walks its slots in ascending order.
+template <int L, int LOOP>
+__global__ __launch_bounds__(256) void k_unpack_csr(UnpackArgs a)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    int64_t b = a.csr_off[p];
+    const int64_t e = a.csr_off[p + 1];
+    while (b < e && a.csr[b] < a.slot_lo) ++b;
+    if (b == e || a.csr[b] >= a.slot_hi) return;
+    static_for<0, kResPlanes[LOOP]>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int F = kOutF[LOOP][k], C = kOutC[LOOP][k];
+        float cur = ld<L, F, C, float>(a.store, p);
+        for (int64_t q = b; q < e && a.csr[q] < a.slot_hi; ++q)
+            cur = reduce_one<LOOP, k>(cur, a.res[k * a.P + (a.csr[q] - a.slot_lo)]);
+        st<L, F, C, float>(a.store, p, cur);
+    });
+}
+
+template <int L>
+static sph_status pack_l(const sph_plan *p, int loop, const PackArgs &a, int waves, hipStream_t st)
+{
+    const unsigned grid = (unsigned)((a.nchunk + waves - 1) / waves);
+    const dim3 blk(64 * waves);
+    if (loop == 0) hipLaunchKernelGGL((k_pack<L, 0>), dim3(grid), blk, 0, st, a);
+    else if (loop == 1) hipLaunchKernelGGL((k_pack<L, 1>), dim3(grid), blk, 0, st, a);
+    else hipLaunchKernelGGL((k_pack<L, 2>), dim3(grid), blk, 0, st, a);
+    (void)p;
+    SPH_CHECK_LAUNCH("pack launch");
+    return SPH_OK;
+}
+
+template <int L, int LOOP>
+static void unpack_ll(const UnpackArgs &a, bool cells, bool csr, int waves, hipStream_t st)
+{
+    if (csr) {
+        hipLaunchKernelGGL((k_unpack_csr<L, LOOP>), dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+        return;
+    }
+    const unsigned grid = (unsigned)((a.nchunk + waves - 1) / waves);
+    if (cells) hipLaunchKernelGGL((k_unpack_chunks<L, LOOP, true>), dim3(grid), dim3(64 * waves), 0, st, a);
+    else hipLaunchKernelGGL((k_unpack_chunks<L, LOOP, false>), dim3(grid), dim3(64 * waves), 0, st, a);
+}
+
+template <int L>
+static sph_status unpack_l(int loop, const UnpackArgs &a, bool cells, bool csr, int waves, hipStream_t st)
+{
+    if (loop == 0) unpack_ll<L, 0>(a, cells, csr, waves, st);
+    else if (loop == 1) unpack_ll<L, 1>(a, cells, csr, waves, st);
+    else unpack_ll<L, 2>(a, cells, csr, waves, st);
+    SPH_CHECK_LAUNCH("unpack launch");
+    return SPH_OK;
+}
+
+#define SPH_BY_LAYOUT(layout, fn, ...)                                              \
+    switch (layout) {                                                               \
+    case 0: return fn<0>(__VA_ARGS__); case 1: return fn<1>(__VA_ARGS__);            \
+    case 2: return fn<2>(__VA_ARGS__); case 3: return fn<3>(__VA_ARGS__);            \
+    case 4: return fn<4>(__VA_ARGS__); case 5: return fn<5>(__VA_ARGS__);            \
+    case 6: return fn<6>(__VA_ARGS__); case 7: return fn<7>(__VA_ARGS__);            \
+    case 8: return fn<8>(__VA_ARGS__);                                              \
+    default: return fail(SPH_E_LAYOUT, "unknown layout");                           \
+    }
+
+sph_status launch_pack(const sph_plan *p, int loop, const sph_store *s, bool cells, int32_t t0, int32_t t1,
+                       void *buf, int waves, hipStream_t st)
+{
+    PackArgs a{};
+    a.store = store_arg(s);
+    a.cells = p->d_cells;
+    a.tasks = p->d_tasks;
+    a.buf = (char *)buf;
+    int64_t nslot;
+    if (cells) {
+        a.chunks = p->d_tiles;
+        a.chunk_base = 0;
+        a.nchunk = p->ntile;
+        a.slot_base = 0;
+        nslot = p->n;
+    } else {
+        a.chunks = p->d_chunks;
+        a.chunk_base = p->chunk_off[t0];
+        a.nchunk = p->chunk_off[t1] - p->chunk_off[t0];
+        a.slot_base = p->slot_off[t0];
+        nslot = p->slot_off[t1] - p->slot_off[t0];
+    }
+    a.P = round_slots(nslot);
+    a.bounds = (float4 *)(a.buf + a.P * 4 * kPackFloats[loop]);
+    if (a.nchunk == 0) return SPH_OK;
+    SPH_BY_LAYOUT(s->layout, pack_l, p, loop, a, waves, st);
+}
+
+sph_status launch_unpack(sph_plan *p, int loop, const void *res, bool cells, int32_t t0, int32_t t1,
+                         const sph_store *s, int waves, hipStream_t st)
+{
+    UnpackArgs a{};
+    a.store = store_arg(s);
+    a.res = (const float *)res;
+    a.n = p->n;
+    bool csr = false;
+    if (cells) {
+        a.chunks = p->d_tiles;
+        a.nchunk = p->ntile;
+        a.P = round_slots(p->n);
+    } else {
+        a.chunks = p->d_chunks;
+        a.chunk_base = p->chunk_off[t0];
+        a.nchunk = p->chunk_off[t1] - p->chunk_off[t0];
+        a.slot_base = p->slot_off[t0];
+        a.P = round_slots(p->slot_off[t1] - p->slot_off[t0]);
+        if (t1 - t0 > 1) {
+            csr = true;
+            a.csr_off = p->d_csr_off;
+            a.csr = p->d_csr;
+            a.slot_lo = p->slot_off[t0];
+            a.slot_hi = p->slot_off[t1];
+        }
+    }
+    if (a.nchunk == 0) return SPH_OK;
+    SPH_BY_LAYOUT(s->layout, unpack_l, loop, a, cells, csr, waves, st);
+}
+
+}  // namespace sph

@@ -1,0 +1,405 @@
+"""Thin ctypes binding of libsph (argument marshalling only).
+
+Every function here forwards to the C entry point of the same name declared in
+``include/sph.h``; all arithmetic runs in the HIP kernels of the library.
+Device memory and streams come from PyTorch (ROCm): buffers are torch tensors
+passed by ``data_ptr()``, streams by ``torch.cuda.current_stream().cuda_stream``.
+The library must exist (built by ``python -m paper_2606_23891_amd.build``);
+loading fails loudly otherwise -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsph.so")
+
+DENSITY, GRADIENT, FORCE = 0, 1, 2
+LOOPS = (DENSITY, GRADIENT, FORCE)
+LAYOUTS = ["AOS", "AOS_RANDOM", "SAOS_GRAD", "SAOS_FORCE", "SAOS_SHARED", "SAOS_GRAD_TYPE",
+           "SAOS_FORCE_TYPE", "SAOS_SHARED_TYPE", "SOA"]
+FIELDS = ["x", "v", "a", "mass", "h", "u", "u_dt", "rho", "rho_dh", "wcount", "div_v", "rot_v",
+          "lap_u", "v_sig", "alpha_v", "alpha_d", "time_bin", "id", "cold"]
+FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
+MAX_SUB = 32
+STATUS = {0: "SPH_OK", -1: "SPH_E_ARG", -2: "SPH_E_LAYOUT", -3: "SPH_E_CAPACITY", -4: "SPH_E_PLAN",
+          -5: "SPH_E_HIP", -6: "SPH_E_UNSUPPORTED"}
+
+
+class sph_store(C.Structure):
+    _fields_ = [("layout", C.c_int32), ("nsub", C.c_int32), ("n", C.c_int64),
+                ("sub", C.c_void_p * MAX_SUB)]
+
+
+class sph_params(C.Structure):
+    _fields_ = [("gamma_ad", C.c_float), ("beta_visc", C.c_float), ("balsara_eps", C.c_float),
+                ("pad", C.c_float)]
+
+
+class sph_tuning(C.Structure):
+    _fields_ = [("blocks_per_cu", C.c_int32), ("window", C.c_int32 * 3), ("pack_waves", C.c_int32),
+                ("queue", C.c_int32), ("reserved", C.c_int32 * 2)]
+
+
+class sph_plan_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("ncell", C.c_int32), ("ntask", C.c_int32), ("nslot", C.c_int64),
+                ("nchunk", C.c_int64), ("ntile", C.c_int32), ("max_cell", C.c_int32),
+                ("max_nbr", C.c_int32), ("batched_ok", C.c_int32)]
+
+
+class SphError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+_lib = None
+vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+_SIGS = {
+    "sph_status_str": ([i32], C.c_char_p),
+    "sph_last_error": ([], C.c_char_p),
+    "sph_layout_info": ([i32, C.POINTER(i32), C.POINTER(sz)], i32),
+    "sph_field_location": ([i32, i32, i32, C.POINTER(i32), C.POINTER(sz), C.POINTER(sz)], i32),
+    "sph_field_info": ([i32, C.POINTER(i32), C.POINTER(i32)], i32),
+    "sph_pack_layout": ([i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)], i32),
+    "sph_store_put": ([vp, i32, vp, vp], i32),
+    "sph_store_get": ([vp, i32, vp, vp], i32),
+    "sph_plan_create": ([vp, i32, vp, i32, i64, C.POINTER(vp)], i32),
+    "sph_plan_destroy": ([vp], None),
+    "sph_plan_get_info": ([vp, vp], i32),
+    "sph_plan_buffer_bytes": ([vp, i32, i32, i32, C.POINTER(i64), C.POINTER(sz), C.POINTER(sz)], i32),
+    "sph_zero_outputs": ([vp, i32, vp, vp], i32),
+    "sph_pack": ([vp, i32, vp, i32, i32, vp, sz, vp], i32),
+    "sph_density": ([vp, vp, sz, i32, i32, vp, vp, sz, vp, vp], i32),
+    "sph_gradient": ([vp, vp, sz, i32, i32, vp, vp, sz, vp, vp], i32),
+    "sph_force": ([vp, vp, sz, i32, i32, vp, vp, sz, vp, vp], i32),
+    "sph_unpack": ([vp, i32, vp, sz, i32, i32, vp, vp], i32),
+    "sph_tuning_default": ([vp], None),
+    "sph_batched_ws_bytes": ([vp, C.POINTER(sz)], i32),
+    "sph_pack_cells": ([vp, i32, vp, vp, sz, vp, vp], i32),
+    "sph_interact_cells": ([vp, i32, vp, sz, vp, vp, vp, sz, vp, vp, vp], i32),
+    "sph_unpack_cells": ([vp, i32, vp, sz, vp, vp, vp], i32),
+    "sph_step_batched": ([vp, vp, vp, vp, vp, sz, vp], i32),
+    "sph_graph_capture": ([vp, vp, vp, vp, vp, sz, C.POINTER(vp)], i32),
+    "sph_graph_launch": ([vp, vp], i32),
+    "sph_graph_destroy": ([vp], None),
+    "sph_adjoint_ws_bytes": ([vp, C.POINTER(sz)], i32),
+    "sph_adjoint_forward": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp], i32),
+    "sph_force_adjoint": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz,
+                           vp], i32),
+    "sph_density_adjoint": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp], i32),
+}
+
+
+def lib():
+    """Load libsph.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_23891_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    for name, (args, res) in _SIGS.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise SphError(status, where, lib().sph_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+def default_params() -> sph_params:
+    return sph_params(5.0 / 3.0, 3.0, 1e-4, 0.0)
+
+
+def default_tuning() -> sph_tuning:
+    t = sph_tuning()
+    lib().sph_tuning_default(C.byref(t))
+    return t
+
+
+# ---------------------------------------------------------------------------
+# host-only queries
+# ---------------------------------------------------------------------------
+def sph_layout_info(layout: int):
+    n = i32()
+    sb = (sz * MAX_SUB)()
+    _check(lib().sph_layout_info(layout, C.byref(n), sb), "sph_layout_info")
+    return [int(sb[i]) for i in range(n.value)]
+
+
+def sph_field_location(layout: int, field: int, comp: int):
+    s, o, st = i32(), sz(), sz()
+    _check(lib().sph_field_location(layout, field, comp, C.byref(s), C.byref(o), C.byref(st)),
+           "sph_field_location")
+    return s.value, o.value, st.value
+
+
+def sph_field_info(field: int):
+    n, b = i32(), i32()
+    _check(lib().sph_field_info(field, C.byref(n), C.byref(b)), "sph_field_info")
+    return n.value, b.value
+
+
+def sph_pack_layout(loop: int):
+    n, rp = i32(), i32()
+    pf = (i32 * 5)()
+    _check(lib().sph_pack_layout(loop, C.byref(n), pf, C.byref(rp)), "sph_pack_layout")
+    return [pf[i] for i in range(n.value)], rp.value
+
+
+# ---------------------------------------------------------------------------
+# device objects
+# ---------------------------------------------------------------------------
+class Store:
+    """A particle store of one layout, substructs held as torch uint8 tensors."""
+
+    def __init__(self, layout: int, n: int, device="cuda"):
+        import torch
+        self.layout, self.n = layout, n
+        self.sub_bytes = sph_layout_info(layout)
+        self.subs = [torch.zeros(max(1, n * b), dtype=torch.uint8, device=device) for b in self.sub_bytes]
+        self.c = sph_store()
+        self.c.layout = layout
+        self.c.nsub = len(self.subs)
+        self.c.n = n
+        for i, t in enumerate(self.subs):
+            self.c.sub[i] = t.data_ptr()
+
+    @property
+    def ref(self):
+        return C.byref(self.c)
+
+    def put(self, name: str, arr, stream=None):
+        import torch
+        t = torch.as_tensor(np.ascontiguousarray(arr)).to(self.subs[0].device)
+        sph_store_put(self, FIELD_ID[name], t, stream)
+
+    def get(self, name: str, stream=None) -> np.ndarray:
+        import torch
+        nc, cb = sph_field_info(FIELD_ID[name])
+        dt = {("x", 8): torch.float64, ("id", 8): torch.int64, ("cold", 8): torch.int64}.get(
+            (name, cb), {4: torch.float32, 1: torch.int8}.get(cb))
+        t = torch.empty((self.n, nc) if nc > 1 else (self.n,), dtype=dt, device=self.subs[0].device)
+        sph_store_get(self, FIELD_ID[name], t, stream)
+        torch.cuda.synchronize()
+        out = t.cpu().numpy()
+        return out.view(np.uint64) if name == "cold" else out
+
+    def put_all(self, fields: Dict[str, np.ndarray]):
+        for k, v in fields.items():
+            if k == "cold":
+                v = np.ascontiguousarray(v).view(np.int64)
+            self.put(k, v)
+
+    def raw(self) -> bytes:
+        import torch
+        torch.cuda.synchronize()
+        return b"".join(t[: self.n * b].cpu().numpy().tobytes() for t, b in zip(self.subs, self.sub_bytes))
+
+
+class Plan:
+    """Cells and tasks of one step, uploaded once."""
+
+    def __init__(self, cells: np.ndarray, tasks: np.ndarray, n: int):
+        self.cells = np.ascontiguousarray(cells)
+        self.tasks = np.ascontiguousarray(tasks)
+        assert self.cells.dtype.itemsize == 48 and self.tasks.dtype.itemsize == 40
+        self.ptr = sph_plan_create(self.cells, self.tasks, n)
+        self.n = n
+
+    def info(self) -> sph_plan_info:
+        return sph_plan_get_info(self)
+
+    def buffer_bytes(self, loop: int, t0: int, t1: int):
+        return sph_plan_buffer_bytes(self, loop, t0, t1)
+
+    def close(self):
+        if self.ptr:
+            lib().sph_plan_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _h(x):
+    return x.ptr if isinstance(x, Plan) else x
+
+
+def _s(x):
+    return x.ref if isinstance(x, Store) else x
+
+
+def sph_store_put(store, field: int, src, stream=None):
+    _check(lib().sph_store_put(_s(store), field, _ptr(src), _stream(stream)), "sph_store_put")
+
+
+def sph_store_get(store, field: int, dst, stream=None):
+    _check(lib().sph_store_get(_s(store), field, _ptr(dst), _stream(stream)), "sph_store_get")
+
+
+def sph_plan_create(cells: np.ndarray, tasks: np.ndarray, n: int):
+    out = vp()
+    _check(lib().sph_plan_create(cells.ctypes.data if cells.size else None, cells.size,
+                                 tasks.ctypes.data if tasks.size else None, tasks.size, n, C.byref(out)),
+           "sph_plan_create")
+    return out.value
+
+
+def sph_plan_get_info(plan) -> sph_plan_info:
+    info = sph_plan_info()
+    _check(lib().sph_plan_get_info(_h(plan), C.byref(info)), "sph_plan_get_info")
+    return info
+
+
+def sph_plan_buffer_bytes(plan, loop: int, t0: int, t1: int):
+    ns, pb, rb = i64(), sz(), sz()
+    _check(lib().sph_plan_buffer_bytes(_h(plan), loop, t0, t1, C.byref(ns), C.byref(pb), C.byref(rb)),
+           "sph_plan_buffer_bytes")
+    return ns.value, pb.value, rb.value
+
+
+def sph_zero_outputs(plan, loop: int, store, stream=None):
+    _check(lib().sph_zero_outputs(_h(plan), loop, _s(store), _stream(stream)), "sph_zero_outputs")
+
+
+def sph_pack(plan, loop: int, store, t0: int, t1: int, buf, stream=None):
+    _check(lib().sph_pack(_h(plan), loop, _s(store), t0, t1, _ptr(buf), _nbytes(buf), _stream(stream)),
+           "sph_pack")
+
+
+def _nbytes(t) -> int:
+    if t is None:
+        return 0
+    return t.numel() * t.element_size()
+
+
+def _interact(name, plan, buf, t0, t1, params, res, counts, stream):
+    fn = getattr(lib(), name)
+    p = params if params is not None else default_params()
+    _check(fn(_h(plan), _ptr(buf), _nbytes(buf), t0, t1, C.byref(p), _ptr(res), _nbytes(res), _ptr(counts),
+              _stream(stream)), name)
+
+
+def sph_density(plan, buf, t0, t1, res, params=None, counts=None, stream=None):
+    _interact("sph_density", plan, buf, t0, t1, params, res, counts, stream)
+
+
+def sph_gradient(plan, buf, t0, t1, res, params=None, counts=None, stream=None):
+    _interact("sph_gradient", plan, buf, t0, t1, params, res, counts, stream)
+
+
+def sph_force(plan, buf, t0, t1, res, params=None, counts=None, stream=None):
+    _interact("sph_force", plan, buf, t0, t1, params, res, counts, stream)
+
+
+INTERACT = {DENSITY: sph_density, GRADIENT: sph_gradient, FORCE: sph_force}
+
+
+def sph_unpack(plan, loop: int, res, t0: int, t1: int, store, stream=None):
+    _check(lib().sph_unpack(_h(plan), loop, _ptr(res), _nbytes(res), t0, t1, _s(store), _stream(stream)),
+           "sph_unpack")
+
+
+def sph_batched_ws_bytes(plan) -> int:
+    b = sz()
+    _check(lib().sph_batched_ws_bytes(_h(plan), C.byref(b)), "sph_batched_ws_bytes")
+    return b.value
+
+
+def sph_pack_cells(plan, loop: int, store, buf, tuning=None, stream=None):
+    _check(lib().sph_pack_cells(_h(plan), loop, _s(store), _ptr(buf), _nbytes(buf),
+                                C.byref(tuning) if tuning else None, _stream(stream)), "sph_pack_cells")
+
+
+def sph_interact_cells(plan, loop: int, buf, res, ws, params=None, tuning=None, counts=None, stream=None):
+    p = params if params is not None else default_params()
+    _check(lib().sph_interact_cells(_h(plan), loop, _ptr(buf), _nbytes(buf), C.byref(p),
+                                    C.byref(tuning) if tuning else None, _ptr(res), _nbytes(res), _ptr(counts),
+                                    _ptr(ws), _stream(stream)), "sph_interact_cells")
+
+
+def sph_unpack_cells(plan, loop: int, res, store, tuning=None, stream=None):
+    _check(lib().sph_unpack_cells(_h(plan), loop, _ptr(res), _nbytes(res), _s(store),
+                                  C.byref(tuning) if tuning else None, _stream(stream)), "sph_unpack_cells")
+
+
+def sph_step_batched(plan, store, ws, params=None, tuning=None, stream=None):
+    p = params if params is not None else default_params()
+    _check(lib().sph_step_batched(_h(plan), _s(store), C.byref(p), C.byref(tuning) if tuning else None,
+                                  _ptr(ws), _nbytes(ws), _stream(stream)), "sph_step_batched")
+
+
+class Graph:
+    """An executable HIP graph of one batched step."""
+
+    def __init__(self, plan, store, ws, params=None, tuning=None):
+        p = params if params is not None else default_params()
+        out = vp()
+        _check(lib().sph_graph_capture(_h(plan), _s(store), C.byref(p), C.byref(tuning) if tuning else None,
+                                       _ptr(ws), _nbytes(ws), C.byref(out)), "sph_graph_capture")
+        self.ptr = out.value
+        self._keep = (plan, store, ws)
+
+    def launch(self, stream=None):
+        _check(lib().sph_graph_launch(self.ptr, _stream(stream)), "sph_graph_launch")
+
+    def close(self):
+        if self.ptr:
+            lib().sph_graph_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# convenience
+# ---------------------------------------------------------------------------
+def alloc_range_buffers(plan: Plan, loop: int, t0: int, t1: int, device="cuda"):
+    import torch
+    ns, pb, rb = plan.buffer_bytes(loop, t0, t1)
+    pack = torch.empty(max(pb, 256), dtype=torch.uint8, device=device)
+    res = torch.empty(max(rb, 256), dtype=torch.uint8, device=device)
+    return ns, pack, res
+
+
+def cell_buffers(plan: Plan, loop: int, device="cuda"):
+    """Pack / result buffers of the batched form (P = n rounded up to 64)."""
+    import torch
+    info = plan.info()
+    P = (plan.n + 63) // 64 * 64
+    pf, rp = sph_pack_layout(loop)
+    pack = torch.empty(P * 4 * sum(pf) + info.ntile * 32 + 256, dtype=torch.uint8, device=device)
+    res = torch.empty(P * 4 * rp + 256, dtype=torch.uint8, device=device)
+    return pack, res

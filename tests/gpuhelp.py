@@ -1,0 +1,126 @@
+"""Helpers shared by the GPU parity tests: drive the HIP path through the C-ABI
+binding, run the oracle on the same seeded inputs, and compare."""
+from __future__ import annotations
+
+import sys
+import time
+
+import numpy as np
+
+import oracle
+from paper_2606_23891_amd import inputs, sph
+
+LOOP_OUT = {0: ["rho", "rho_dh", "wcount"], 1: ["div_v", "rot_v", "lap_u", "v_sig"], 2: ["a", "u_dt"]}
+
+
+def log(msg: str):
+    print(f"[{time.strftime('%H:%M:%S')}] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def device_store(ps: inputs.ParticleSet, layout: int, extra: dict | None = None) -> sph.Store:
+    st = sph.Store(layout, ps.n)
+    f = dict(ps.fields)
+    if extra:
+        f.update(extra)
+    st.put_all(f)
+    return st
+
+
+def run_per_task(plan: sph.Plan, store: sph.Store, loop: int, ntask: int, bundle: int = 1,
+                 counts: bool = False):
+    """zero -> for each bundle of tasks: pack, interact, unpack.  Returns per-slot
+    counts summed per particle when asked."""
+    import torch
+    sph.sph_zero_outputs(plan, loop, store)
+    cnt_part = np.zeros(plan.n, np.int64) if counts else None
+    for t0 in range(0, ntask, bundle):
+        t1 = min(ntask, t0 + bundle)
+        ns, pack, res = sph.alloc_range_buffers(plan, loop, t0, t1)
+        if ns == 0:
+            continue
+        cbuf = torch.zeros(ns, dtype=torch.int32, device="cuda") if counts else None
+        sph.sph_pack(plan, loop, store, t0, t1, pack)
+        sph.INTERACT[loop](plan, pack, t0, t1, res, counts=cbuf)
+        sph.sph_unpack(plan, loop, res, t0, t1, store)
+        if counts:
+            torch.cuda.synchronize()
+            c = cbuf.cpu().numpy()
+            parts = slot_particles(plan, t0, t1)
+            np.add.at(cnt_part, parts, c)
+    return cnt_part
+
+
+def slot_particles(plan: sph.Plan, t0: int, t1: int) -> np.ndarray:
+    """particle index of every slot of tasks [t0, t1), in slot order"""
+    cells, tasks = plan.cells, plan.tasks
+    out = []
+    for t in range(t0, t1):
+        ci, cj = tasks["ci"][t], tasks["cj"][t]
+        out.append(np.arange(cells["first"][ci], cells["first"][ci] + cells["count"][ci]))
+        if ci != cj:
+            out.append(np.arange(cells["first"][cj], cells["first"][cj] + cells["count"][cj]))
+    return np.concatenate(out) if out else np.zeros(0, np.int64)
+
+
+def run_batched_loop(plan: sph.Plan, store: sph.Store, loop: int, tuning=None, counts: bool = False):
+    import torch
+    pack, res = sph.cell_buffers(plan, loop)
+    ws = torch.zeros(1024, dtype=torch.uint8, device="cuda")
+    cbuf = torch.zeros(plan.n, dtype=torch.int32, device="cuda") if counts else None
+    sph.sph_pack_cells(plan, loop, store, pack, tuning)
+    sph.sph_interact_cells(plan, loop, pack, res, ws, tuning=tuning, counts=cbuf)
+    sph.sph_unpack_cells(plan, loop, res, store, tuning)
+    torch.cuda.synchronize()
+    return cbuf.cpu().numpy() if counts else None
+
+
+def outputs(store: sph.Store, loop: int) -> dict:
+    return {k: store.get(k) for k in LOOP_OUT[loop]}
+
+
+def scaled_error(gpu: np.ndarray, ref: np.ndarray, S: np.ndarray) -> float:
+    """max_i |q_gpu - q_ref| / max(|q_ref|, S_i); where the scale is 0 the GPU
+    value must be exactly 0."""
+    gpu = np.asarray(gpu, np.float64)
+    ref = np.asarray(ref, np.float64)
+    den = np.maximum(np.abs(ref), S)
+    bad = (den == 0) & (gpu != 0)
+    if bad.any():
+        return float("inf")
+    with np.errstate(invalid="ignore", divide="ignore"):
+        e = np.where(den > 0, np.abs(gpu - ref) / np.where(den > 0, den, 1.0), 0.0)
+    return float(e.max()) if e.size else 0.0
+
+
+def oracle_loop(ps_fields: dict, loop: int, prev: dict, rows=None) -> dict:
+    f = ps_fields
+    if loop == 0:
+        return oracle.density(f["x"], f["mass"], f["h"], rows=rows)
+    if loop == 1:
+        return oracle.gradient(f["x"], f["v"], f["mass"], f["h"], f["u"], prev["rho"], rows=rows)
+    return oracle.force(f["x"], f["v"], f["mass"], f["h"], f["u"], prev["rho"], prev["rho_dh"],
+                        prev["div_v"], prev["rot_v"], f["alpha_v"], f["alpha_d"], rows=rows)
+
+
+def compare_loop(loop: int, gpu: dict, ref: dict, rows=None) -> dict:
+    """scaled errors per output (rows: the sampled particles the oracle computed)"""
+    sel = (lambda a: a) if rows is None else (lambda a: a[rows])
+    S = ref["S"]
+    errs = {}
+    if loop == 0:
+        errs["rho"] = scaled_error(sel(gpu["rho"]), ref["rho"], S[:, 0])
+        errs["rho_dh"] = scaled_error(sel(gpu["rho_dh"]), ref["rho_dh"], S[:, 1])
+        errs["wcount"] = scaled_error(sel(gpu["wcount"]), ref["wcount"], S[:, 2])
+    elif loop == 1:
+        errs["div_v"] = scaled_error(sel(gpu["div_v"]), ref["div_v"], S[:, 0])
+        for c in range(3):
+            errs[f"rot_v{c}"] = scaled_error(sel(gpu["rot_v"])[:, c], ref["rot_v"][:, c], S[:, 1 + c])
+        errs["lap_u"] = scaled_error(sel(gpu["lap_u"]), ref["lap_u"], S[:, 4])
+        v = sel(gpu["v_sig"]).astype(np.float64)
+        errs["v_sig"] = float(np.max(np.abs(v - ref["v_sig"]) / np.maximum(ref["v_sig"], 1e-300)))
+    else:
+        for c in range(3):
+            errs[f"a{c}"] = scaled_error(sel(gpu["a"])[:, c], ref["a"][:, c], S[:, c])
+        errs["u_dt"] = scaled_error(sel(gpu["u_dt"]), ref["u_dt"], S[:, 3])
+    return errs

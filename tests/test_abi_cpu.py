@@ -1,0 +1,91 @@
+"""C-ABI checks that need no GPU: exported symbols, the library's layout tables
+against the oracle's independently written ones, and argument validation that
+must fail before anything is enqueued."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_23891_amd import inputs, sph
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "sph.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sph_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = sph.lib()
+    names = declared_functions()
+    assert len(names) >= 30
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) == set(sph._SIGS), set(names) ^ set(sph._SIGS)
+
+
+@pytest.mark.parametrize("layout", range(9))
+def test_layout_tables_match_oracle(layout):
+    assert sph.sph_layout_info(layout) == oracle.layout_info(layout)
+    for name, fid in sph.FIELD_ID.items():
+        nc, cb = sph.sph_field_info(fid)
+        assert (nc, cb) == (oracle.FIELD_TYPES[name][1], np.dtype(oracle.FIELD_TYPES[name][0]).itemsize)
+        for c in range(nc):
+            assert sph.sph_field_location(layout, fid, c) == oracle.field_location(layout, fid, c)
+
+
+def test_pack_record_matches_oracle():
+    for loop in range(3):
+        planes, rp = sph.sph_pack_layout(loop)
+        assert tuple(planes) == oracle.PACK_PLANES[loop]
+        assert rp == oracle.RESULT_PLANES[loop]
+
+
+def _status(name, *args):
+    return getattr(sph.lib(), name)(*args)
+
+
+def test_validation_errors_before_any_launch():
+    L = sph.lib()
+    assert L.sph_status_str(-3).decode() == "buffer too small"
+    # null plan
+    assert _status("sph_pack", None, 0, None, 0, 1, None, 0, None) == -1
+    assert _status("sph_density", None, None, 0, 0, 1, None, None, 0, None, None) == -1
+    # unknown layout / loop
+    nsub = C.c_int32()
+    sb = (C.c_size_t * 32)()
+    assert L.sph_layout_info(9, C.byref(nsub), sb) == -2
+    assert L.sph_pack_layout(3, C.byref(nsub), (C.c_int32 * 5)(), C.byref(nsub)) == -1
+    # plan validation
+    ps = inputs.make_config(0, n_side=8, grid=4)
+    out = C.c_void_p()
+    cells, tasks = ps.cells.copy(), ps.tasks.copy()
+    tasks["cj"][5] = 10 ** 6
+    assert L.sph_plan_create(cells.ctypes.data, cells.size, tasks.ctypes.data, tasks.size, ps.n,
+                             C.byref(out)) == -4
+    assert b"out of range" in L.sph_last_error()
+    tasks = ps.tasks.copy()
+    self_t = np.nonzero(tasks["ci"] == tasks["cj"])[0][0]
+    tasks["shift"][self_t] = [1.0, 0, 0]
+    assert L.sph_plan_create(cells.ctypes.data, cells.size, tasks.ctypes.data, tasks.size, ps.n,
+                             C.byref(out)) == -4
+    cells["count"][3] += 10 ** 6
+    assert L.sph_plan_create(cells.ctypes.data, cells.size, ps.tasks.ctypes.data, ps.tasks.size, ps.n,
+                             C.byref(out)) == -4
+    assert L.sph_plan_create(None, -1, None, 0, 0, C.byref(out)) == -1
+    assert out.value is None
+    # a store whose substruct count does not match its layout
+    st = sph.sph_store()
+    st.layout, st.nsub, st.n = 0, 3, 10
+    assert L.sph_store_put(C.byref(st), 0, C.c_void_p(256), None) == -2
+    st.layout = 42
+    assert L.sph_store_get(C.byref(st), 0, C.c_void_p(256), None) == -2
+    st.layout, st.nsub = 0, 1
+    st.sub[0] = 0x1001  # misaligned
+    assert L.sph_store_put(C.byref(st), 0, C.c_void_p(256), None) == -1
+    assert b"aligned" in L.sph_last_error()

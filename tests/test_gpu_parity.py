@@ -1,0 +1,191 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Pack and unpack: byte equality.  Interaction loops: scaled error
+max |q_gpu - q_ref| / max(|q_ref|, sum |terms|) <= 1e-5 (FP32 GPU vs FP64
+oracle), signal velocity relative <= 1e-5, interaction counts equal.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_23891_amd import inputs, sph
+
+from gpuhelp import (LOOP_OUT, compare_loop, device_store, log, oracle_loop, outputs, run_batched_loop,
+                     run_per_task, slot_particles)
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _small_sets():
+    # uniform 64-per-cell grid, a 512-per-cell grid (multi-tile cells) and an uneven octree
+    return {
+        "lattice8": inputs.make_config(0, n_side=8, grid=4),
+        "grid512": inputs.make_config(2, n_side=32, grid=4),
+        "octree": inputs.make_config(3, n_side=24),
+    }
+
+
+@pytest.fixture(scope="module")
+def sets():
+    return _small_sets()
+
+
+@pytest.mark.parametrize("layout", range(9))
+def test_store_bytes_match_oracle(layout):
+    ps = inputs.make_config(0, n_side=8, grid=4)
+    f = inputs.random_fields(ps.n, 7, x=ps.fields["x"])
+    log(f"store layout={layout}")
+    st = sph.Store(layout, ps.n)
+    st.put_all(f)
+    host = oracle.HostStore(layout, ps.n, fill=0)
+    host.put_all(f)
+    assert st.raw() == host.raw()
+    for k, v in f.items():
+        np.testing.assert_array_equal(st.get(k).reshape(v.shape), v)
+
+
+def _ranges(ntask):
+    return [(0, ntask), (0, 1), (ntask // 2, ntask // 2 + 1), (3, min(ntask, 40)), (ntask - 1, ntask), (5, 5)]
+
+
+@pytest.mark.parametrize("layout", range(9))
+def test_pack_bitexact(sets, layout):
+    import torch
+    for name, ps in sets.items():
+        if name != "octree" and layout not in (0, 8):
+            continue
+        f = inputs.random_fields(ps.n, 11, x=ps.fields["x"])
+        st = sph.Store(layout, ps.n)
+        st.put_all(f)
+        host = oracle.HostStore(layout, ps.n)
+        host.put_all(f)
+        plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+        for loop in range(3):
+            for t0, t1 in _ranges(len(ps.tasks)):
+                log(f"pack {name} layout={layout} loop={loop} range=[{t0},{t1})")
+                ns, pack, res = sph.alloc_range_buffers(plan, loop, t0, t1)
+                pack.zero_()
+                sph.sph_pack(plan, loop, st, t0, t1, pack)
+                torch.cuda.synchronize()
+                ref = oracle.pack(host, loop, ps.cells, ps.tasks, t0, t1)
+                got = pack.cpu().numpy()[: ref.size]
+                assert np.array_equal(got, ref), (name, layout, loop, t0, t1)
+        plan.close()
+
+
+@pytest.mark.parametrize("layout", [0, 1, 4, 7, 8])
+def test_unpack_bitexact(sets, layout):
+    import torch
+    rng = np.random.default_rng(3)
+    for name, ps in sets.items():
+        f = inputs.random_fields(ps.n, 13, x=ps.fields["x"])
+        plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+        nt = len(ps.tasks)
+        for loop in range(3):
+            st = sph.Store(layout, ps.n)
+            st.put_all(f)
+            host = oracle.HostStore(layout, ps.n)
+            host.put_all(f)
+            sph.sph_zero_outputs(plan, loop, st)
+            oracle.zero_outputs(host, loop)
+            for t0, t1 in [(0, 1), (1, 7), (7, nt // 3), (nt // 3, nt), (4, 4)]:
+                log(f"unpack {name} layout={layout} loop={loop} range=[{t0},{t1})")
+                ns, pack, res = sph.alloc_range_buffers(plan, loop, t0, t1)
+                P = oracle.round_slots(ns)
+                r = rng.uniform(-1, 1, (oracle.RESULT_PLANES[loop], P)).astype(np.float32)
+                res[: r.nbytes].copy_(torch.from_numpy(r.view(np.uint8).reshape(-1)))
+                sph.sph_unpack(plan, loop, res, t0, t1, st)
+                oracle.unpack(host, loop, ps.cells, ps.tasks, t0, t1, r)
+            assert st.raw() == host.raw(), (name, layout, loop)
+        plan.close()
+
+
+@pytest.mark.parametrize("layout", [0, 2, 6, 8])
+def test_cells_pack_unpack_bitexact(sets, layout):
+    import torch
+    rng = np.random.default_rng(5)
+    for name, ps in sets.items():
+        f = inputs.random_fields(ps.n, 17, x=ps.fields["x"])
+        plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+        assert plan.info().batched_ok
+        for loop in range(3):
+            log(f"cells pack/unpack {name} layout={layout} loop={loop}")
+            st = sph.Store(layout, ps.n)
+            st.put_all(f)
+            host = oracle.HostStore(layout, ps.n)
+            host.put_all(f)
+            pack, res = sph.cell_buffers(plan, loop)
+            pack.zero_()
+            sph.sph_pack_cells(plan, loop, st, pack)
+            torch.cuda.synchronize()
+            ref = oracle.pack_cells(host, loop, ps.cells)
+            assert np.array_equal(pack.cpu().numpy()[: ref.size], ref)
+            # the cell pack is the self-task pack of every cell, in cell order
+            P = oracle.round_slots(ps.n)
+            r = rng.uniform(-1, 1, (oracle.RESULT_PLANES[loop], P)).astype(np.float32)
+            r[:, :5] = [-0.0, 0.0, 1e-40, -1e-40, 3.0]   # signed zeros and subnormals
+            res[: r.nbytes].copy_(torch.from_numpy(r.view(np.uint8).reshape(-1)))
+            sph.sph_unpack_cells(plan, loop, res, st)
+            oracle.unpack_cells(host, loop, r)
+            assert st.raw() == host.raw()
+        plan.close()
+
+
+def _check_loops(ps, layout, mode, rows=None, bundle=1):
+    """density -> gradient -> force on the GPU; each loop compared with the oracle
+    fed the GPU's own previous-loop outputs (loop isolation)."""
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    st = device_store(ps, layout)
+    prev = {}
+    worst = {}
+    for loop in range(3):
+        log(f"loops {mode} layout={layout} loop={loop} n={ps.n}")
+        if mode == "per_task":
+            cnt = run_per_task(plan, st, loop, len(ps.tasks), bundle=bundle, counts=True)
+        else:
+            cnt = run_batched_loop(plan, st, loop, counts=True)
+        g = outputs(st, loop)
+        ref = oracle_loop(ps.fields, loop, prev, rows=rows)
+        errs = compare_loop(loop, g, ref, rows=rows)
+        worst.update(errs)
+        gc = cnt if rows is None else cnt[rows]
+        assert np.array_equal(gc, ref["count"]), (loop, np.abs(gc - ref["count"]).max())
+        for k in LOOP_OUT[loop]:
+            prev[k] = g[k].astype(np.float64)
+    plan.close()
+    log(f"worst scaled errors: {worst}")
+    for k, e in worst.items():
+        assert e <= TOL, (k, e, worst)
+    return worst
+
+
+@pytest.mark.parametrize("mode", ["per_task", "batched"])
+def test_loops_lattice(mode):
+    ps = inputs.make_config(4, n_side=16)
+    _check_loops(ps, 8, mode)
+
+
+@pytest.mark.parametrize("mode", ["per_task", "batched"])
+def test_loops_multitile_cells(mode):
+    ps = inputs.make_config(2, n_side=32, grid=4)
+    rows = np.random.default_rng(1).choice(ps.n, 2048, replace=False)
+    _check_loops(ps, 0, mode, rows=rows, bundle=64)
+
+
+@pytest.mark.parametrize("mode", ["per_task", "batched"])
+def test_loops_octree_uneven(mode):
+    ps = inputs.make_config(3, n_side=24)
+    _check_loops(ps, 4, mode, bundle=16)
+
+
+def test_density_closed_form_lattice():
+    ps = inputs.make_config(0, jitter=0.0)
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    st = device_store(ps, 0)
+    run_per_task(plan, st, 0, len(ps.tasks))
+    rho = st.get("rho").astype(np.float64)
+    np.testing.assert_allclose(rho, 1.0039807860264176, rtol=1e-5)
+    run_batched_loop(plan, st, 0)
+    np.testing.assert_allclose(st.get("rho").astype(np.float64), 1.0039807860264176, rtol=1e-5)
+    plan.close()

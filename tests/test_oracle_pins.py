@@ -76,6 +76,12 @@ def test_kernel_derivatives_numerical():
         dr = 1e-6 * H
         num_r = (L.or_W(r + dr, h) - L.or_W(r - dr, h)) / (2 * dr) / r
         assert L.or_F(r, h) == pytest.approx(num_r, rel=1e-6, abs=1e-6 * abs(L.or_F(0.0, h)))
+        # derivatives used by the error scale
+        assert L.or_dWdr(r, h) == pytest.approx(num_r * r, rel=1e-6, abs=1e-6 * abs(L.or_F(0.0, h)) * H)
+        num_f = (L.or_F(r + dr, h) - L.or_F(r - dr, h)) / (2 * dr)
+        assert L.or_dFdr(r, h) == pytest.approx(num_f, rel=1e-5, abs=1e-6 * abs(L.or_F(0.0, h)) / H)
+        num_hr = (L.or_dWdh(r + dr, h) - L.or_dWdh(r - dr, h)) / (2 * dr)
+        assert L.or_d2Wdhdr(r, h) == pytest.approx(num_hr, rel=1e-5, abs=1e-6 * abs(L.or_dWdh(0.0, h)) / H)
     assert L.or_F(1.01 * H, h) == 0.0
 
 
