@@ -1,0 +1,302 @@
+"""Benchmark of the SPH pack / interact / unpack hot path on one MI355X.
+
+One step = density -> gradient -> force, each as pack -> interaction ->
+unpack, over the whole synthetic workload (inputs resident in HBM).  The
+timed region runs the batched form stage by stage on one stream with HIP
+events between the stages, so every kernel's average duration is measured
+inside the timed region.  Reported beside it: the same step replayed as one
+captured HIP graph, the per-task form (one launch per task and stage, the
+paper's offload cycle with single-task bundles), and the CPU oracle timed on
+a bounded sample of the same workload.
+
+Prints one JSON line.  Default workload: the 256^3 Gresho-vortex set on a 32^3
+cell grid (16 777 216 particles, 458 752 tasks).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pair interactions/s + pack/unpack GB/s (batched vs per-task, FP32 @1e-5 rel)"
+# FP32 operations the pair body of each loop executes per interacting pair
+# (add, mul, min/max, sqrt, rsqrt, rcp = 1; fma = 2; the candidate test excluded)
+PAIR_FLOPS = {0: 32, 1: 55, 2: 81}
+# algorithmic HBM bytes per particle: fields read from the store + packed record
+# written (+ 32 bytes of tile bounds per 64 particles); unpack: result read +
+# outputs written
+PACK_BYTES = {0: 32 + 20 + 0.5, 1: 52 + 40 + 0.5, 2: 80 + 68 + 0.5}
+UNPACK_BYTES = {0: 12 + 12, 1: 24 + 24, 2: 16 + 16}
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+LOOP_NAME = {0: "density", 1: "gradient", 2: "force"}
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2, help="workload 1..3 (2: 256^3 Gresho)")
+    ap.add_argument("--grid", type=int, default=None, help="cells per side (uniform workloads)")
+    ap.add_argument("--n-side", type=int, default=None)
+    ap.add_argument("--layout", default="SAOS_SHARED")
+    ap.add_argument("--per-task", default="auto", help="auto | full | off | <tasks> (sampled, scaled)")
+    ap.add_argument("--per-task-budget", type=float, default=40.0, help="seconds for the per-task leg")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--tuning", default=None, help="JSON file with sph_tuning fields")
+    return ap.parse_args()
+
+
+def workload_name(k, ps):
+    st = ps.meta
+    kind = {1: "gresho", 2: "gresho", 3: "clustered-octree"}.get(k, f"cfg{k}")
+    g = st.get("grid")
+    cells = f"{g}^3 cells" if g else f"{len(ps.cells)} octree leaves"
+    return f"{kind}-{st['n_side']}^3 ({ps.n} particles), {cells}, {len(ps.tasks)} tasks"
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
+                                   "part of this build (see the design notes on sharding)",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_2606_23891_amd import inputs, sph
+
+    torch.cuda.set_device(0)
+    dev = torch.cuda.get_device_properties(0)
+    t0 = time.time()
+    kw = {}
+    if a.grid:
+        kw["grid"] = a.grid
+    if a.n_side:
+        kw["n_side"] = a.n_side
+    ps = inputs.make_config(a.config, **kw)
+    log(f"workload built in {time.time() - t0:.1f}s: n={ps.n} cells={len(ps.cells)} tasks={len(ps.tasks)}")
+    layout = sph.LAYOUTS.index(a.layout)
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    info = plan.info()
+    store = sph.Store(layout, ps.n)
+    store.put_all(ps.fields)
+    tuning = sph.default_tuning()
+    if a.tuning:
+        cfg = json.load(open(a.tuning))
+        for k, v in cfg.items():
+            if k == "window":
+                for i, w in enumerate(v):
+                    tuning.window[i] = w
+            elif hasattr(tuning, k):
+                setattr(tuning, k, v)
+    params = sph.default_params()
+    stream = torch.cuda.current_stream()
+    bufs = {L: sph.cell_buffers(plan, L) for L in range(3)}
+    ws = torch.zeros(1 << 12, dtype=torch.uint8, device="cuda")
+
+    def stage(L, s):
+        pack, res = bufs[L]
+        if s == 0:
+            sph.sph_pack_cells(plan, L, store, pack, tuning)
+        elif s == 1:
+            sph.sph_interact_cells(plan, L, pack, res, ws, params=params, tuning=tuning)
+        else:
+            sph.sph_unpack_cells(plan, L, res, store, tuning)
+
+    # interaction counts (untimed)
+    pairs = {}
+    cnt = torch.zeros(ps.n, dtype=torch.int32, device="cuda")
+    for L in range(3):
+        pack, res = bufs[L]
+        sph.sph_pack_cells(plan, L, store, pack, tuning)
+        sph.sph_interact_cells(plan, L, pack, res, ws, params=params, tuning=tuning, counts=cnt)
+        sph.sph_unpack_cells(plan, L, res, store, tuning)
+        torch.cuda.synchronize()
+        pairs[L] = int(cnt.to(torch.int64).sum().item())
+    total_pairs = sum(pairs.values())
+    log(f"interacting pairs per step: {pairs}")
+
+    for _ in range(a.warmup):
+        for L in range(3):
+            for s in range(3):
+                stage(L, s)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, events between all 9 stages
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(10)] for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for k in range(a.steps):
+        ev[k][0].record(stream)
+        i = 1
+        for L in range(3):
+            for s in range(3):
+                stage(L, s)
+                ev[k][i].record(stream)
+                i += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    stage_ms = np.zeros(9)
+    step_ms = []
+    for k in range(a.steps):
+        for i in range(9):
+            stage_ms[i] += ev[k][i].elapsed_time(ev[k][i + 1])
+        step_ms.append(ev[k][0].elapsed_time(ev[k][9]))
+    stage_ms /= a.steps
+    ms_per_step = float(np.mean(step_ms))
+    value = total_pairs / (ms_per_step * 1e-3)
+    log(f"batched: {ms_per_step:.3f} ms/step (wall {1e3 * wall / a.steps:.3f}), {value:.3e} pairs/s")
+
+    stages = {}
+    n = ps.n
+    for L in range(3):
+        p_ms, i_ms, u_ms = stage_ms[3 * L:3 * L + 3]
+        stages[f"pack_{LOOP_NAME[L]}"] = {"ms": p_ms, "GB/s": PACK_BYTES[L] * n / (p_ms * 1e-3) / 1e9}
+        stages[f"{LOOP_NAME[L]}"] = {"ms": i_ms, "pairs": pairs[L],
+                                     "TFLOP/s": PAIR_FLOPS[L] * pairs[L] / (i_ms * 1e-3) / 1e12,
+                                     "pairs/s": pairs[L] / (i_ms * 1e-3)}
+        stages[f"unpack_{LOOP_NAME[L]}"] = {"ms": u_ms, "GB/s": UNPACK_BYTES[L] * n / (u_ms * 1e-3) / 1e9}
+    pu_bytes = sum((PACK_BYTES[L] + UNPACK_BYTES[L]) * n for L in range(3))
+    pu_ms = sum(stage_ms[3 * L] + stage_ms[3 * L + 2] for L in range(3))
+    pack_unpack_gbs = pu_bytes / (pu_ms * 1e-3) / 1e9
+
+    # dominant kernel and its roofline
+    names = list(stages)
+    dom = names[int(np.argmax([stages[k]["ms"] for k in names]))]
+    if "GB/s" in stages[dom]:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": stages[dom]["GB/s"], "peak": PEAK_HBM_GBS,
+                "unit": "GB/s"}
+    else:
+        roof = {"kernel": dom, "bound": "alu", "achieved": stages[dom]["TFLOP/s"], "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "pair interactions/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": workload_name(a.config, ps), "layout": a.layout, "form": "batched",
+                   "pairs_per_step": total_pairs, "device": dev.name, "cu": dev.multi_processor_count},
+        "pack_unpack_GBps": pack_unpack_gbs,
+        "stages": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                   for k, v in stages.items()},
+        "roofline": roof,
+    }
+
+    # the same step as one captured graph
+    if not a.no_graph:
+        wsb = torch.zeros(sph.sph_batched_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+        g = sph.Graph(plan, store, wsb, params=params, tuning=tuning)
+        g.launch(stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(a.steps):
+            g.launch(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out["graph_ms_per_step"] = e0.elapsed_time(e1) / a.steps
+        g.close()
+        del wsb
+        log(f"graph: {out['graph_ms_per_step']:.3f} ms/step")
+
+    # the per-task form
+    if a.per_task != "off":
+        ntask = len(ps.tasks)
+        pb, rb = 0, 0
+        for L in range(3):
+            p_, r_ = sph.sph_plan_task_max_bytes(plan, L)
+            pb, rb = max(pb, p_), max(rb, r_)
+        pbuf = torch.empty(pb, dtype=torch.uint8, device="cuda")
+        rbuf = torch.empty(rb, dtype=torch.uint8, device="cuda")
+        # probe the launch rate on a slice, then run all tasks or a scaled sample
+        probe = min(ntask, 2048)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        sph.sph_run_per_task(plan, 0, store, 0, probe, pbuf, rbuf, params=params)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for L in range(3):
+            sph.sph_run_per_task(plan, L, store, 0, probe, pbuf, rbuf, params=params)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        est = e0.elapsed_time(e1) / probe * ntask / 1e3
+        if a.per_task == "full" or (a.per_task == "auto" and est <= a.per_task_budget):
+            nt = ntask
+        elif a.per_task == "auto":
+            nt = max(probe, int(ntask * a.per_task_budget / est))
+        else:
+            nt = min(ntask, int(a.per_task))
+        e0.record(stream)
+        for L in range(3):
+            sph.sph_run_per_task(plan, L, store, 0, nt, pbuf, rbuf, params=params)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pt_ms = e0.elapsed_time(e1) * ntask / nt
+        out["per_task_ms_per_step"] = pt_ms
+        out["per_task_tasks_timed"] = nt
+        out["per_task_scaled"] = nt < ntask
+        out["batched_speedup_vs_per_task"] = pt_ms / ms_per_step
+        log(f"per-task: {pt_ms:.1f} ms/step ({nt}/{ntask} tasks timed)")
+        del pbuf, rbuf
+
+    # the CPU oracle on a bounded sample of the same workload
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(ps, store, a.cpu_seconds)
+
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(ps, store, budget_s):
+    """Oracle (FP64 brute force over all N, OpenMP) on sampled rows, all three
+    loops; unit scaled to interacting pairs per second."""
+    import oracle
+
+    f = ps.fields
+    rho = store.get("rho").astype(np.float64)
+    rdh = store.get("rho_dh").astype(np.float64)
+    D = store.get("div_v").astype(np.float64)
+    R = store.get("rot_v").astype(np.float64)
+    rng = np.random.default_rng(0)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rows = rng.choice(ps.n, 8, replace=False)
+    t0 = time.perf_counter()
+    c = _oracle_rows(oracle, f, rho, rdh, D, R, rows)
+    t1 = time.perf_counter() - t0
+    nrow = int(max(8, min(ps.n, 8 * budget_s / max(t1, 1e-3))))
+    rows = rng.choice(ps.n, nrow, replace=False)
+    t0 = time.perf_counter()
+    c = _oracle_rows(oracle, f, rho, rdh, D, R, rows)
+    dt = time.perf_counter() - t0
+    return {"value": c / dt, "unit": "pair interactions/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nrow} random particles of the workload, density+gradient+force, each summed by "
+                      f"brute force over all {ps.n} particles in FP64 ({dt:.1f} s)",
+            "seconds": dt}
+
+
+def _oracle_rows(oracle, f, rho, rdh, D, R, rows):
+    d = oracle.density(f["x"], f["mass"], f["h"], rows=rows)
+    g = oracle.gradient(f["x"], f["v"], f["mass"], f["h"], f["u"], rho, rows=rows)
+    fo = oracle.force(f["x"], f["v"], f["mass"], f["h"], f["u"], rho, rdh, D, R, f["alpha_v"], f["alpha_d"],
+                      rows=rows)
+    return int(d["count"].sum() + g["count"].sum() + fo["count"].sum())
+
+
+if __name__ == "__main__":
+    main()

@@ -231,6 +231,17 @@ sph_status sph_force(const sph_plan *plan, const void *pack_buf, size_t pack_byt
 sph_status sph_unpack(const sph_plan *plan, sph_loop loop, const void *res_buf, size_t res_bytes,
                       int32_t t0, int32_t t1, const sph_store *store, void *stream);
 
+/* Per-task driver: for every task t in [t0, t1), in order, one pack, one
+ * interaction and one unpack launch over [t, t+1) -- the paper's offload
+ * cycle with one task per bundle -- after zeroing the loop's outputs when
+ * zero_first is set.  pack_buf / res_buf must hold the largest single task. */
+sph_status sph_run_per_task(const sph_plan *plan, sph_loop loop, const sph_store *store, int32_t t0,
+                            int32_t t1, int32_t zero_first, const sph_params *params, void *pack_buf,
+                            size_t pack_bytes, void *res_buf, size_t res_bytes, void *stream);
+/* Bytes of the pack and result buffers of the largest single task. */
+sph_status sph_plan_task_max_bytes(const sph_plan *plan, sph_loop loop, size_t *pack_bytes,
+                                   size_t *result_bytes);
+
 /* ---------------------------------------------------------------------- */
 /* Batched form: all tasks of a step per launch (the paper's bundling of    */
 /* ready tasks, Sec. 2.3, taken to one bundle per step).  Each cell is      */

@@ -60,10 +60,10 @@ def lib():
     for name in ("or_W", "or_dWdh", "or_F", "or_dWdr", "or_d2Wdhdr", "or_dFdr"):
         getattr(L, name).restype = d
         getattr(L, name).argtypes = [d, d]
-    L.or_density.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
-    L.or_gradient.argtypes = [i64, vp, vp, vp, vp, vp, vp, d, d, i64, vp, vp, vp, vp, vp, vp, vp]
-    L.or_force.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, d, d, i64, vp,
-                           vp, vp, vp, vp]
+    L.or_density.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.or_gradient.argtypes = [i64, vp, vp, vp, vp, vp, vp, d, d, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.or_force.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, d, d, i64, vp, vp,
+                           vp, vp, vp, vp, vp, vp]
     L.or_balsara.argtypes = [i64, vp, vp, vp, vp, vp, vp, d, d, vp]
     L.or_layout_info.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(sz)]
     L.or_field_location.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(sz),
@@ -97,22 +97,29 @@ BETA_VISC = 3.0
 BALSARA_EPS = 1e-4
 
 
-def density(x, m, h, rows=None) -> Dict[str, np.ndarray]:
+def _eps(epsx):
+    return None if epsx is None else _c(epsx, np.float64)
+
+
+def density(x, m, h, rows=None, epsx=None) -> Dict[str, np.ndarray]:
+    """FP64 density sums.  S: arithmetic error scale; P: position error scale for
+    the per-particle position resolution epsx (0 when epsx is None); band: pairs
+    whose distance to the support edge is within 1e-6 H + epsx_i + epsx_j."""
     L = lib()
     x = _c(x, np.float64); m = _c(m, np.float32); h = _c(h, np.float32)
     n = x.shape[0]
     rows = None if rows is None else _c(rows, np.int64)
     nr = n if rows is None else rows.size
     out = {k: np.zeros(nr) for k in ("rho", "rho_dh", "wcount")}
-    S = np.zeros((nr, 3)); cnt = np.zeros(nr, np.int32)
-    L.or_density(n, _p(x), _p(m), _p(h), nr, _p(rows), _p(out["rho"]), _p(out["rho_dh"]),
-                 _p(out["wcount"]), _p(S), _p(cnt))
-    out["S"] = S
-    out["count"] = cnt
+    S = np.zeros((nr, 3)); P = np.zeros((nr, 3)); cnt = np.zeros(nr, np.int32); band = np.zeros(nr, np.int32)
+    epsx = _eps(epsx)
+    L.or_density(n, _p(x), _p(m), _p(h), nr, _p(rows), _p(epsx), _p(out["rho"]), _p(out["rho_dh"]),
+                 _p(out["wcount"]), _p(S), _p(P), _p(cnt), _p(band))
+    out.update(S=S, P=P, count=cnt, band=band)
     return out
 
 
-def gradient(x, v, m, h, u, rho, rows=None, gamma=GAMMA_AD, beta=BETA_VISC) -> Dict[str, np.ndarray]:
+def gradient(x, v, m, h, u, rho, rows=None, gamma=GAMMA_AD, beta=BETA_VISC, epsx=None) -> Dict[str, np.ndarray]:
     L = lib()
     x = _c(x, np.float64); v = _c(v, np.float32); m = _c(m, np.float32); h = _c(h, np.float32)
     u = _c(u, np.float32); rho = _c(rho, np.float64)
@@ -120,14 +127,15 @@ def gradient(x, v, m, h, u, rho, rows=None, gamma=GAMMA_AD, beta=BETA_VISC) -> D
     rows = None if rows is None else _c(rows, np.int64)
     nr = n if rows is None else rows.size
     D = np.zeros(nr); R = np.zeros((nr, 3)); Lp = np.zeros(nr); V = np.zeros(nr)
-    S = np.zeros((nr, 5)); cnt = np.zeros(nr, np.int32)
-    L.or_gradient(n, _p(x), _p(v), _p(m), _p(h), _p(u), _p(rho), gamma, beta, nr, _p(rows),
-                  _p(D), _p(R), _p(Lp), _p(V), _p(S), _p(cnt))
-    return {"div_v": D, "rot_v": R, "lap_u": Lp, "v_sig": V, "S": S, "count": cnt}
+    S = np.zeros((nr, 5)); P = np.zeros((nr, 5)); cnt = np.zeros(nr, np.int32); band = np.zeros(nr, np.int32)
+    epsx = _eps(epsx)
+    L.or_gradient(n, _p(x), _p(v), _p(m), _p(h), _p(u), _p(rho), gamma, beta, nr, _p(rows), _p(epsx),
+                  _p(D), _p(R), _p(Lp), _p(V), _p(S), _p(P), _p(cnt), _p(band))
+    return {"div_v": D, "rot_v": R, "lap_u": Lp, "v_sig": V, "S": S, "P": P, "count": cnt, "band": band}
 
 
 def force(x, v, m, h, u, rho, rho_dh, D, R, alpha_v, alpha_d, atilde=None, rows=None,
-          gamma=GAMMA_AD, beta=BETA_VISC, eps=BALSARA_EPS) -> Dict[str, np.ndarray]:
+          gamma=GAMMA_AD, beta=BETA_VISC, eps=BALSARA_EPS, epsx=None) -> Dict[str, np.ndarray]:
     L = lib()
     x = _c(x, np.float64); v = _c(v, np.float32); m = _c(m, np.float32); h = _c(h, np.float32)
     u = _c(u, np.float32); rho = _c(rho, np.float64); rho_dh = _c(rho_dh, np.float64)
@@ -137,11 +145,13 @@ def force(x, v, m, h, u, rho, rho_dh, D, R, alpha_v, alpha_d, atilde=None, rows=
     n = x.shape[0]
     rows = None if rows is None else _c(rows, np.int64)
     nr = n if rows is None else rows.size
-    a = np.zeros((nr, 3)); udt = np.zeros(nr); S = np.zeros((nr, 4)); cnt = np.zeros(nr, np.int32)
+    a = np.zeros((nr, 3)); udt = np.zeros(nr); S = np.zeros((nr, 4)); P = np.zeros((nr, 4))
+    cnt = np.zeros(nr, np.int32); band = np.zeros(nr, np.int32)
+    epsx = _eps(epsx)
     L.or_force(n, _p(x), _p(v), _p(m), _p(h), _p(u), _p(rho), _p(rho_dh), _p(D), _p(R),
-               _p(alpha_v), _p(alpha_d), _p(atilde), gamma, beta, eps, nr, _p(rows),
-               _p(a), _p(udt), _p(S), _p(cnt))
-    return {"a": a, "u_dt": udt, "S": S, "count": cnt}
+               _p(alpha_v), _p(alpha_d), _p(atilde), gamma, beta, eps, nr, _p(rows), _p(epsx),
+               _p(a), _p(udt), _p(S), _p(P), _p(cnt), _p(band))
+    return {"a": a, "u_dt": udt, "S": S, "P": P, "count": cnt, "band": band}
 
 
 def balsara(h, u, rho, D, R, alpha_v, gamma=GAMMA_AD, eps=BALSARA_EPS) -> np.ndarray:
@@ -151,6 +161,13 @@ def balsara(h, u, rho, D, R, alpha_v, gamma=GAMMA_AD, eps=BALSARA_EPS) -> np.nda
     out = np.zeros(h.size)
     L.or_balsara(h.size, _p(h), _p(u), _p(rho), _p(D), _p(R), _p(alpha_v), gamma, eps, _p(out))
     return out
+
+
+def pack_resolution(cells) -> np.ndarray:
+    """Per-particle position resolution of the packed FP32 offsets: 2^-22 times
+    the width of the particle's cell (offsets span at most a few cell widths and
+    are rounded once, plus once more when translated between cell frames)."""
+    return np.repeat(np.asarray(cells["width"], np.float64), np.asarray(cells["count"])) * 2.0 ** -22
 
 
 def full_chain(f: Dict[str, np.ndarray]) -> Dict[str, np.ndarray]:

@@ -115,26 +115,31 @@ static inline double mi(double d)
 /* Density loop: over all j including i with r < H_i                         */
 /*   rho_i = sum m_j W(r, h_i);  rho_dh_i = sum m_j dW/dh(r, h_i);            */
 /*   wcount_i = sum W(r, h_i).                                               */
-/* S holds, per output, the error scale of the sum: for every term, the sum  */
-/* of |elementary products| plus |r| times a bound on |d term / d r_ij|       */
-/* (the first-order condition of the sum under rounding of its inputs).      */
+/* Error scales returned beside every sum (for the parity tolerance):        */
+/*   S: arithmetic scale, per term the sum of |elementary products|;          */
+/*   P: position scale, per term a bound on |d term / d r_ij| times           */
+/*      (epsx_i + epsx_j), the resolution of the packed positions (optional); */
+/*   band: pairs within 1e-6 H + epsx_i + epsx_j of the support edge.         */
 /* ------------------------------------------------------------------------ */
 void or_density(int64_t n, const double *x, const float *m, const float *h,
                 int64_t nrow, const int64_t *rows,
-                double *rho, double *rho_dh, double *wcount, double *S, int32_t *cnt)
+                const double *epsx, double *rho, double *rho_dh, double *wcount, double *S, double *P,
+                int32_t *cnt, int32_t *band)
 {
     int64_t nr = rows ? nrow : n;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < nr; k++) {
         int64_t i = rows ? rows[k] : k;
         double H = OR_GAMMA_K * (double)h[i];
-        double sr = 0, sd = 0, sw = 0, s0 = 0, s1 = 0, s2 = 0;
-        int32_t c = 0;
+        double sr = 0, sd = 0, sw = 0, s0 = 0, s1 = 0, s2 = 0, q0 = 0, q1 = 0, q2 = 0;
+        int32_t c = 0, b = 0;
         for (int64_t j = 0; j < n; j++) {
             double dx = mi(x[3 * i] - x[3 * j]);
             double dy = mi(x[3 * i + 1] - x[3 * j + 1]);
             double dz = mi(x[3 * i + 2] - x[3 * j + 2]);
             double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double ep = epsx ? epsx[i] + epsx[j] : 0.0;
+            if (fabs(r - H) < 1e-6 * H + ep) b++;
             if (!(r < H)) continue;
             double W = or_W(r, h[i]);
             double Wh = or_dWdh(r, h[i]);
@@ -142,15 +147,20 @@ void or_density(int64_t n, const double *x, const float *m, const float *h,
             sr += mj * W;
             sd += mj * Wh;
             sw += W;
-            double Wr = fabs(or_dWdr(r, h[i])) * r;
-            s0 += mj * W + mj * Wr;
-            s1 += fabs(mj * Wh) + mj * fabs(or_d2Wdhdr(r, h[i])) * r;
-            s2 += W + Wr;
+            double Wr = fabs(or_dWdr(r, h[i]));
+            s0 += mj * W;
+            s1 += fabs(mj * Wh);
+            s2 += W;
+            q0 += mj * Wr * ep;
+            q1 += mj * fabs(or_d2Wdhdr(r, h[i])) * ep;
+            q2 += Wr * ep;
             c++;
         }
         rho[k] = sr; rho_dh[k] = sd; wcount[k] = sw;
         if (S) { S[3 * k] = s0; S[3 * k + 1] = s1; S[3 * k + 2] = s2; }
+        if (P) { P[3 * k] = q0; P[3 * k + 1] = q1; P[3 * k + 2] = q2; }
         if (cnt) cnt[k] = c;
+        if (band) band[k] = b;
     }
 }
 
@@ -166,8 +176,9 @@ static double sound_speed(double gam, double u) { return sqrt(gam * (gam - 1.0) 
 /* ------------------------------------------------------------------------ */
 void or_gradient(int64_t n, const double *x, const float *v, const float *m, const float *h,
                  const float *u, const double *rhoj, double gam, double beta,
-                 int64_t nrow, const int64_t *rows,
-                 double *D, double *R, double *L, double *V, double *S, int32_t *cnt)
+                 int64_t nrow, const int64_t *rows, const double *epsx,
+                 double *D, double *R, double *L, double *V, double *S, double *P, int32_t *cnt,
+                 int32_t *band)
 {
     int64_t nr = rows ? nrow : n;
 #pragma omp parallel for schedule(dynamic, 16)
@@ -177,13 +188,16 @@ void or_gradient(int64_t n, const double *x, const float *v, const float *m, con
         double ci = sound_speed(gam, u[i]);
         double d = 0, r0 = 0, r1 = 0, r2 = 0, l = 0, vmax = 0;
         double ad = 0, ar0 = 0, ar1 = 0, ar2 = 0, al = 0;
-        int32_t c = 0;
+        double pd = 0, pr0 = 0, pr1 = 0, pr2 = 0, pl = 0;
+        int32_t c = 0, b = 0;
         for (int64_t j = 0; j < n; j++) {
             if (j == i) continue;
             double rx = mi(x[3 * i] - x[3 * j]);
             double ry = mi(x[3 * i + 1] - x[3 * j + 1]);
             double rz = mi(x[3 * i + 2] - x[3 * j + 2]);
             double r = sqrt(rx * rx + ry * ry + rz * rz);
+            double ep = epsx ? epsx[i] + epsx[j] : 0.0;
+            if (fabs(r - H) < 1e-6 * H + ep) b++;
             if (!(r < H)) continue;
             double F = or_F(r, h[i]);
             double gx = F * rx, gy = F * ry, gz = F * rz; /* grad_i W(r_ij, h_i) */
@@ -197,15 +211,20 @@ void or_gradient(int64_t n, const double *x, const float *v, const float *m, con
             double t2 = mj * (vx * gy - vy * gx);
             double tl = 2.0 * (mj / rhoj[j]) * ((double)u[i] - (double)u[j]) * F;
             d += td; r0 += t0; r1 += t1; r2 += t2; l += tl;
-            /* error scale: componentwise products + r |d/dr_ij| bound */
-            double aF = fabs(F), aFp = fabs(or_dFdr(r, h[i])) * r;
+            /* scales: componentwise products; gradient-norm bounds times ep */
+            double aF = fabs(F), aFp = fabs(or_dFdr(r, h[i]));
             double vn = sqrt(vx * vx + vy * vy + vz * vz);
             double vrr = fabs(vx * rx + vy * ry + vz * rz);
-            ad += mj * aF * (fabs(vx * rx) + fabs(vy * ry) + fabs(vz * rz)) + mj * (aFp * vrr + aF * r * vn);
-            ar0 += mj * aF * (fabs(vy * rz) + fabs(vz * ry)) + mj * (aFp * fabs(vy * rz - vz * ry) + aF * r * vn);
-            ar1 += mj * aF * (fabs(vz * rx) + fabs(vx * rz)) + mj * (aFp * fabs(vz * rx - vx * rz) + aF * r * vn);
-            ar2 += mj * aF * (fabs(vx * ry) + fabs(vy * rx)) + mj * (aFp * fabs(vx * ry - vy * rx) + aF * r * vn);
-            al += fabs(tl) + 2.0 * (mj / rhoj[j]) * fabs((double)u[i] - (double)u[j]) * aFp;
+            ad += mj * aF * (fabs(vx * rx) + fabs(vy * ry) + fabs(vz * rz));
+            ar0 += mj * aF * (fabs(vy * rz) + fabs(vz * ry));
+            ar1 += mj * aF * (fabs(vz * rx) + fabs(vx * rz));
+            ar2 += mj * aF * (fabs(vx * ry) + fabs(vy * rx));
+            al += fabs(tl);
+            pd += mj * (aFp * vrr + aF * vn) * ep;
+            pr0 += mj * (aFp * fabs(vy * rz - vz * ry) + aF * vn) * ep;
+            pr1 += mj * (aFp * fabs(vz * rx - vx * rz) + aF * vn) * ep;
+            pr2 += mj * (aFp * fabs(vx * ry - vy * rx) + aF * vn) * ep;
+            pl += 2.0 * (mj / rhoj[j]) * fabs((double)u[i] - (double)u[j]) * aFp * ep;
             double vr = (r > 0) ? (vx * rx + vy * ry + vz * rz) / r : 0.0;
             double mu = vr < 0 ? vr : 0.0;
             double sig = ci + sound_speed(gam, u[j]) - beta * mu;
@@ -214,7 +233,9 @@ void or_gradient(int64_t n, const double *x, const float *v, const float *m, con
         }
         D[k] = d; R[3 * k] = r0; R[3 * k + 1] = r1; R[3 * k + 2] = r2; L[k] = l; V[k] = vmax;
         if (S) { S[5 * k] = ad; S[5 * k + 1] = ar0; S[5 * k + 2] = ar1; S[5 * k + 3] = ar2; S[5 * k + 4] = al; }
+        if (P) { P[5 * k] = pd; P[5 * k + 1] = pr0; P[5 * k + 2] = pr1; P[5 * k + 3] = pr2; P[5 * k + 4] = pl; }
         if (cnt) cnt[k] = c;
+        if (band) band[k] = b;
     }
 }
 
@@ -276,8 +297,8 @@ void or_balsara(int64_t n, const float *h, const float *u, const double *rho, co
 void or_force(int64_t n, const double *x, const float *v, const float *m, const float *h,
               const float *u, const double *rho, const double *rho_dh, const double *D,
               const double *R, const float *alpha_v, const float *alpha_d, const double *atilde,
-              double gam, double beta, double eps, int64_t nrow, const int64_t *rows,
-              double *acc, double *udt, double *S, int32_t *cnt)
+              double gam, double beta, double eps, int64_t nrow, const int64_t *rows, const double *epsx,
+              double *acc, double *udt, double *S, double *P, int32_t *cnt, int32_t *band)
 {
     int64_t nr = rows ? nrow : n;
     or_pp *pp = (or_pp *)malloc(sizeof(or_pp) * (size_t)n);
@@ -289,8 +310,8 @@ void or_force(int64_t n, const double *x, const float *v, const float *m, const 
         int64_t i = rows ? rows[k] : k;
         or_pp pi = pp[i];
         double a0 = 0, a1 = 0, a2 = 0, du = 0;
-        double s0 = 0, s1 = 0, s2 = 0, sd = 0;
-        int32_t c = 0;
+        double s0 = 0, s1 = 0, s2 = 0, sd = 0, q0 = 0, q1 = 0, q2 = 0, qd = 0;
+        int32_t c = 0, b = 0;
         for (int64_t j = 0; j < n; j++) {
             if (j == i) continue;
             or_pp pj = pp[j];
@@ -299,6 +320,8 @@ void or_force(int64_t n, const double *x, const float *v, const float *m, const 
             double rz = mi(x[3 * i + 2] - x[3 * j + 2]);
             double r = sqrt(rx * rx + ry * ry + rz * rz);
             double Hmax = pi.H > pj.H ? pi.H : pj.H;
+            double ep = epsx ? epsx[i] + epsx[j] : 0.0;
+            if (fabs(r - Hmax) < 1e-6 * Hmax + ep) b++;
             if (!(r < Hmax)) continue;
             double Fi = (r < pi.H) ? or_F(r, h[i]) : 0.0;
             double Fj = (r < pj.H) ? or_F(r, h[j]) : 0.0;
@@ -328,28 +351,34 @@ void or_force(int64_t n, const double *x, const float *v, const float *m, const 
             double e2 = mj * 0.5 * (pi.ad + pj.ad) * fabs(vr) * (pi.u - pj.u) *
                         (ex * Gbx + ey * Gby + ez * Gbz) / rhobar;
             du += e0 + e1 + e2;
-            /* error scale: |elementary products| + r |d/dr_ij| bounds */
+            /* scales: |elementary products|; gradient-norm bounds times ep */
             double Fip = (r < pi.H) ? fabs(or_dFdr(r, h[i])) : 0.0;
             double Fjp = (r < pj.H) ? fabs(or_dFdr(r, h[j])) : 0.0;
             double X = fabs(pi.A * Fi) + fabs(pj.A * Fj) + fabs(Pi * Fbar);
             double Xp = fabs(pi.A) * Fip + fabs(pj.A) * Fjp + fabs(Pi) * 0.5 * (Fip + Fjp);
             double vn = sqrt(vx * vx + vy * vy + vz * vz);
             double dPi = 0.5 * aij * (pi.c + pj.c + 2.0 * beta * fabs(mu)) / rhobar; /* |dPi/dmu| */
-            double rs = Xp * r + fabs(Fbar) * dPi * vn;                            /* r |grad s| */
-            s0 += mj * (X * fabs(rx) + rs * fabs(rx) + X * r);
-            s1 += mj * (X * fabs(ry) + rs * fabs(ry) + X * r);
-            s2 += mj * (X * fabs(rz) + rs * fabs(rz) + X * r);
+            double gs = Xp + (r > 0 ? fabs(Fbar) * dPi * vn / r : 0.0);             /* |grad s| */
+            s0 += mj * X * fabs(rx);
+            s1 += mj * X * fabs(ry);
+            s2 += mj * X * fabs(rz);
+            q0 += mj * (gs * fabs(rx) + X) * ep;
+            q1 += mj * (gs * fabs(ry) + X) * ep;
+            q2 += mj * (gs * fabs(rz) + X) * ep;
             double cvr = fabs(vx * rx) + fabs(vy * ry) + fabs(vz * rz), dvr = fabs(vx * rx + vy * ry + vz * rz);
             double Fbp = 0.5 * (Fip + Fjp), adb = 0.5 * (pi.ad + pj.ad), du_ = fabs(pi.u - pj.u);
-            sd += mj * fabs(pi.A * Fi) * cvr + mj * fabs(pi.A) * (Fip * r * dvr + fabs(Fi) * r * vn);
-            sd += 0.5 * mj * (fabs(Pi * Fbar) * cvr + fabs(Pi) * (Fbp * r * dvr + fabs(Fbar) * r * vn) +
-                              fabs(Fbar) * dvr * dPi * vn);
-            sd += mj * adb * du_ / rhobar * (fabs(Fbar) * cvr + Fbp * r * dvr + fabs(Fbar) * r * vn);
+            sd += mj * fabs(pi.A * Fi) * cvr + 0.5 * mj * fabs(Pi * Fbar) * cvr +
+                  mj * adb * du_ / rhobar * fabs(Fbar) * cvr;
+            qd += (mj * fabs(pi.A) * (Fip * dvr + fabs(Fi) * vn) +
+                   0.5 * mj * (fabs(Pi) * (Fbp * dvr + fabs(Fbar) * vn) + (r > 0 ? fabs(Fbar) * dvr * dPi * vn / r : 0.0)) +
+                   mj * adb * du_ / rhobar * (Fbp * dvr + fabs(Fbar) * vn)) * ep;
             c++;
         }
         acc[3 * k] = a0; acc[3 * k + 1] = a1; acc[3 * k + 2] = a2; udt[k] = du;
         if (S) { S[4 * k] = s0; S[4 * k + 1] = s1; S[4 * k + 2] = s2; S[4 * k + 3] = sd; }
+        if (P) { P[4 * k] = q0; P[4 * k + 1] = q1; P[4 * k + 2] = q2; P[4 * k + 3] = qd; }
         if (cnt) cnt[k] = c;
+        if (band) band[k] = b;
     }
     free(pp);
 }

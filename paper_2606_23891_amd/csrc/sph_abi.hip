@@ -576,6 +576,53 @@ sph_status sph_unpack(const sph_plan *p, sph_loop loop, const void *res_buf, siz
     return launch_unpack(mp, loop, res_buf, false, t0, t1, store, 4, (hipStream_t)stream);
 }
 
+sph_status sph_plan_task_max_bytes(const sph_plan *p, sph_loop loop, size_t *pack_bytes, size_t *result_bytes)
+{
+    if (!p || !pack_bytes || !result_bytes) return fail(SPH_E_ARG, "null argument");
+    sph_status s;
+    if ((s = check_loop(loop))) return s;
+    size_t pb = 0, rb = 0;
+    for (int32_t t = 0; t < p->ntask; ++t) {
+        const int64_t ns = p->slot_off[t + 1] - p->slot_off[t];
+        const int64_t nc = p->chunk_off[t + 1] - p->chunk_off[t];
+        pb = std::max(pb, pack_bytes_for(loop, ns, nc));
+        rb = std::max(rb, result_bytes_for(loop, ns));
+    }
+    *pack_bytes = pb;
+    *result_bytes = rb;
+    return SPH_OK;
+}
+
+sph_status sph_run_per_task(const sph_plan *p, sph_loop loop, const sph_store *store, int32_t t0, int32_t t1,
+                            int32_t zero_first, const sph_params *prm, void *pack_buf, size_t pack_bytes,
+                            void *res_buf, size_t res_bytes, void *stream)
+{
+    if (!p) return fail(SPH_E_ARG, "plan is null");
+    sph_status s;
+    if ((s = check_loop(loop)) || (s = check_store(store)) || (s = check_range(p, t0, t1))) return s;
+    if (!prm) return fail(SPH_E_ARG, "params is null");
+    if (store->n != p->n) return fail(SPH_E_ARG, "store size differs from the plan's");
+    if (!pack_buf || !res_buf || !aligned256(pack_buf) || !aligned256(res_buf))
+        return fail(SPH_E_ARG, "buffer null or not 256-byte aligned");
+    for (int32_t t = t0; t < t1; ++t) {
+        const int64_t ns = p->slot_off[t + 1] - p->slot_off[t];
+        if (pack_bytes < pack_bytes_for(loop, ns, p->chunk_off[t + 1] - p->chunk_off[t]) ||
+            res_bytes < result_bytes_for(loop, ns))
+            return fail(SPH_E_CAPACITY, "buffers smaller than task " + std::to_string(t));
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (zero_first && (s = launch_zero(p, loop, store, st))) return s;
+    sph_plan *mp = const_cast<sph_plan *>(p);
+    for (int32_t t = t0; t < t1; ++t) {
+        if (p->slot_off[t + 1] == p->slot_off[t]) continue;
+        if ((s = launch_pack(p, loop, store, false, t, t + 1, pack_buf, 4, st))) return s;
+        if ((s = launch_interact(p, loop, false, t, t + 1, pack_buf, prm, nullptr, res_buf, nullptr, nullptr, st)))
+            return s;
+        if ((s = launch_unpack(mp, loop, res_buf, false, t, t + 1, store, 4, st))) return s;
+    }
+    return SPH_OK;
+}
+
 // ---------------------------------------------------------------------------
 // batched form
 // ---------------------------------------------------------------------------

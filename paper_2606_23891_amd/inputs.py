@@ -185,8 +185,10 @@ def clustered_set(n_side: int = 188, seed: int = 4, n_clumps: int = 256, a0: flo
     v = rng.normal(0.0, 0.05, (n, 3))
     v[n_bg:] += bulk[cid]
     tree = cKDTree(x, boxsize=1.0)
-    dist, _ = tree.query(x, k=49, workers=workers)
-    r48 = dist[:, 48]
+    dist, _ = tree.query(x, k=50, workers=workers)
+    # support radius midway between the 48th and 49th neighbour (index 0 is
+    # the particle itself), so no neighbour sits on the support edge
+    r48 = 0.5 * (dist[:, 48] + dist[:, 49])
     h = r48 / SUPPORT_PER_H
     h = np.maximum(h, h.max() / h_span)
     m = 1.0 / n
@@ -375,7 +377,11 @@ def make_config(k: int, *, jitter: float = 0.1, grid: Optional[int] = None,
     elif k == 3:
         ns = n_side or 188
         f = clustered_set(ns, seed)
-        f, cells, tasks = octree(f, top=32 if ns >= 64 else 8)
+        hsup = SUPPORT_PER_H * float(f["h"].max())
+        top = 32
+        while top > 1 and hsup >= 1.0 / top:
+            top //= 2
+        f, cells, tasks = octree(f, top=top)
         return ParticleSet(f, cells, tasks, {"config": k, "n_side": ns})
     else:
         raise ValueError(k)

@@ -78,6 +78,8 @@ _SIGS = {
     "sph_gradient": ([vp, vp, sz, i32, i32, vp, vp, sz, vp, vp], i32),
     "sph_force": ([vp, vp, sz, i32, i32, vp, vp, sz, vp, vp], i32),
     "sph_unpack": ([vp, i32, vp, sz, i32, i32, vp, vp], i32),
+    "sph_run_per_task": ([vp, i32, vp, i32, i32, i32, vp, vp, sz, vp, sz, vp], i32),
+    "sph_plan_task_max_bytes": ([vp, i32, C.POINTER(sz), C.POINTER(sz)], i32),
     "sph_tuning_default": ([vp], None),
     "sph_batched_ws_bytes": ([vp, C.POINTER(sz)], i32),
     "sph_pack_cells": ([vp, i32, vp, vp, sz, vp, vp], i32),
@@ -326,6 +328,20 @@ INTERACT = {DENSITY: sph_density, GRADIENT: sph_gradient, FORCE: sph_force}
 def sph_unpack(plan, loop: int, res, t0: int, t1: int, store, stream=None):
     _check(lib().sph_unpack(_h(plan), loop, _ptr(res), _nbytes(res), t0, t1, _s(store), _stream(stream)),
            "sph_unpack")
+
+
+def sph_plan_task_max_bytes(plan, loop: int):
+    pb, rb = sz(), sz()
+    _check(lib().sph_plan_task_max_bytes(_h(plan), loop, C.byref(pb), C.byref(rb)), "sph_plan_task_max_bytes")
+    return pb.value, rb.value
+
+
+def sph_run_per_task(plan, loop: int, store, t0: int, t1: int, pack, res, zero_first=True, params=None,
+                     stream=None):
+    p = params if params is not None else default_params()
+    _check(lib().sph_run_per_task(_h(plan), loop, _s(store), t0, t1, 1 if zero_first else 0, C.byref(p),
+                                  _ptr(pack), _nbytes(pack), _ptr(res), _nbytes(res), _stream(stream)),
+           "sph_run_per_task")
 
 
 def sph_batched_ws_bytes(plan) -> int:

@@ -146,11 +146,13 @@ def _check_loops(ps, layout, mode, rows=None, bundle=1):
         else:
             cnt = run_batched_loop(plan, st, loop, counts=True)
         g = outputs(st, loop)
-        ref = oracle_loop(ps.fields, loop, prev, rows=rows)
+        ref = oracle_loop(ps.fields, loop, prev, rows=rows, epsx=oracle.pack_resolution(ps.cells))
         errs = compare_loop(loop, g, ref, rows=rows)
         worst.update(errs)
         gc = cnt if rows is None else cnt[rows]
-        assert np.array_equal(gc, ref["count"]), (loop, np.abs(gc - ref["count"]).max())
+        # counts agree except for pairs within 1e-6 H of the support edge
+        dc = np.abs(gc.astype(np.int64) - ref["count"])
+        assert np.all(dc <= ref["band"]), (loop, dc.max(), int((dc > ref["band"]).sum()))
         for k in LOOP_OUT[loop]:
             prev[k] = g[k].astype(np.float64)
     plan.close()
