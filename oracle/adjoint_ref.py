@@ -113,6 +113,28 @@ def local_loss(f, atilde, rho, rdh, k, rows_d, rows_f):
     return float((fo["a"] ** 2).sum())
 
 
+def straddles_kink(f: dict, kind: str, k: int, comp: int, rel_eps=1e-6) -> bool:
+    """whether the +-eps step of a coordinate flips the sign of v_kj . r_kj for
+    some neighbour pair (where the viscosity switches on and L has a kink)"""
+    if kind == "m":
+        return False
+    H = GK * f["h"].astype(np.float64)
+    js = _near(f["x"], k, float(H.max()) * 1.01 + 1e-5)
+    signs = []
+    for sgn in (+1.0, -1.0):
+        x = f["x"][js].copy()
+        v = f["v"][js].astype(np.float64).copy()
+        kk = int(np.nonzero(js == k)[0][0])
+        if kind == "x":
+            x[kk, comp] += sgn * rel_eps
+        else:
+            v[kk, comp] += sgn * rel_eps * max(1.0, abs(float(v[kk, comp])))
+        d = x[kk] - x
+        d -= np.round(d)
+        signs.append(np.sign(((v[kk] - v) * d).sum(1)))
+    return bool(np.any(signs[0] != signs[1]))
+
+
 def fd_gradient(f: dict, atilde: np.ndarray, coords, rel_eps=1e-6):
     """central differences of L for (kind, particle, component) coordinates;
     kind in {"x", "v", "m"}; eps = 1e-6 for x, 1e-6 max(1, |v|) for v, 1e-6 m_k for m"""
@@ -123,20 +145,22 @@ def fd_gradient(f: dict, atilde: np.ndarray, coords, rel_eps=1e-6):
     for kind, k, comp in coords:
         rows_d = _near(f["x"], k, Hm * 1.01 + 1e-5)
         rows_f = _near(f["x"], k, 3.0 * Hm * 1.01 + 1e-5)
-        vals = []
+        vals, at = [], []
         for sgn in (+1.0, -1.0):
             g = {kk: vv.copy() for kk, vv in f.items()}
+            # v and m enter the oracle as float32: step by the float32 value
+            # actually stored, and divide by the step actually taken
             if kind == "x":
-                eps = rel_eps
-                g["x"][k, comp] += sgn * eps
+                g["x"][k, comp] += sgn * rel_eps
+                at.append(g["x"][k, comp])
             elif kind == "v":
                 eps = rel_eps * max(1.0, abs(float(f["v"][k, comp])))
-                g["v"] = g["v"].astype(np.float64)
-                g["v"][k, comp] += sgn * eps
+                g["v"][k, comp] = np.float32(float(f["v"][k, comp]) + sgn * eps)
+                at.append(float(g["v"][k, comp]))
             else:
                 eps = rel_eps * float(f["mass"][k])
-                g["mass"] = g["mass"].astype(np.float64)
-                g["mass"][k] += sgn * eps
+                g["mass"][k] = np.float32(float(f["mass"][k]) + sgn * eps)
+                at.append(float(g["mass"][k]))
             vals.append(local_loss(g, atilde, base["rho"], base["rho_dh"], k, rows_d, rows_f))
-        out.append((vals[0] - vals[1]) / (2.0 * eps))
+        out.append((vals[0] - vals[1]) / (at[0] - at[1]))
     return np.array(out)
