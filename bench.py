@@ -58,7 +58,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--tuning", default=None, help="JSON file with sph_tuning fields")
+    ap.add_argument("--tuning", default="auto",
+                    help="auto (the tuner's cache for this device and workload, else defaults), "
+                         "default, or a JSON file with sph_tuning fields")
     return ap.parse_args()
 
 
@@ -96,15 +98,20 @@ def main():
     info = plan.info()
     store = sph.Store(layout, ps.n)
     store.put_all(ps.fields)
+    from paper_2606_23891_amd import tune
+
     tuning = sph.default_tuning()
-    if a.tuning:
-        cfg = json.load(open(a.tuning))
-        for k, v in cfg.items():
-            if k == "window":
-                for i, w in enumerate(v):
-                    tuning.window[i] = w
-            elif hasattr(tuning, k):
-                setattr(tuning, k, v)
+    tuned_from = "defaults"
+    if a.tuning == "auto":
+        entry = tune.load(dev.name, tune.signature(ps, a.layout))
+        if entry:
+            tune.apply(tuning, entry)
+            tuned_from = "tuning cache"
+    elif a.tuning != "default":
+        tune.apply(tuning, json.load(open(a.tuning)))
+        tuned_from = a.tuning
+    log(f"tuning ({tuned_from}): blocks/CU {tuning.blocks_per_cu} windows {list(tuning.window)} "
+        f"queue {tuning.queue} pack waves {tuning.pack_waves}")
     params = sph.default_params()
     stream = torch.cuda.current_stream()
     bufs = {L: sph.cell_buffers(plan, L) for L in range(3)}
@@ -193,7 +200,10 @@ def main():
         "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": workload_name(a.config, ps), "layout": a.layout, "form": "batched",
-                   "pairs_per_step": total_pairs, "device": dev.name, "cu": dev.multi_processor_count},
+                   "pairs_per_step": total_pairs, "device": dev.name, "cu": dev.multi_processor_count,
+                   "tuning": {"source": tuned_from, "blocks_per_cu": tuning.blocks_per_cu,
+                              "window": list(tuning.window), "queue": tuning.queue,
+                              "pack_waves": tuning.pack_waves}},
         "pack_unpack_GBps": pack_unpack_gbs,
         "stages": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                    for k, v in stages.items()},

@@ -384,6 +384,8 @@ sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task 
     std::vector<int32_t> nbr_off(ncell + 1, 0);
     std::vector<Nbr> nbr;
     std::vector<int32_t> items;
+    std::vector<int32_t> jt_off(ncell + 1, 0);
+    std::vector<JTile> jt;
     if (ok) {
         for (int32_t c = 0; c < ncell; ++c) {
             cr[c].first = cells[c].first;
@@ -422,6 +424,15 @@ sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task 
                                      (float)(a.loc[2] - k.shift[2] - b.loc[2])};
         }
         for (int32_t c = 0; c < ncell; ++c) p->max_nbr = std::max(p->max_nbr, deg[c]);
+        // flattened j-tile lists: every tile of every neighbour entry, in entry order
+        for (int32_t c = 0; c < ncell; ++c) {
+            for (int32_t e = nbr_off[c]; e < nbr_off[c + 1]; ++e) {
+                const int32_t nc = nbr[e].cell;
+                for (int32_t t = 0; t < (cells[nc].count + 63) / 64; ++t) jt.push_back(JTile{cr[nc].tile0 + t, e});
+            }
+            jt_off[c + 1] = (int32_t)jt.size();
+            p->max_jt = std::max(p->max_jt, jt_off[c + 1] - jt_off[c]);
+        }
         // work items: tiles by descending candidate count (longest first)
         std::vector<int64_t> cost(tiles.size());
         for (size_t i = 0; i < tiles.size(); ++i) {
@@ -448,7 +459,8 @@ sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task 
         p->num_cu = ncu;
     if ((st = upload(&p->d_cells, p->cells)) || (st = upload(&p->d_tasks, p->tasks)) ||
         (st = upload(&p->d_chunks, ch)) || (st = upload(&p->d_tiles, tiles)) || (st = upload(&p->d_cellr, cr)) ||
-        (st = upload(&p->d_nbr, nbr)) || (st = upload(&p->d_nbr_off, nbr_off)) || (st = upload(&p->d_items, items))) {
+        (st = upload(&p->d_nbr, nbr)) || (st = upload(&p->d_nbr_off, nbr_off)) || (st = upload(&p->d_items, items)) ||
+        (st = upload(&p->d_jt_off, jt_off)) || (st = upload(&p->d_jt, jt))) {
         sph_plan_destroy(p);
         return st;
     }
@@ -461,7 +473,7 @@ void sph_plan_destroy(sph_plan *p)
     if (!p) return;
     (void)hipSetDevice(p->device);
     void *ptrs[] = {p->d_cells, p->d_tasks, p->d_chunks, p->d_tiles, p->d_cellr, p->d_nbr,
-                    p->d_nbr_off, p->d_items, p->d_csr_off, p->d_csr};
+                    p->d_nbr_off, p->d_items, p->d_jt_off, p->d_jt, p->d_csr_off, p->d_csr};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;

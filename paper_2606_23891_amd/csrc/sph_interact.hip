@@ -4,13 +4,15 @@
 // Mapping on gfx950.  One wave64 owns an i-tile: up to 64 consecutive packed
 // particles of one cell, one per lane.  It walks the j-tiles of the partner
 // cell(s) in three steps:
-//   1. tile cull -- a j-tile whose bounding box (written by the pack kernel)
-//      lies beyond the i-tile's reach is skipped whole;
-//   2. stage -- lane k loads j-particle k of a surviving tile, drops it when
-//      it is beyond reach of the i-tile's box, and the survivors are compacted
-//      (ballot + mbcnt) into an LDS candidate window together with the
-//      per-particle quantities the pair term needs (sound speed, A = P/(Omega
-//      rho^2), Balsara-limited viscosity, ...), computed once per candidate;
+//   1. tile cull -- lane k tests j-tile k of the item's j-tile list against
+//      the i-tile's box (tile boxes are written by the pack kernel), so one
+//      ballot culls 64 tiles with one round trip to memory;
+//   2. stage -- for each surviving tile lane k holds j-particle k (the next
+//      tile's records are already in flight), drops it when it is beyond
+//      reach of the i-tile's box, and the survivors are compacted (ballot +
+//      mbcnt) into an LDS candidate window together with the per-particle
+//      quantities the pair term needs (sound speed, A = P/(Omega rho^2),
+//      Balsara-limited viscosity, ...), computed once per candidate;
 //   3. when the window is full (or the tile list ends) every lane tests every
 //      candidate (broadcast LDS reads, ~8 VALU each) and records the hits as
 //      bits; then each lane walks only its own set bits and evaluates the pair
@@ -46,6 +48,8 @@ struct InteractArgs {
     const CellRange *cellr;
     const Nbr *nbr;
     const int32_t *nbr_off;
+    const int32_t *jt_off;      // MODE 1: per cell j-tile list
+    const JTile *jt;
     int32_t *queue;
     int32_t use_queue;
     float gam, beta, eps;
@@ -94,40 +98,57 @@ __device__ __forceinline__ float spline_f(float q, float H_over_r)
 // ---------------------------------------------------------------------------
 // per-loop data: i registers, LDS candidate window, pair terms
 // ---------------------------------------------------------------------------
+// LDS candidate window of one wave.  ph holds, per candidate, the position
+// relative to the i-tile centre and -|x|^2 (the phase-1 test reads only ph,
+// plus H^2 for the force loop); the other planes feed the pair term.
 template <int LOOP, int WIN>
 struct Lds;
 
 template <int WIN>
 struct Lds<0, WIN> {
-    float4 c0[WIN];  // x y z m
+    float4 ph[WIN];  // x y z -|x|^2
+    float m[WIN];
     int32_t jslot[WIN];
     uint32_t mask[WIN / 32][64];
 };
 template <int WIN>
 struct Lds<1, WIN> {
-    float4 c0[WIN];  // x y z m
-    float4 c1[WIN];  // vx vy vz c
-    float2 c2[WIN];  // u m/rho
+    float4 ph[WIN];  // x y z -|x|^2
+    float4 c1[WIN];  // vx vy vz m
+    float4 c2[WIN];  // u m/rho c -
     int32_t jslot[WIN];
     uint32_t mask[WIN / 32][64];
 };
 template <int WIN>
 struct Lds<2, WIN> {
-    float4 c0[WIN];  // x y z H^2
+    float4 ph[WIN];  // x y z -|x|^2
     float4 c1[WIN];  // vx vy vz m
     float4 c2[WIN];  // H 1/H A c
     float4 c3[WIN];  // K5 alpha~ alpha_d rho
-    float c4[WIN];   // u
+    float2 c4[WIN];  // u H^2
     int32_t jslot[WIN];
     uint32_t mask[WIN / 32][64];
 };
 
 struct IData {
-    float x, y, z, H, H2, invH;
+    float x, y, z, H, H2, invH;    // position relative to the i-tile centre
     float vx, vy, vz, u, c;
     float K5, A, at, ad, rho;
+    float nx2, ny2, nz2;            // -2 x, -2 y, -2 z (phase-1 test)
+    float t0;                       // |x|^2 - delta - H^2 (density, gradient) or |x|^2 - delta (force)
+    float ri, xi2;                  // |x| and |x|^2
+    float rj;                       // bound on |x_j| of staged candidates (tile centre frame)
     int32_t slot;
 };
+
+// Rounding bound of the phase-1 test: every intermediate is at most 2 R^2 with
+// R = |x_i| + max |x_j| >= the supports involved, and the test takes 13
+// roundings, so 20 * 2^-24 R^2 bounds the error; delta uses 2^-17 R^2.
+__device__ __forceinline__ float test_delta(float ri, float rj)
+{
+    const float R = ri + rj;
+    return 0x1p-17f * R * R;
+}
 
 struct Acc {
     float s0, s1, s2, s3, s4, s5;
@@ -185,71 +206,117 @@ __device__ __forceinline__ void load_i(const InteractArgs &a, int64_t slot, bool
     }
 }
 
-// stage candidate j (pack slot js, translated by (tx,ty,tz)) at LDS index k
+// the packed record of one j particle, held in registers between its load and
+// its staging (loaded one tile ahead of use)
+template <int LOOP>
+struct JRec;
+template <>
+struct JRec<0> {
+    float4 p0;
+    float m;
+};
+template <>
+struct JRec<1> {
+    float4 p0, p1;
+    float2 p2;
+};
+template <>
+struct JRec<2> {
+    float4 p0, p1, p2, p3;
+    float ad;
+};
+
+template <int LOOP>
+__device__ __forceinline__ void load_j(const InteractArgs &a, int64_t js, bool ok, JRec<LOOP> &r)
+{
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (LOOP == 0) {
+        r.p0 = ok ? ((const float4 *)a.pack)[js] : z4;
+        r.m = ok ? ((const float *)(a.pack + a.P * 16))[js] : 0.f;
+    } else if constexpr (LOOP == 1) {
+        r.p0 = ok ? ((const float4 *)a.pack)[js] : z4;
+        r.p1 = ok ? ((const float4 *)(a.pack + a.P * 16))[js] : z4;
+        r.p2 = ok ? ((const float2 *)(a.pack + a.P * 32))[js] : make_float2(0.f, 0.f);
+    } else {
+        r.p0 = ok ? ((const float4 *)a.pack)[js] : z4;
+        r.p1 = ok ? ((const float4 *)(a.pack + a.P * 16))[js] : z4;
+        r.p2 = ok ? ((const float4 *)(a.pack + a.P * 32))[js] : z4;
+        r.p3 = ok ? ((const float4 *)(a.pack + a.P * 48))[js] : z4;
+        r.ad = ok ? ((const float *)(a.pack + a.P * 64))[js] : 0.f;
+    }
+}
+
+// stage candidate j (record r, pack slot js, translated by (tx,ty,tz) and
+// shifted to the i-tile centre (cx,cy,cz)) at LDS index k
 template <int LOOP, int WIN>
 __device__ __forceinline__ void stage_j(const InteractArgs &a, Lds<LOOP, WIN> &L, int k, int64_t js,
-                                        const float4 &p0, float tx, float ty, float tz)
+                                        const JRec<LOOP> &r, float tx, float ty, float tz, float cx, float cy,
+                                        float cz)
 {
     const float g = a.gam;
-    const float x = p0.x + tx, y = p0.y + ty, z = p0.z + tz;
+    const float x = (r.p0.x + tx) - cx, y = (r.p0.y + ty) - cy, z = (r.p0.z + tz) - cz;
     L.jslot[k] = (int32_t)js;
+    L.ph[k] = make_float4(x, y, z, -fmaf(z, z, fmaf(y, y, x * x)));
     if constexpr (LOOP == 0) {
-        const float m = ((const float *)(a.pack + a.P * 16))[js];
-        L.c0[k] = make_float4(x, y, z, m);
+        L.m[k] = r.m;
     } else if constexpr (LOOP == 1) {
-        const float4 p1 = ((const float4 *)(a.pack + a.P * 16))[js];
-        const float2 p2 = ((const float2 *)(a.pack + a.P * 32))[js];
-        L.c0[k] = make_float4(x, y, z, p1.w);
-        L.c1[k] = make_float4(p1.x, p1.y, p1.z, sqrtf(g * (g - 1.0f) * p2.x));
-        L.c2[k] = make_float2(p2.x, p1.w / p2.y);
+        L.c1[k] = r.p1;
+        L.c2[k] = make_float4(r.p2.x, r.p1.w / r.p2.y, sqrtf(g * (g - 1.0f) * r.p2.x), 0.f);
     } else {
-        const float4 p1 = ((const float4 *)(a.pack + a.P * 16))[js];
-        const float4 p2 = ((const float4 *)(a.pack + a.P * 32))[js];
-        const float4 p3 = ((const float4 *)(a.pack + a.P * 48))[js];
-        const float ad = ((const float *)(a.pack + a.P * 64))[js];
-        const float h = p0.w, u = p2.x, rho = p2.y, rdh = p2.z, D = p2.w;
+        const float h = r.p0.w, u = r.p2.x, rho = r.p2.y, rdh = r.p2.z, D = r.p2.w;
         const float H = kGammaK * h, ih = 1.0f / H;
         const float A = (g - 1.0f) * u / (rho + h * rdh * (1.0f / 3.0f));
         const float c = sqrtf(g * (g - 1.0f) * u);
         const float irho = 1.0f / rho;
         const float div = fabsf(D * irho);
-        const float curl = sqrtf(p3.x * p3.x + p3.y * p3.y + p3.z * p3.z) * irho;
-        const float at = p3.w * div / (div + curl + a.eps * c / h);
-        L.c0[k] = make_float4(x, y, z, H * H);
-        L.c1[k] = p1;
+        const float curl = sqrtf(r.p3.x * r.p3.x + r.p3.y * r.p3.y + r.p3.z * r.p3.z) * irho;
+        const float at = r.p3.w * div / (div + curl + a.eps * c / h);
+        L.c1[k] = r.p1;
         L.c2[k] = make_float4(H, ih, A, c);
-        L.c3[k] = make_float4(kC3 * ih * ih * ih * ih * ih, at, ad, rho);
-        L.c4[k] = u;
+        L.c3[k] = make_float4(kC3 * ih * ih * ih * ih * ih, at, r.ad, rho);
+        L.c4[k] = make_float2(u, H * H);
     }
 }
 
-template <int LOOP>
-__device__ __forceinline__ bool hit(const IData &d, const float4 &c, float &r2)
+// Phase-1 test of candidate k, as a sign: the result is negative when
+// |x_i - x_j|^2 < H^2 + delta_i, evaluated as |x_i|^2 - delta_i - H^2 + |x_j|^2 -
+// 2 x_i.x_j with delta_i covering the rounding of these four operations, so the
+// hits are a superset of the exact test that the pair term applies again.
+template <int LOOP, int WIN>
+__device__ __forceinline__ float test_sign(const Lds<LOOP, WIN> &L, int k, const IData &d)
 {
-    const float dx = d.x - c.x, dy = d.y - c.y, dz = d.z - c.z;
-    r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    if constexpr (LOOP == 2) return r2 < fmaxf(d.H2, c.w);
-    else return r2 < d.H2;
+    const float4 q = L.ph[k];
+    float t;
+    if constexpr (LOOP == 2) t = (d.t0 - fmaxf(d.H2, L.c4[k].y)) - q.w;
+    else t = d.t0 - q.w;
+    return fmaf(d.nx2, q.x, fmaf(d.ny2, q.y, fmaf(d.nz2, q.z, t)));
 }
 
 template <int LOOP, int WIN>
 __device__ __forceinline__ void pair(const InteractArgs &a, const Lds<LOOP, WIN> &L, int k, const IData &d,
                                      Acc &acc)
 {
-    const float4 c0 = L.c0[k];
+    const float4 c0 = L.ph[k];
     const float rx = d.x - c0.x, ry = d.y - c0.y, rz = d.z - c0.z;
     const float r2 = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
     if constexpr (LOOP == 0) {
+        if (!(r2 < d.H2)) return;  // the exact criterion
+        const float mj = L.m[k];
         const float r = fast_sqrt(r2);
         const float q = r * d.invH;
         float w, dw;
         spline_w_dw(q, w, dw);
-        acc.s0 = fmaf(c0.w, w, acc.s0);                      // sum m w
-        acc.s1 = fmaf(c0.w, fmaf(q, dw, 3.0f * w), acc.s1);  // sum m (3w + q w')
-        acc.s2 += w;                                         // sum w
+        acc.s0 = fmaf(mj, w, acc.s0);                      // sum m w
+        acc.s1 = fmaf(mj, fmaf(q, dw, 3.0f * w), acc.s1);  // sum m (3w + q w')
+        acc.s2 += w;                                       // sum w
         acc.n++;
     } else {
         if (L.jslot[k] == d.slot) return;  // j != i
+        if constexpr (LOOP == 1) {
+            if (!(r2 < d.H2)) return;
+        } else {
+            if (!(r2 < fmaxf(d.H2, L.c4[k].y))) return;
+        }
         const float4 c1 = L.c1[k];
         const float vx = d.vx - c1.x, vy = d.vy - c1.y, vz = d.vz - c1.z;
         const float invr = r2 > 0.f ? fast_rsq(r2) : 0.f;
@@ -257,22 +324,23 @@ __device__ __forceinline__ void pair(const InteractArgs &a, const Lds<LOOP, WIN>
         const float dot = fmaf(vz, rz, fmaf(vy, ry, vx * rx));
         const float mu = fminf(dot * invr, 0.0f);
         if constexpr (LOOP == 1) {
-            const float2 c2 = L.c2[k];
+            const float4 c2 = L.c2[k];  // u m/rho c
             const float f = spline_f(r * d.invH, d.H * invr);    // w'/q
-            const float mf = c0.w * f;
+            const float mf = c1.w * f;
             acc.s0 = fmaf(mf, dot, acc.s0);                                   // D
             acc.s1 = fmaf(mf, fmaf(vy, rz, -vz * ry), acc.s1);                // R
             acc.s2 = fmaf(mf, fmaf(vz, rx, -vx * rz), acc.s2);
             acc.s3 = fmaf(mf, fmaf(vx, ry, -vy * rx), acc.s3);
             acc.s4 = fmaf(c2.y * (d.u - c2.x), f, acc.s4);                    // L / 2
-            acc.s5 = fmaxf(acc.s5, d.c + c1.w - a.beta * mu);                 // V
+            acc.s5 = fmaxf(acc.s5, d.c + c2.z - a.beta * mu);                 // V
             acc.n++;
         } else {
             const float4 c2 = L.c2[k];  // H 1/H A c
             const float4 c3 = L.c3[k];  // K5 at ad rho
-            const float uj = L.c4[k];
+            const float2 c4 = L.c4[k];  // u H^2
+            const float uj = c4.x;
             const float fi = r2 < d.H2 ? d.K5 * spline_f(r * d.invH, d.H * invr) : 0.0f;
-            const float fj = r2 < c0.w ? c3.x * spline_f(r * c2.y, c2.x * invr) : 0.0f;
+            const float fj = r2 < c4.y ? c3.x * spline_f(r * c2.y, c2.x * invr) : 0.0f;
             const float fb = 0.5f * (fi + fj);
             const float vsig = d.c + c2.w - a.beta * mu;
             const float irb = fast_rcp(0.5f * (d.rho + c3.w));
@@ -324,22 +392,23 @@ __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, 
 {
     const int lane = threadIdx.x & 63;
     wave_sync();
+    nc = __builtin_amdgcn_readfirstlane(nc);
     const int nw = (nc + 31) >> 5;
+    IData dd = d;
+    if constexpr (LOOP == 2) dd.t0 = dd.xi2 - test_delta(dd.ri, dd.rj);
     for (int w = 0; w < nw; ++w) {
         uint32_t m = 0;
         const int kb = 32 * w;
-        const int kn = min(32, nc - kb);
+        const int kn = __builtin_amdgcn_readfirstlane(min(32, nc - kb));
+        // shift each candidate's sign bit in: candidate kb + b ends at bit 31 - b
         if (kn == 32) {
-#pragma unroll 8
-            for (int b = 0; b < 32; ++b) {
-                float r2;
-                m |= (hit<LOOP>(d, L.c0[kb + b], r2) ? 1u : 0u) << b;
-            }
+#pragma unroll 16
+            for (int b = 0; b < 32; ++b)
+                m = __builtin_amdgcn_alignbit(m, __float_as_uint(test_sign<LOOP, WIN>(L, kb + b, dd)), 31);
         } else {
-            for (int b = 0; b < kn; ++b) {
-                float r2;
-                m |= (hit<LOOP>(d, L.c0[kb + b], r2) ? 1u : 0u) << b;
-            }
+            for (int b = 0; b < kn; ++b)
+                m = __builtin_amdgcn_alignbit(m, __float_as_uint(test_sign<LOOP, WIN>(L, kb + b, dd)), 31);
+            m <<= (32 - kn);
         }
         L.mask[w][lane] = valid ? m : 0u;
     }
@@ -355,61 +424,145 @@ __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, 
         const bool act = cur != 0;
         if (!__any(act)) break;
         if (act) {
-            const int b = __builtin_ctz(cur);
-            cur &= cur - 1;
+            const int b = __builtin_clz(cur);
+            cur &= ~(0x80000000u >> b);
             pair<LOOP, WIN>(a, L, 32 * w + b, d, acc);
         }
     }
     wave_sync();
 }
 
-// gather the candidates of one j range (slots [js0, js0 + jn), bounds of its
-// 64-slot tiles at bnd, translation t) into the window, flushing when full
+// one j-tile as seen by one lane during the cull: slots, translation, box
+struct TileInfo {
+    int64_t js0;
+    int32_t jn;
+    float tx, ty, tz;
+};
+
+__device__ __forceinline__ TileInfo bcast(const TileInfo &t, int l)
+{
+    TileInfo o;
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)(uint64_t)t.js0, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)t.js0 >> 32), l);
+    o.js0 = (int64_t)(((uint64_t)hi << 32) | lo);
+    o.jn = __builtin_amdgcn_readlane(t.jn, l);
+    o.tx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t.tx), l));
+    o.ty = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t.ty), l));
+    o.tz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t.tz), l));
+    return o;
+}
+
+// stage the j particles of one tile that reach the i box; flush when full
 template <int LOOP, int WIN>
-__device__ __forceinline__ void scan_range(const InteractArgs &a, Lds<LOOP, WIN> &L, int &nc, int64_t js0,
-                                           int jn, const float4 *bnd, float tx, float ty, float tz,
-                                           const IData &d, bool valid, const float4 &lo, const float4 &hi,
-                                           Acc &acc)
+__device__ __forceinline__ void stage_tile(const InteractArgs &a, Lds<LOOP, WIN> &L, int &nc, const TileInfo &t,
+                                           const JRec<LOOP> &r, const IData &d, bool valid, const float4 &lo,
+                                           const float4 &hi, const float4 &cen, Acc &acc)
 {
     const int lane = threadIdx.x & 63;
-    const int ntile = (jn + 63) >> 6;
-    const float hmi = lo.w;  // largest support of the i-tile
-    for (int t = 0; t < ntile; ++t) {
-        // 1. tile cull on the j-tile's stored box
-        const float4 blo = bnd[2 * t], bhi = bnd[2 * t + 1];
-        const float gx = fmaxf(fmaxf(blo.x + tx - hi.x, lo.x - (bhi.x + tx)), 0.f);
-        const float gy = fmaxf(fmaxf(blo.y + ty - hi.y, lo.y - (bhi.y + ty)), 0.f);
-        const float gz = fmaxf(fmaxf(blo.z + tz - hi.z, lo.z - (bhi.z + tz)), 0.f);
-        const float reach_t = LOOP == 2 ? fmaxf(hmi, blo.w) : hmi;
-        if (fmaf(gz, gz, fmaf(gy, gy, gx * gx)) >= reach_t * reach_t * 1.0001f) continue;
-        // 2. stage the j particles of the tile that reach the i box
-        const int jk = 64 * t + lane;
-        const bool jv = jk < jn;
-        const int64_t js = js0 + jk;
-        float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f);
-        bool keep = false;
-        if (jv) {
-            p0 = ((const float4 *)a.pack)[js];
-            const float x = p0.x + tx, y = p0.y + ty, z = p0.z + tz;
-            const float ex = fmaxf(fmaxf(lo.x - x, x - hi.x), 0.f);
-            const float ey = fmaxf(fmaxf(lo.y - y, y - hi.y), 0.f);
-            const float ez = fmaxf(fmaxf(lo.z - z, z - hi.z), 0.f);
-            const float reach = LOOP == 2 ? fmaxf(hmi, kGammaK * p0.w) : hmi;
-            keep = fmaf(ez, ez, fmaf(ey, ey, ex * ex)) < reach * reach * 1.0001f;
+    const float hmi = lo.w;
+    bool keep = false;
+    if (lane < t.jn) {
+        const float x = r.p0.x + t.tx, y = r.p0.y + t.ty, z = r.p0.z + t.tz;
+        const float ex = fmaxf(fmaxf(lo.x - x, x - hi.x), 0.f);
+        const float ey = fmaxf(fmaxf(lo.y - y, y - hi.y), 0.f);
+        const float ez = fmaxf(fmaxf(lo.z - z, z - hi.z), 0.f);
+        const float reach = LOOP == 2 ? fmaxf(hmi, kGammaK * r.p0.w) : hmi;
+        keep = fmaf(ez, ez, fmaf(ey, ey, ex * ex)) < reach * reach * 1.0001f;
+    }
+    const uint64_t bal = __ballot(keep);
+    const int cnt = __popcll(bal);
+    if (cnt == 0) return;
+    if (nc + cnt > WIN) {
+        flush<LOOP, WIN>(a, L, nc, d, valid, acc);
+        nc = 0;
+    }
+    if (keep) {
+        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        stage_j<LOOP, WIN>(a, L, nc + rank, t.js0 + lane, r, t.tx, t.ty, t.tz, cen.x, cen.y, cen.z);
+    }
+    nc = __builtin_amdgcn_readfirstlane(nc + cnt);
+}
+
+// gather the candidates of one item's j-tile list (nj tiles) into the window
+template <int LOOP, int MODE, int WIN>
+__device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN> &L, int &nc, const Chunk &ch,
+                                          IData &d, bool valid, const float4 &lo, const float4 &hi,
+                                          const float4 &cen, Acc &acc)
+{
+    const float ex = hi.x - lo.x, ey = hi.y - lo.y, ez = hi.z - lo.z;
+    const float halfdiag = 0.5f * sqrtf(fmaxf(ex * ex + ey * ey + ez * ez, 0.f));
+    float hjm = 0.f;  // largest support of the surviving j-tiles so far
+    const int lane = threadIdx.x & 63;
+    int nj, jt0 = 0;
+    if (MODE == 0) {
+        nj = (ch.jn + 63) >> 6;
+    } else {
+        jt0 = a.jt_off[ch.cell];
+        nj = a.jt_off[ch.cell + 1] - jt0;
+    }
+    const float hmi = lo.w;
+    for (int base = 0; base < nj; base += 64) {
+        // 1. lane-parallel cull of up to 64 j-tiles on their stored boxes
+        TileInfo ti{0, 0, 0.f, 0.f, 0.f};
+        bool ok = false;
+        const int q = base + lane;
+        if (q < nj) {
+            float4 blo, bhi;
+            if (MODE == 0) {
+                const int64_t bt = (int64_t)ch.jchunk0 - a.chunk_base + q;
+                blo = a.bounds[2 * bt];
+                bhi = a.bounds[2 * bt + 1];
+                ti.js0 = ch.jslot0 - a.slot_base + 64 * (int64_t)q;
+                ti.jn = min(64, ch.jn - 64 * q);
+            } else {
+                const JTile e = a.jt[jt0 + q];
+                const Nbr nb = a.nbr[e.nbr];
+                const Chunk tj = a.items_chunks[e.tile];
+                blo = a.bounds[2 * (int64_t)e.tile];
+                bhi = a.bounds[2 * (int64_t)e.tile + 1];
+                ti.js0 = tj.slot0;
+                ti.jn = tj.n;
+                ti.tx = nb.dx;
+                ti.ty = nb.dy;
+                ti.tz = nb.dz;
+            }
+            const float gx = fmaxf(fmaxf(blo.x + ti.tx - hi.x, lo.x - (bhi.x + ti.tx)), 0.f);
+            const float gy = fmaxf(fmaxf(blo.y + ti.ty - hi.y, lo.y - (bhi.y + ti.ty)), 0.f);
+            const float gz = fmaxf(fmaxf(blo.z + ti.tz - hi.z, lo.z - (bhi.z + ti.tz)), 0.f);
+            const float reach = LOOP == 2 ? fmaxf(hmi, blo.w) : hmi;
+            ok = fmaf(gz, gz, fmaf(gy, gy, gx * gx)) < reach * reach * 1.0001f;
         }
-        const uint64_t bal = __ballot(keep);
-        const int cnt = __popcll(bal);
-        if (cnt == 0) continue;
-        if (nc + cnt > WIN) {
-            flush<LOOP, WIN>(a, L, nc, d, valid, acc);
-            nc = 0;
+        uint64_t m = __ballot(ok);
+        if (m == 0) continue;
+        if constexpr (LOOP == 2) {
+            // candidates of these tiles reach at most max(i-tile support, their tile's support)
+            float hj = 0.f;
+            if (ok) hj = MODE == 0 ? a.bounds[2 * ((int64_t)ch.jchunk0 - a.chunk_base + q)].w
+                                   : a.bounds[2 * (int64_t)a.jt[jt0 + q].tile].w;
+            hjm = fmaxf(hjm, wmax(hj));
+            d.rj = halfdiag + 1.001f * fmaxf(hmi, hjm);
         }
-        if (keep) {
-            const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            stage_j<LOOP, WIN>(a, L, nc + rank, js, p0, tx, ty, tz);
+        // 2. stage surviving tiles, the next tile's records loaded ahead
+        int cur = __builtin_ctzll(m);
+        m &= m - 1;
+        TileInfo ct = bcast(ti, cur);
+        JRec<LOOP> cr;
+        load_j<LOOP>(a, ct.js0 + lane, lane < ct.jn, cr);
+        for (;;) {
+            const bool more = m != 0;
+            TileInfo nt = ct;
+            JRec<LOOP> nr;
+            if (more) {
+                const int nx = __builtin_ctzll(m);
+                m &= m - 1;
+                nt = bcast(ti, nx);
+                load_j<LOOP>(a, nt.js0 + lane, lane < nt.jn, nr);
+            }
+            stage_tile<LOOP, WIN>(a, L, nc, ct, cr, d, valid, lo, hi, cen, acc);
+            if (!more) break;
+            ct = nt;
+            cr = nr;
         }
-        nc += cnt;
     }
 }
 
@@ -458,21 +611,29 @@ __global__ __launch_bounds__(256) void k_interact(InteractArgs a)
         hi.y = wmax(valid ? d.y : -inf);
         hi.z = wmax(valid ? d.z : -inf);
         hi.w = 0.f;
+        // i positions relative to the tile centre; phase-1 constants
+        float4 cen;
+        cen.x = 0.5f * (lo.x + hi.x);
+        cen.y = 0.5f * (lo.y + hi.y);
+        cen.z = 0.5f * (lo.z + hi.z);
+        cen.w = 0.f;
+        {
+            const float ex = hi.x - lo.x, ey = hi.y - lo.y, ez = hi.z - lo.z;
+            const float halfdiag = valid ? 0.5f * sqrtf(ex * ex + ey * ey + ez * ez) : 0.f;
+            d.x -= cen.x;
+            d.y -= cen.y;
+            d.z -= cen.z;
+            d.ri = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+            d.xi2 = fmaf(d.z, d.z, fmaf(d.y, d.y, d.x * d.x));
+            d.rj = halfdiag + 1.001f * lo.w;
+            d.nx2 = -2.0f * d.x;
+            d.ny2 = -2.0f * d.y;
+            d.nz2 = -2.0f * d.z;
+            d.t0 = (d.xi2 - test_delta(d.ri, d.rj)) - d.H2;
+        }
         Acc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0};
         int nc = 0;
-        if (MODE == 0) {
-            scan_range<LOOP, WIN>(a, L, nc, ch.jslot0 - a.slot_base, ch.jn,
-                                  a.bounds + 2 * (ch.jchunk0 - a.chunk_base), 0.f, 0.f, 0.f, d, valid, lo, hi,
-                                  acc);
-        } else {
-            const int e0 = a.nbr_off[ch.cell], e1 = a.nbr_off[ch.cell + 1];
-            for (int e = e0; e < e1; ++e) {
-                const Nbr nb = a.nbr[e];
-                const CellRange cr = a.cellr[nb.cell];
-                scan_range<LOOP, WIN>(a, L, nc, cr.first, cr.count, a.bounds + 2 * cr.tile0, nb.dx, nb.dy, nb.dz,
-                                      d, valid, lo, hi, acc);
-            }
-        }
+        scan_item<LOOP, MODE, WIN>(a, L, nc, ch, d, valid, lo, hi, cen, acc);
         if (nc > 0) flush<LOOP, WIN>(a, L, nc, d, valid, acc);
         if (valid) write_out<LOOP>(a, d, acc);
     }
@@ -536,6 +697,8 @@ sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, 
         a.cellr = p->d_cellr;
         a.nbr = p->d_nbr;
         a.nbr_off = p->d_nbr_off;
+        a.jt_off = p->d_jt_off;
+        a.jt = p->d_jt;
         a.bounds = (const float4 *)(a.pack + a.P * 4 * kPackFloats[loop]);
         a.queue = (int32_t *)ws;
         a.use_queue = tn->queue;

@@ -63,6 +63,13 @@ struct CellRange {
     int32_t tile0;  // first tile of the cell
 };
 
+// One entry of a cell's flattened j-tile list: a tile of a neighbour cell and
+// the neighbour entry whose translation moves it into the cell's frame.
+struct JTile {
+    int32_t tile;
+    int32_t nbr;
+};
+
 }  // namespace sph
 
 struct sph_plan {
@@ -86,6 +93,9 @@ struct sph_plan {
     sph::Nbr *d_nbr = nullptr;
     int32_t *d_nbr_off = nullptr;
     int32_t *d_items = nullptr;      // tiles in descending cost order
+    int32_t *d_jt_off = nullptr;     // per cell: first entry of its j-tile list
+    sph::JTile *d_jt = nullptr;      // flattened j-tiles of every cell's neighbours
+    int32_t max_jt = 0;
     // per-particle slot lists, built on the first multi-task unpack
     std::mutex csr_mu;
     bool csr_built = false;

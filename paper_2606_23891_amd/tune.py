@@ -1,0 +1,170 @@
+"""Autotuner for the batched form's launch parameters.
+
+For each loop it times the interaction kernel over candidate windows (the LDS
+candidate buffer per wave), persistent-grid sizes (blocks per CU) and work
+distribution (device queue or static stride), and times pack + unpack over
+waves per block; it keeps the fastest of each (median of a few HIP-event
+timed repetitions on the device) and records them in a JSON cache keyed by
+device name and workload signature.  ``bench.py --tuning auto`` reads the cache.
+
+Usage: python -m paper_2606_23891_amd.tune [--config 2] [--grid 32] [--layout SAOS_SHARED]
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuning_cache.json")
+
+WINDOWS = {0: (128, 256, 512), 1: (128, 256, 512), 2: (64, 128, 256)}
+BLOCKS_PER_CU = (2, 4, 8, 16)
+QUEUE = (1, 0)
+PACK_WAVES = (1, 2, 4, 8)
+
+
+def signature(ps, layout_name: str) -> str:
+    st = ps.meta
+    return f"cfg{st.get('config')}-n{ps.n}-cells{len(ps.cells)}-tasks{len(ps.tasks)}-{layout_name}"
+
+
+def load(device: str, sig: str):
+    if not os.path.exists(CACHE):
+        return None
+    try:
+        data = json.load(open(CACHE))
+    except (OSError, ValueError):
+        return None
+    return data.get(device, {}).get(sig)
+
+
+def apply(tuning, entry: dict):
+    for k, v in entry.items():
+        if k == "window":
+            for i, w in enumerate(v):
+                tuning.window[i] = int(w)
+        elif k in ("blocks_per_cu", "pack_waves", "queue"):
+            setattr(tuning, k, int(v))
+    return tuning
+
+
+def _timed(fn, reps=3):
+    import torch
+    s = torch.cuda.current_stream()
+    fn()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune(plan, store, log=print):
+    """Return (best sph_tuning fields as a dict, timings)."""
+    import torch
+
+    from . import sph
+
+    ws = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+    params = sph.default_params()
+    best = {"window": [256, 256, 128], "blocks_per_cu": 8, "queue": 1, "pack_waves": 4}
+    times = {}
+    bufs = {L: sph.cell_buffers(plan, L) for L in range(3)}
+    # make every loop's inputs valid: one plain pass through the three loops
+    t = sph.default_tuning()
+    for L in range(3):
+        pack, res = bufs[L]
+        sph.sph_pack_cells(plan, L, store, pack, t)
+        sph.sph_interact_cells(plan, L, pack, res, ws, params=params, tuning=t)
+        sph.sph_unpack_cells(plan, L, res, store, t)
+    torch.cuda.synchronize()
+    # pack / unpack waves per block (all loops together)
+    pw_best, pw_t = None, None
+    for pw in PACK_WAVES:
+        t = sph.default_tuning()
+        t.pack_waves = pw
+
+        def run():
+            for L in range(3):
+                pack, res = bufs[L]
+                sph.sph_pack_cells(plan, L, store, pack, t)
+                sph.sph_unpack_cells(plan, L, res, store, t)
+        ms = _timed(run)
+        times[f"pack_unpack_waves{pw}"] = ms
+        log(f"pack+unpack waves={pw}: {ms:.3f} ms")
+        if pw_t is None or ms < pw_t:
+            pw_best, pw_t = pw, ms
+    best["pack_waves"] = pw_best
+    # interaction kernels; the grid size and queue mode are shared by the loops,
+    # so they are chosen on the sum of the three loops' best windows
+    totals = {}
+    for bpc, q in itertools.product(BLOCKS_PER_CU, QUEUE):
+        tot, wins = 0.0, []
+        for L in range(3):
+            pack, res = bufs[L]
+            sph.sph_pack_cells(plan, L, store, pack)
+            bw, bt = None, None
+            for w in WINDOWS[L]:
+                t = sph.default_tuning()
+                t.blocks_per_cu, t.queue = bpc, q
+                t.window[L] = w
+                ms = _timed(lambda: sph.sph_interact_cells(plan, L, pack, res, ws, params=params, tuning=t))
+                times[f"loop{L}_bpc{bpc}_q{q}_w{w}"] = ms
+                if bt is None or ms < bt:
+                    bw, bt = w, ms
+            tot += bt
+            wins.append(bw)
+        totals[(bpc, q)] = (tot, wins)
+        log(f"blocks/CU={bpc} queue={q}: {tot:.3f} ms (windows {wins})")
+    (bpc, q), (tot, wins) = min(totals.items(), key=lambda kv: kv[1][0])
+    best.update(blocks_per_cu=bpc, queue=q, window=wins)
+    return best, times
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--grid", type=int, default=None)
+    ap.add_argument("--n-side", type=int, default=None)
+    ap.add_argument("--layout", default="SAOS_SHARED")
+    a = ap.parse_args()
+    import torch
+
+    from . import inputs, sph
+
+    kw = {}
+    if a.grid:
+        kw["grid"] = a.grid
+    if a.n_side:
+        kw["n_side"] = a.n_side
+    ps = inputs.make_config(a.config, **kw)
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    store = sph.Store(sph.LAYOUTS.index(a.layout), ps.n)
+    store.put_all(ps.fields)
+    dev = torch.cuda.get_device_properties(0).name
+    sig = signature(ps, a.layout)
+    log = lambda m: print(f"[tune {time.strftime('%H:%M:%S')}] {m}", file=sys.stderr, flush=True)
+    best, times = tune(plan, store, log)
+    data = {}
+    if os.path.exists(CACHE):
+        try:
+            data = json.load(open(CACHE))
+        except ValueError:
+            data = {}
+    data.setdefault(dev, {})[sig] = best
+    with open(CACHE, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    print(json.dumps({"device": dev, "workload": sig, "best": best, "times_ms": times}))
+
+
+if __name__ == "__main__":
+    main()
