@@ -17,8 +17,14 @@
 //   rhobar_j W(r,h_j) + rhodhbar_j W_h(r,h_j)                 into mbar_k.
 //
 // Mapping: one thread per particle k, walking the particles of its cell's
-// neighbour cells (the plan's cell tasks) in FP32; positions are packed once
-// to float32 offsets from each particle's own cell corner.
+// neighbour cells (the plan's cell tasks).  The forward pass that produces
+// rho, rho_dh and a evaluates in FP64 from the float64 positions: a is a sum
+// of pair terms that nearly cancel on a near-uniform particle set, and every
+// gradient is proportional to abar = dL/da = 2a, so FP32 rounding of a (up to a
+// few 1e-3 of |a| for such particles) would set the accuracy of the whole
+// gradient.  MI355X runs FP64 vector arithmetic at the rate of unpacked FP32.
+// The hand-written backward kernels run in FP32 on positions packed once to
+// float32 offsets from each particle's own cell corner.
 #include <hip/hip_runtime.h>
 
 #include "sph_internal.hpp"
@@ -36,7 +42,8 @@ struct AdjArgs {
     // packed per particle (workspace)
     float4 *pos;  // dx dy dz (cell frame) h
     float4 *vm;   // vx vy vz m
-    float4 *ua;   // u alpha~ alpha_d (unused)
+    float4 *ua;      // u alpha~ alpha_d (unused)
+    double *rho64;   // forward rho, rho_dh in float64
     float gam, beta;
 };
 
@@ -71,6 +78,52 @@ __device__ __forceinline__ void kern_F(float r, float H, float &F, float &Fp)
         const float t = 1.0f - q;
         F = K5 * (-6.0f * t * t / q);
         Fp = K5 * iH * 6.0f * t * (1.0f + q) / (q * q);
+    }
+}
+
+// FP64 pieces of the forward pass
+__device__ __forceinline__ void spl64(double q, double &w, double &dw)
+{
+    if (q < 0.5) {
+        w = 1.0 - 6.0 * q * q + 6.0 * q * q * q;
+        dw = -12.0 * q + 18.0 * q * q;
+    } else {
+        const double t = q < 1.0 ? 1.0 - q : 0.0;
+        w = 2.0 * t * t * t;
+        dw = -6.0 * t * t;
+    }
+}
+
+__device__ __forceinline__ double kern_F64(double r, double H)
+{
+    if (!(r < H)) return 0.0;
+    const double q = r / H, H2 = H * H;
+    const double K5 = (8.0 / 3.14159265358979323846) / (H2 * H2 * H);
+    if (q < 0.5) return K5 * (-12.0 + 18.0 * q);
+    const double t = 1.0 - q;
+    return K5 * (-6.0 * t * t / q);
+}
+
+// walk every neighbour-cell particle j of particle k with float64 separations
+// x_k - x_j + shift, the shift recovered from the entry's translation
+template <class Fn>
+__device__ __forceinline__ void for_neighbours64(const AdjArgs &a, int32_t cell, int64_t k, const double *x, Fn &&fn)
+{
+    const double xk = x[3 * k], yk = x[3 * k + 1], zk = x[3 * k + 2];
+    const sph_cell &ck = a.cells[cell];
+    const int e0 = a.nbr_off[cell], e1 = a.nbr_off[cell + 1];
+    for (int e = e0; e < e1; ++e) {
+        const Nbr nb = a.nbr[e];
+        const sph_cell &cj = a.cells[nb.cell];
+        const CellRange cr = a.cellr[nb.cell];
+        // translation = loc(cj) + shift - loc(ck)
+        const double sx = ((double)nb.dx - cj.loc[0]) + ck.loc[0];
+        const double sy = ((double)nb.dy - cj.loc[1]) + ck.loc[1];
+        const double sz = ((double)nb.dz - cj.loc[2]) + ck.loc[2];
+        for (int q = 0; q < cr.count; ++q) {
+            const int64_t j = cr.first + q;
+            fn(j, xk - (x[3 * j] + sx), yk - (x[3 * j + 1] + sy), zk - (x[3 * j + 2] + sz));
+        }
     }
 }
 
@@ -129,27 +182,29 @@ __global__ void k_adj_prep_xm(AdjArgs a, const double *x, const float *m, const 
     a.vm[k] = make_float4(0.f, 0.f, 0.f, m[k]);
 }
 
-__global__ void k_adj_density(AdjArgs a, float *rho, float *rho_dh)
+__global__ void k_adj_density(AdjArgs a, const double *x, float *rho, float *rho_dh, double *rho64)
 {
     int64_t k;
     int32_t c;
     if (!my_particle(a, k, c)) return;
-    const float4 pk = a.pos[k];
-    const float H = kGammaK * pk.w, iH = 1.0f / H, H2 = H * H;
-    float s0 = 0.f, s1 = 0.f;
-    for_neighbours(a, c, pk, [&](int64_t j, float rx, float ry, float rz) {
-        const float r2 = rx * rx + ry * ry + rz * rz;
+    const double H = 1.8257418583505537 * (double)a.pos[k].w, H2 = H * H;
+    double s0 = 0.0, s1 = 0.0;
+    for_neighbours64(a, c, k, x, [&](int64_t j, double rx, double ry, double rz) {
+        const double r2 = rx * rx + ry * ry + rz * rz;
         if (!(r2 < H2)) return;
-        const float q = sqrtf(r2) * iH;
-        float w, dw, d2w;
-        spl(q, w, dw, d2w);
-        const float mj = a.vm[j].w;
+        const double q = sqrt(r2) / H;
+        double w, dw;
+        spl64(q, w, dw);
+        const double mj = a.vm[j].w;
         s0 += mj * w;
-        s1 += mj * (3.0f * w + q * dw);
+        s1 += mj * (3.0 * w + q * dw);
     });
-    const float iH3 = iH * iH * iH;
-    rho[k] = kC3 * iH3 * s0;
-    rho_dh[k] = -kGammaK * kC3 * iH3 * iH * s1;
+    const double C = (8.0 / 3.14159265358979323846) / (H2 * H);
+    const double r0 = C * s0, r1 = -1.8257418583505537 * C / H * s1;
+    rho[k] = (float)r0;
+    rho_dh[k] = (float)r1;
+    rho64[2 * k] = r0;
+    rho64[2 * k + 1] = r1;
 }
 
 struct PairQ {  // per-particle quantities of the force loop
@@ -172,43 +227,54 @@ __device__ __forceinline__ PairQ pq(const AdjArgs &a, int64_t k, const float *rh
     return p;
 }
 
-__global__ void k_adj_force(AdjArgs a, const float *rho, const float *rho_dh, float *acc, float *udt)
+__global__ void k_adj_force(AdjArgs a, const double *x, const double *rho64, float *acc, float *udt)
 {
     int64_t k;
     int32_t c;
     if (!my_particle(a, k, c)) return;
-    const float4 pk = a.pos[k];
+    const double g = a.gam, beta = a.beta;
+    auto q64 = [&](int64_t i, double &H, double &A, double &cs, double &rh, double &u, double &at, double &ad) {
+        const double h = a.pos[i].w;
+        const float4 ua = a.ua[i];
+        H = 1.8257418583505537 * h;
+        rh = rho64[2 * i];
+        u = ua.x;
+        A = (g - 1.0) * u / (rh + h * rho64[2 * i + 1] / 3.0);
+        cs = sqrt(g * (g - 1.0) * u);
+        at = ua.y;
+        ad = ua.z;
+    };
+    double Hk, Ak, ck, rk, uk, atk, adk;
+    q64(k, Hk, Ak, ck, rk, uk, atk, adk);
     const float4 vk = a.vm[k];
-    const PairQ P = pq(a, k, rho, rho_dh);
-    float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f;
-    for_neighbours(a, c, pk, [&](int64_t j, float rx, float ry, float rz) {
+    double ax = 0.0, ay = 0.0, az = 0.0, du = 0.0;
+    for_neighbours64(a, c, k, x, [&](int64_t j, double rx, double ry, double rz) {
         if (j == k) return;
-        const float Hj = kGammaK * a.pos[j].w;
-        const float r2 = rx * rx + ry * ry + rz * rz;
-        const float Hm = fmaxf(P.H, Hj);
+        const double Hj0 = 1.8257418583505537 * (double)a.pos[j].w;
+        const double r2 = rx * rx + ry * ry + rz * rz;
+        const double Hm = Hk > Hj0 ? Hk : Hj0;
         if (!(r2 < Hm * Hm)) return;
-        const PairQ Q = pq(a, j, rho, rho_dh);
+        double Hj, Aj, cj, rj, uj, atj, adj;
+        q64(j, Hj, Aj, cj, rj, uj, atj, adj);
         const float4 vj = a.vm[j];
-        const float r = sqrtf(r2);
-        float Fk, Fkp, Fj, Fjp;
-        kern_F(r, P.H, Fk, Fkp);
-        kern_F(r, Q.H, Fj, Fjp);
-        const float Fb = 0.5f * (Fk + Fj);
-        const float vx = vk.x - vj.x, vy = vk.y - vj.y, vz = vk.z - vj.z;
-        const float dot = vx * rx + vy * ry + vz * rz;
-        const float mu = r > 0.f ? fminf(dot / r, 0.f) : 0.f;
-        const float rb = 0.5f * (P.rho + Q.rho);
-        const float Pi = -0.5f * 0.5f * (P.at + Q.at) * (P.c + Q.c - a.beta * mu) * mu / rb;
-        const float S = P.A * Fk + Q.A * Fj + Pi * Fb;
-        ax -= vj.w * S * rx;
-        ay -= vj.w * S * ry;
-        az -= vj.w * S * rz;
-        du += vj.w * (P.A * Fk * dot + 0.5f * Pi * Fb * dot + 0.5f * (P.ad + Q.ad) * fabsf(dot) * (P.u - Q.u) * Fb / rb);
+        const double r = sqrt(r2);
+        const double Fk = kern_F64(r, Hk), Fj = kern_F64(r, Hj), Fb = 0.5 * (Fk + Fj);
+        const double vx = (double)vk.x - vj.x, vy = (double)vk.y - vj.y, vz = (double)vk.z - vj.z;
+        const double dot = vx * rx + vy * ry + vz * rz;
+        const double mu = (r > 0.0 && dot < 0.0) ? dot / r : 0.0;
+        const double rb = 0.5 * (rk + rj);
+        const double Pi = -0.5 * 0.5 * (atk + atj) * (ck + cj - beta * mu) * mu / rb;
+        const double S = Ak * Fk + Aj * Fj + Pi * Fb;
+        const double mj = vj.w;
+        ax -= mj * S * rx;
+        ay -= mj * S * ry;
+        az -= mj * S * rz;
+        du += mj * (Ak * Fk * dot + 0.5 * Pi * Fb * dot + 0.5 * (adk + adj) * fabs(dot) * (uk - uj) * Fb / rb);
     });
-    acc[3 * k] = ax;
-    acc[3 * k + 1] = ay;
-    acc[3 * k + 2] = az;
-    udt[k] = du;
+    acc[3 * k] = (float)ax;
+    acc[3 * k + 1] = (float)ay;
+    acc[3 * k + 2] = (float)az;
+    udt[k] = (float)du;
 }
 
 __global__ void k_force_adjoint(AdjArgs a, const float *rho, const float *rho_dh, const float *abar, float *xbar,
@@ -337,7 +403,7 @@ static sph_status adj_setup(const sph_plan *p, void *ws, size_t ws_bytes, AdjArg
 {
     if (!p) return fail(SPH_E_ARG, "plan is null");
     if (!p->batched_ok) return fail(SPH_E_UNSUPPORTED, "cells do not tile the store in order");
-    const size_t need = (size_t)round_slots(p->n) * 48;
+    const size_t need = (size_t)round_slots(p->n) * 64;
     if (!ws || ((uintptr_t)ws & 255u)) return fail(SPH_E_ARG, "workspace null or misaligned");
     if (ws_bytes < need) return fail(SPH_E_CAPACITY, "adjoint workspace needs " + std::to_string(need) + " bytes");
     a.n = p->n;
@@ -351,6 +417,7 @@ static sph_status adj_setup(const sph_plan *p, void *ws, size_t ws_bytes, AdjArg
     a.pos = (float4 *)ws;
     a.vm = a.pos + P;
     a.ua = a.vm + P;
+    a.rho64 = (double *)(a.ua + P);
     return SPH_OK;
 }
 
@@ -365,7 +432,7 @@ extern "C" {
 sph_status sph_adjoint_ws_bytes(const sph_plan *p, size_t *bytes)
 {
     if (!p || !bytes) return fail(SPH_E_ARG, "null argument");
-    *bytes = (size_t)round_slots(p->n) * 48;
+    *bytes = (size_t)round_slots(p->n) * 64;
     return SPH_OK;
 }
 
@@ -385,9 +452,8 @@ sph_status sph_adjoint_forward(const sph_plan *p, const double *x, const float *
     a.beta = prm->beta_visc;
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_adj_prep, adj_grid(a), dim3(256), 0, st, a, x, v, m, h, u, atilde, alpha_d);
-    hipLaunchKernelGGL(k_adj_density, adj_grid(a), dim3(256), 0, st, a, rho, rho_dh);
-    hipLaunchKernelGGL(k_adj_force, adj_grid(a), dim3(256), 0, st, a, (const float *)rho, (const float *)rho_dh,
-                       acc, u_dt);
+    hipLaunchKernelGGL(k_adj_density, adj_grid(a), dim3(256), 0, st, a, x, rho, rho_dh, a.rho64);
+    hipLaunchKernelGGL(k_adj_force, adj_grid(a), dim3(256), 0, st, a, x, (const double *)a.rho64, acc, u_dt);
     SPH_CHECK_LAUNCH("adjoint forward launch");
     return SPH_OK;
 }
