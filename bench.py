@@ -58,6 +58,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--layouts", default=None,
+                    help="'all' or comma list: also time pack + unpack of every loop per store layout")
+    ap.add_argument("--offload", default=None,
+                    help="'all' or comma list of layouts: also time the offload form (pinned host store)")
     ap.add_argument("--tuning", default="auto",
                     help="auto (the tuner's cache for this device and workload, else defaults), "
                          "default, or a JSON file with sph_tuning fields")
@@ -266,11 +270,118 @@ def main():
         log(f"per-task: {pt_ms:.1f} ms/step ({nt}/{ntask} tasks timed)")
         del pbuf, rbuf
 
+    # pack + unpack per store layout (the paper's layout comparison, on HBM)
+    if a.layouts:
+        names = sph.LAYOUTS if a.layouts == "all" else a.layouts.split(",")
+        out["layouts"] = layout_sweep(ps, plan, names, tuning, a.steps)
+
+    if a.offload:
+        names = sph.LAYOUTS if a.offload == "all" else a.offload.split(",")
+        out["offload"] = offload_sweep(ps, plan, names, tuning)
+
     # the CPU oracle on a bounded sample of the same workload
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(ps, store, a.cpu_seconds)
 
     print(json.dumps(out), flush=True)
+
+
+def layout_sweep(ps, plan, names, tuning, steps):
+    """pack + unpack time of each loop for every store layout (fresh store each)"""
+    import torch
+
+    from paper_2606_23891_amd import sph
+
+    bufs = {L: sph.cell_buffers(plan, L) for L in range(3)}
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name in names:
+        st = sph.Store(sph.LAYOUTS.index(name), ps.n)
+        st.put_all(ps.fields)
+        torch.cuda.synchronize()
+        row = {}
+        for L in range(3):
+            pack, r = bufs[L]
+            for s_ in range(2):
+                sph.sph_pack_cells(plan, L, st, pack, tuning)
+                sph.sph_unpack_cells(plan, L, r, st, tuning)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            tp = tu = 0.0
+            for _ in range(steps):
+                e[0].record(stream)
+                sph.sph_pack_cells(plan, L, st, pack, tuning)
+                e[1].record(stream)
+                sph.sph_unpack_cells(plan, L, r, st, tuning)
+                e[2].record(stream)
+                torch.cuda.synchronize()
+                tp += e[0].elapsed_time(e[1])
+                tu += e[1].elapsed_time(e[2])
+            tp /= steps
+            tu /= steps
+            row[LOOP_NAME[L]] = {"pack_ms": round(tp, 4), "unpack_ms": round(tu, 4),
+                                 "pack_GB/s": round(PACK_BYTES[L] * ps.n / (tp * 1e-3) / 1e9, 1),
+                                 "unpack_GB/s": round(UNPACK_BYTES[L] * ps.n / (tu * 1e-3) / 1e9, 1)}
+        row["total_ms"] = round(sum(v["pack_ms"] + v["unpack_ms"] for k, v in row.items() if k in LOOP_NAME.values()), 4)
+        res[name] = row
+        log(f"layout {name}: pack+unpack {row['total_ms']:.3f} ms per step")
+        del st
+        torch.cuda.empty_cache()
+    base = res.get("AOS", {}).get("total_ms")
+    if base:
+        for name in res:
+            res[name]["vs_AOS"] = round(res[name]["total_ms"] / base, 4)
+    return res
+
+
+def offload_sweep(ps, plan, names, tuning, reps=2):
+    """the offload form per layout: host store in pinned memory, per-loop copies
+    of the substructs each loop needs, batched compute on the device"""
+    import torch
+
+    from paper_2606_23891_amd import sph
+
+    stream = torch.cuda.current_stream()
+    ws = torch.zeros(sph.sph_batched_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    res = {}
+    for name in names:
+        lay = sph.LAYOUTS.index(name)
+        dev = sph.Store(lay, ps.n)
+        dev.put_all(ps.fields)
+        host = sph.Store(lay, ps.n, device="pinned")
+        for h, d in zip(host.subs, dev.subs):
+            h.copy_(d.cpu())
+        h2d = d2h = 0
+        for L in range(3):
+            a_, b_ = sph.sph_offload_bytes(lay, L, ps.n)
+            h2d += a_
+            d2h += b_
+        sph.sph_offload_step(plan, host, dev, ws, tuning=tuning)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            sph.sph_offload_step(plan, host, dev, ws, tuning=tuning)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"ms_per_step": round(ms, 3), "h2d_GB": round(h2d / 1e9, 3), "d2h_GB": round(d2h / 1e9, 3),
+                     "link_GB/s": round((h2d + d2h) / (ms * 1e-3) / 1e9, 1)}
+        log(f"offload {name}: {ms:.1f} ms/step, {res[name]}")
+        del dev, host
+        torch.cuda.empty_cache()
+    # a plain pinned copy of the same volume, for the link's reference rate
+    nb = 1 << 30
+    hsrc = torch.empty(nb, dtype=torch.uint8, pin_memory=True)
+    dd = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    dd.copy_(hsrc, non_blocking=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    dd.copy_(hsrc, non_blocking=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    res["pinned_copy_h2d_GB/s"] = round(nb / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    return res
 
 
 def cpu_baseline(ps, store, budget_s):

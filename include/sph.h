@@ -274,6 +274,23 @@ sph_status sph_graph_launch(void *graph_exec, void *stream);
 void sph_graph_destroy(void *graph_exec);
 
 /* ---------------------------------------------------------------------- */
+/* Offload form (Sec. 2.3's launch: H2D, compute, D2H).  `host` is the      */
+/* authoritative store in pinned host memory, `dev` a device store of the   */
+/* same layout.  For each loop: copy host -> device every substruct holding  */
+/* a field the loop's pack reads, or holding one of its outputs together    */
+/* with other fields; run pack -> interaction -> unpack (batched form); copy */
+/* device -> host every substruct holding one of the loop's outputs.  All    */
+/* copies are stream-ordered hipMemcpyAsync.                                 */
+/* ---------------------------------------------------------------------- */
+/* Bytes moved each way for one loop over n particles of a layout. */
+sph_status sph_offload_bytes(sph_layout layout, sph_loop loop, int64_t n, size_t *h2d_bytes,
+                             size_t *d2h_bytes);
+/* One offload step (density, gradient, force).  ws as for sph_step_batched. */
+sph_status sph_offload_step(const sph_plan *plan, const sph_store *host, const sph_store *dev,
+                            const sph_params *params, const sph_tuning *tuning, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Adjoint of L = sum_i |a_i|^2 through density and force (hand-written).   */
 /* The artificial-viscosity switch alpha~ = alpha_v B and alpha_d are held  */
 /* fixed; h and u are constants.  Density is recomputed in backward.        */

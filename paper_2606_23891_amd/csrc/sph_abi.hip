@@ -756,6 +756,42 @@ sph_status sph_step_batched(const sph_plan *p, const sph_store *store, const sph
     return step_batched(p, store, prm, tn, ws, ws_bytes, (hipStream_t)stream);
 }
 
+// ---------------------------------------------------------------------------
+// offload form
+// ---------------------------------------------------------------------------
+// fields each loop's pack reads (Table 1, extended as for the pack records)
+static const int kReadFields[3][11] = {{FX, FMASS, FH, -1},
+                                       {FX, FV, FMASS, FH, FU, FRHO, -1},
+                                       {FX, FV, FMASS, FH, FU, FRHO, FRHODH, FDIV, FROT, FAV, FAD}};
+
+static bool loop_reads(int loop, int f)
+{
+    for (int k = 0; k < 11 && kReadFields[loop][k] >= 0; ++k)
+        if (kReadFields[loop][k] == f) return true;
+    return false;
+}
+static bool loop_writes(int loop, int f)
+{
+    for (int k = 0; k < kResPlanes[loop]; ++k)
+        if (kOutField[loop][k] == f) return true;
+    return false;
+}
+
+// per substruct: 1 = copy to the device, 2 = copy back, both bits possible
+static void offload_plan(int layout, int loop, int flags[kMaxSub])
+{
+    const LayoutDesc &d = kLayouts[layout];
+    bool rd[kMaxSub] = {}, out[kMaxSub] = {}, other[kMaxSub] = {};
+    for (int f = 0; f < NFIELD; ++f)
+        for (int c = 0; c < kNComp[f]; ++c) {
+            const int s = d.sub[f][c];
+            if (loop_reads(loop, f)) rd[s] = true;
+            if (loop_writes(loop, f)) out[s] = true;
+            else other[s] = true;
+        }
+    for (int s = 0; s < d.nsub; ++s) flags[s] = ((rd[s] || (out[s] && other[s])) ? 1 : 0) | (out[s] ? 2 : 0);
+}
+
 struct GraphHandle {
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -789,6 +825,64 @@ sph_status sph_graph_capture(const sph_plan *p, const sph_store *store, const sp
         return hip_fail(e, "hipGraphInstantiate");
     }
     *graph_exec = new GraphHandle{g, ex};
+    return SPH_OK;
+}
+
+sph_status sph_offload_bytes(sph_layout layout, sph_loop loop, int64_t n, size_t *h2d, size_t *d2h)
+{
+    if ((int)layout < 0 || (int)layout >= kNLayouts) return fail(SPH_E_LAYOUT, "unknown layout");
+    sph_status s;
+    if ((s = check_loop(loop))) return s;
+    if (!h2d || !d2h || n < 0) return fail(SPH_E_ARG, "bad argument");
+    int fl[kMaxSub];
+    offload_plan(layout, loop, fl);
+    size_t a = 0, b = 0;
+    for (int k = 0; k < kLayouts[layout].nsub; ++k) {
+        const size_t bytes = (size_t)n * kLayouts[layout].sub_bytes[k];
+        if (fl[k] & 1) a += bytes;
+        if (fl[k] & 2) b += bytes;
+    }
+    *h2d = a;
+    *d2h = b;
+    return SPH_OK;
+}
+
+sph_status sph_offload_step(const sph_plan *p, const sph_store *host, const sph_store *dev, const sph_params *prm,
+                            const sph_tuning *tn, void *ws, size_t ws_bytes, void *stream)
+{
+    sph_status s;
+    if ((s = batched_checks(p, 0)) || (s = check_store(host)) || (s = check_store(dev)) || (s = check_tuning(tn)))
+        return s;
+    if (!prm) return fail(SPH_E_ARG, "params is null");
+    if (host->layout != dev->layout || host->n != p->n || dev->n != p->n)
+        return fail(SPH_E_ARG, "host and device stores must share the plan's size and one layout");
+    size_t need = 0;
+    sph_batched_ws_bytes(p, &need);
+    if (!ws || !aligned256(ws)) return fail(SPH_E_ARG, "workspace null or misaligned");
+    if (ws_bytes < need) return fail(SPH_E_CAPACITY, "workspace needs " + std::to_string(need) + " bytes");
+    if (p->n == 0) return SPH_OK;
+    sph_tuning def;
+    sph_tuning_default(&def);
+    if (!tn) tn = &def;
+    hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)ws;
+    void *q = base;
+    void *pack = base + 256;
+    void *res = base + 256 + pack_bytes_for(2, p->n, p->ntile);
+    const LayoutDesc &d = kLayouts[host->layout];
+    for (int loop = 0; loop < 3; ++loop) {
+        int fl[kMaxSub];
+        offload_plan(host->layout, loop, fl);
+        for (int k = 0; k < d.nsub; ++k)
+            if (fl[k] & 1)
+                SPH_HIP(hipMemcpyAsync(dev->sub[k], host->sub[k], (size_t)p->n * d.sub_bytes[k], hipMemcpyHostToDevice, st));
+        if ((s = launch_pack(p, loop, dev, true, 0, 0, pack, tn->pack_waves, st))) return s;
+        if ((s = launch_interact(p, loop, true, 0, p->ntask, pack, prm, tn, res, nullptr, q, st))) return s;
+        if ((s = launch_unpack(const_cast<sph_plan *>(p), loop, res, true, 0, 0, dev, tn->pack_waves, st))) return s;
+        for (int k = 0; k < d.nsub; ++k)
+            if (fl[k] & 2)
+                SPH_HIP(hipMemcpyAsync(host->sub[k], dev->sub[k], (size_t)p->n * d.sub_bytes[k], hipMemcpyDeviceToHost, st));
+    }
     return SPH_OK;
 }
 

@@ -89,6 +89,8 @@ _SIGS = {
     "sph_graph_capture": ([vp, vp, vp, vp, vp, sz, C.POINTER(vp)], i32),
     "sph_graph_launch": ([vp, vp], i32),
     "sph_graph_destroy": ([vp], None),
+    "sph_offload_bytes": ([i32, i32, i64, C.POINTER(sz), C.POINTER(sz)], i32),
+    "sph_offload_step": ([vp, vp, vp, vp, vp, vp, sz, vp], i32),
     "sph_adjoint_ws_bytes": ([vp, C.POINTER(sz)], i32),
     "sph_adjoint_forward": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp], i32),
     "sph_force_adjoint": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz,
@@ -177,13 +179,18 @@ def sph_pack_layout(loop: int):
 # device objects
 # ---------------------------------------------------------------------------
 class Store:
-    """A particle store of one layout, substructs held as torch uint8 tensors."""
+    """A particle store of one layout, substructs held as torch uint8 tensors
+    (device memory, or pinned host memory with device="pinned")."""
 
     def __init__(self, layout: int, n: int, device="cuda"):
         import torch
         self.layout, self.n = layout, n
         self.sub_bytes = sph_layout_info(layout)
-        self.subs = [torch.zeros(max(1, n * b), dtype=torch.uint8, device=device) for b in self.sub_bytes]
+        if device == "pinned":
+            self.subs = [torch.zeros(max(1, n * b) + 256, dtype=torch.uint8, pin_memory=True) for b in self.sub_bytes]
+            self.subs = [_aligned_view(t, max(1, n * b)) for t, b in zip(self.subs, self.sub_bytes)]
+        else:
+            self.subs = [torch.zeros(max(1, n * b), dtype=torch.uint8, device=device) for b in self.sub_bytes]
         self.c = sph_store()
         self.c.layout = layout
         self.c.nsub = len(self.subs)
@@ -202,6 +209,8 @@ class Store:
 
     def get(self, name: str, stream=None) -> np.ndarray:
         import torch
+        if not self.subs[0].is_cuda:
+            raise RuntimeError("field access of a host store: use sph_store_get on a device copy")
         nc, cb = sph_field_info(FIELD_ID[name])
         dt = {("x", 8): torch.float64, ("id", 8): torch.int64, ("cold", 8): torch.int64}.get(
             (name, cb), {4: torch.float32, 1: torch.int8}.get(cb))
@@ -221,6 +230,12 @@ class Store:
         import torch
         torch.cuda.synchronize()
         return b"".join(t[: self.n * b].cpu().numpy().tobytes() for t, b in zip(self.subs, self.sub_bytes))
+
+
+def _aligned_view(t, nbytes: int):
+    """a 256-byte aligned view of nbytes inside the host tensor t"""
+    off = (-t.data_ptr()) % 256
+    return t[off:off + nbytes]
 
 
 class Plan:
@@ -371,6 +386,19 @@ def sph_step_batched(plan, store, ws, params=None, tuning=None, stream=None):
     p = params if params is not None else default_params()
     _check(lib().sph_step_batched(_h(plan), _s(store), C.byref(p), C.byref(tuning) if tuning else None,
                                   _ptr(ws), _nbytes(ws), _stream(stream)), "sph_step_batched")
+
+
+def sph_offload_bytes(layout: int, loop: int, n: int):
+    a, b = sz(), sz()
+    _check(lib().sph_offload_bytes(layout, loop, n, C.byref(a), C.byref(b)), "sph_offload_bytes")
+    return a.value, b.value
+
+
+def sph_offload_step(plan, host_store, dev_store, ws, params=None, tuning=None, stream=None):
+    p = params if params is not None else default_params()
+    _check(lib().sph_offload_step(_h(plan), _s(host_store), _s(dev_store), C.byref(p),
+                                  C.byref(tuning) if tuning else None, _ptr(ws), _nbytes(ws), _stream(stream)),
+           "sph_offload_step")
 
 
 class Graph:
