@@ -115,7 +115,7 @@ def test_offload_step_matches_resident_step(layout):
     D2H of the output substructs reproduces the resident batched step bit for
     bit, and leaves every other field of the host store untouched"""
     import torch
-    ps = inputs.make_config(1, n_side=24)
+    ps = inputs.make_config(1, n_side=32)
     lay = sph.LAYOUTS.index(layout)
     f = dict(ps.fields)
     extra = inputs.random_fields(ps.n, 21, x=f["x"])
