@@ -35,6 +35,8 @@ PAIR_FLOPS = {0: 32, 1: 55, 2: 81}
 # outputs written
 PACK_BYTES = {0: 32 + 20 + 0.5, 1: 52 + 40 + 0.5, 2: 80 + 68 + 0.5}
 UNPACK_BYTES = {0: 12 + 12, 1: 24 + 24, 2: 16 + 16}
+# interaction kernel: its packed records read once + its result planes written
+INTERACT_BYTES = {0: 20 + 0.5 + 12, 1: 40 + 0.5 + 24, 2: 68 + 0.5 + 16}
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 LOOP_NAME = {0: "density", 1: "gradient", 2: "force"}
@@ -62,10 +64,40 @@ def parse():
                     help="'all' or comma list: also time pack + unpack of every loop per store layout")
     ap.add_argument("--offload", default=None,
                     help="'all' or comma list of layouts: also time the offload form (pinned host store)")
+    ap.add_argument("--copy-mib", type=int, default=1024,
+                    help="size of the plain elementwise copy timed after the step (the achievable-HBM "
+                         "reference, and the calibration dispatch of HBM-traffic counter runs)")
     ap.add_argument("--tuning", default="auto",
                     help="auto (the tuner's cache for this device and workload, else defaults), "
                          "default, or a JSON file with sph_tuning fields")
     return ap.parse_args()
+
+
+TRAFFIC_SUMMARY = "hbm_traffic_gresho256.md"
+
+
+def stage_kernel(stage, layout, tuning):
+    """the kernel a batched stage launches (its demangled name)"""
+    for L, nm in LOOP_NAME.items():
+        if stage == f"pack_{nm}":
+            return f"void sph::k_pack<{layout}, {L}>(sph::PackArgs)"
+        if stage == f"unpack_{nm}":
+            return f"void sph::k_unpack_chunks<{layout}, {L}, true>(sph::UnpackArgs)"
+        if stage == nm:
+            return f"void sph::k_interact<{L}, 1, {tuning.window[L]}>(sph::InteractArgs)"
+    raise KeyError(stage)
+
+
+def stage_bytes(stage, n):
+    """algorithmic HBM bytes of one launch of a batched stage"""
+    for L, nm in LOOP_NAME.items():
+        if stage == f"pack_{nm}":
+            return PACK_BYTES[L] * n
+        if stage == f"unpack_{nm}":
+            return UNPACK_BYTES[L] * n
+        if stage == nm:
+            return INTERACT_BYTES[L] * n
+    raise KeyError(stage)
 
 
 def workload_name(k, ps):
@@ -107,7 +139,7 @@ def main():
     tuning = sph.default_tuning()
     tuned_from = "defaults"
     if a.tuning == "auto":
-        entry = tune.load(dev.name, tune.signature(ps, a.layout))
+        entry = tune.load(tune.device_key(dev), tune.signature(ps, a.layout))
         if entry:
             tune.apply(tuning, entry)
             tuned_from = "tuning cache"
@@ -197,14 +229,23 @@ def main():
         roof = {"kernel": dom, "bound": "alu", "achieved": stages[dom]["TFLOP/s"], "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    # HBM bytes per launch of that kernel from the committed counter summary of
+    # this workload, if it was taken from the current kernel sources
+    from paper_2606_23891_amd import profiling
+
+    wl = f"{workload_name(a.config, ps)}; {a.layout}"
+    tr = profiling.load_traffic(os.path.join(ROOT, "profiles", TRAFFIC_SUMMARY), wl)
+    kname = stage_kernel(dom, layout, tuning)
+    roof["traffic"] = tr["kernels"][kname]["bytes"] if tr and kname in tr["kernels"] else None
+    roof["traffic_unit"] = "bytes per launch"
+    roof["algorithmic_bytes"] = stage_bytes(dom, n)
 
     out = {
         "metric": METRIC, "value": value, "unit": "pair interactions/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": workload_name(a.config, ps), "layout": a.layout, "form": "batched",
-                   "pairs_per_step": total_pairs, "device": dev.name, "cu": dev.multi_processor_count,
+                   "pairs_per_step": total_pairs, "device": tune.device_key(dev), "cu": dev.multi_processor_count,
                    "tuning": {"source": tuned_from, "blocks_per_cu": tuning.blocks_per_cu,
                               "window": list(tuning.window), "queue": tuning.queue,
                               "pack_waves": tuning.pack_waves}},
@@ -213,6 +254,21 @@ def main():
                    for k, v in stages.items()},
         "roofline": roof,
     }
+
+    # a plain elementwise copy (read + write of copy_mib MiB each) on the same stream
+    if a.copy_mib > 0:
+        src = torch.zeros(a.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.neg(src, out=dst)
+        e0.record(stream)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out["hbm_copy_GBps"] = 2 * (a.copy_mib << 20) * 3 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        log(f"plain copy: {out['hbm_copy_GBps']:.0f} GB/s")
+        del src, dst
 
     # the same step as one captured graph
     if not a.no_graph:
@@ -396,11 +452,17 @@ def cpu_baseline(ps, store, budget_s):
     R = store.get("rot_v").astype(np.float64)
     rng = np.random.default_rng(0)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    rows = rng.choice(ps.n, 8, replace=False)
-    t0 = time.perf_counter()
-    c = _oracle_rows(oracle, f, rho, rdh, D, R, rows)
-    t1 = time.perf_counter() - t0
-    nrow = int(max(8, min(ps.n, 8 * budget_s / max(t1, 1e-3))))
+    # grow a probe until it runs long enough to time, then size the sample to the budget
+    nrow, t1 = 8, 0.0
+    while nrow < ps.n:
+        rows = rng.choice(ps.n, nrow, replace=False)
+        t0 = time.perf_counter()
+        _oracle_rows(oracle, f, rho, rdh, D, R, rows)
+        t1 = time.perf_counter() - t0
+        if t1 >= 0.5 or t1 >= budget_s / 4:
+            break
+        nrow *= 4
+    nrow = int(max(8, min(ps.n, nrow * budget_s / max(t1, 1e-3))))
     rows = rng.choice(ps.n, nrow, replace=False)
     t0 = time.perf_counter()
     c = _oracle_rows(oracle, f, rho, rdh, D, R, rows)

@@ -1,0 +1,220 @@
+"""Summaries of rocprofv3 runs of bench.py, and the HBM traffic figures that
+bench.py reports beside its roofline.
+
+HBM traffic per launch comes from two counter runs of the same bench command:
+``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE`` (KiB per dispatch).  Each counter
+is scaled by the ratio of a known byte count to what the same counter reads
+for a plain elementwise copy of that size (``bench.py --copy-mib``, the
+``torch.neg`` over a buffer much larger than the last-level cache), so the
+figures are in the copy's bytes.  The summary records a hash of the kernel
+sources and the workload; bench.py reports the figures only while both match.
+
+CLI (on the pulled rocprofv3 output directories):
+  python -m paper_2606_23891_amd.profiling stats  <kernel_stats.csv> --out F --command C --title T
+  python -m paper_2606_23891_amd.profiling traffic <fetch_dir> <write_dir> --copy-mib 1024 \
+      --workload W --out F --command-fetch C1 --command-write C2
+  python -m paper_2606_23891_amd.profiling sq <pmc_dir> [<pmc_dir> ...] --out F --command C
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+COPY_TAG = "neg_kernel"
+JSON_BEGIN = "<!-- traffic-json"
+JSON_END = "-->"
+
+
+def source_hash() -> str:
+    """sha256 over the kernel sources and the build flags"""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.hpp")))
+    files.append(os.path.join(HERE, "build.py"))
+    for p in files:
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _find_csv(d: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def read_counter(d: str, counter: str):
+    """kernel name -> list of per-dispatch values of one counter"""
+    path = _find_csv(d, "counter_collection.csv")
+    out = defaultdict(list)
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            out[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+    return dict(out)
+
+
+def read_counters(d: str):
+    """kernel name -> counter -> list of per-dispatch values (every counter of a run)"""
+    path = _find_csv(d, "counter_collection.csv")
+    out = defaultdict(lambda: defaultdict(list))
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            out[row["Kernel_Name"]][row["Counter_Name"]].append(float(row["Counter_Value"]))
+    return out
+
+
+def _mean(v):
+    return sum(v) / len(v)
+
+
+def traffic(fetch_dir: str, write_dir: str, copy_bytes: int) -> dict:
+    fe = read_counter(fetch_dir, "FETCH_SIZE")
+    wr = read_counter(write_dir, "WRITE_SIZE")
+    cf = [k for k in fe if COPY_TAG in k]
+    cw = [k for k in wr if COPY_TAG in k]
+    if len(cf) != 1 or len(cw) != 1:
+        raise RuntimeError(f"calibration copy not found once: {cf} {cw}")
+    # the copy reads and writes copy_bytes each; counters are KiB per dispatch
+    f_factor = copy_bytes / (_mean(fe[cf[0]]) * 1024.0)
+    w_factor = copy_bytes / (_mean(wr[cw[0]]) * 1024.0)
+    kern = {}
+    for k in sorted(set(fe) & set(wr)):
+        if not k.startswith("void sph::") and not k.startswith("sph::"):
+            continue
+        fb = _mean(fe[k]) * 1024.0 * f_factor
+        wb = _mean(wr[k]) * 1024.0 * w_factor
+        kern[k] = {"dispatches": len(fe[k]), "fetch_bytes": fb, "write_bytes": wb, "bytes": fb + wb}
+    return {"copy_bytes": copy_bytes, "fetch_factor": f_factor, "write_factor": w_factor,
+            "copy_fetch_KiB": _mean(fe[cf[0]]), "copy_write_KiB": _mean(wr[cw[0]]), "kernels": kern}
+
+
+def traffic_markdown(t: dict, workload: str, cmd_fetch: str, cmd_write: str, algo: dict | None = None) -> str:
+    t = dict(t, workload=workload, source_hash=source_hash())
+    lines = [f"# HBM traffic per launch: {workload}", "",
+             "Two counter runs of the same bench command (one counter each), on one MI355X from the "
+             "repository root:", "", "```", cmd_fetch, cmd_write, "```", "",
+             f"Calibration: one plain elementwise copy of {t['copy_bytes']} bytes (read and write) reads "
+             f"FETCH_SIZE {t['copy_fetch_KiB']:.0f} KiB and WRITE_SIZE {t['copy_write_KiB']:.0f} KiB; "
+             f"factors {t['fetch_factor']:.4f} (fetch) and {t['write_factor']:.4f} (write) scale every "
+             "kernel's counters below.", "",
+             "| kernel | dispatches | fetch MB | write MB | total MB |" + (" algorithmic MB | ratio |" if algo else ""),
+             "|---|---|---|---|---|" + ("---|---|" if algo else "")]
+    for k, v in sorted(t["kernels"].items(), key=lambda kv: -kv[1]["bytes"]):
+        row = (f"| `{k}` | {v['dispatches']} | {v['fetch_bytes'] / 1e6:.1f} | {v['write_bytes'] / 1e6:.1f} | "
+               f"{v['bytes'] / 1e6:.1f} |")
+        if algo:
+            a = algo.get(k)
+            row += f" {a / 1e6:.1f} | {v['bytes'] / a:.2f} |" if a else " | |"
+        lines.append(row)
+    lines += ["", f"Kernel sources hash {t['source_hash']}.", "", JSON_BEGIN, json.dumps(t), JSON_END, ""]
+    return "\n".join(lines)
+
+
+def load_traffic(path: str, workload: str):
+    """the traffic summary at path if it matches these sources and workload, else None"""
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    i = txt.find(JSON_BEGIN)
+    if i < 0:
+        return None
+    j = txt.find(JSON_END, i)
+    try:
+        t = json.loads(txt[i + len(JSON_BEGIN):j])
+    except ValueError:
+        return None
+    if t.get("source_hash") != source_hash() or t.get("workload") != workload:
+        return None
+    return t
+
+
+def stats_markdown(stats_csv: str, title: str, command: str, note: str = "") -> str:
+    rows = list(csv.DictReader(open(stats_csv, newline="")))
+    lines = [f"# {title}", "", "Command (run on one MI355X from the repository root):", "", "```", command, "```", ""]
+    if note:
+        lines += [note, ""]
+    lines += ["| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"]
+        if len(name) > 70:
+            name = name[:67] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(lines) + "\n"
+
+
+def sq_markdown(dirs, title: str, commands, match: str = "sph::") -> str:
+    """per-kernel averages of every counter in one or more --pmc runs"""
+    table = defaultdict(dict)
+    names = []
+    for d in dirs:
+        for k, cs in read_counters(d).items():
+            if match not in k:
+                continue
+            for c, v in cs.items():
+                table[k][c] = _mean(v)
+                if c not in names:
+                    names.append(c)
+    lines = [f"# {title}", "", "Commands (each a run of its own, on one MI355X from the repository root):", "",
+             "```", *commands, "```", "", "Per-dispatch averages.", ""]
+    for k in sorted(table):
+        lines.append(f"## `{k}`")
+        lines.append("")
+        lines.append("| counter | value |")
+        lines.append("|---|---|")
+        for c in names:
+            if c in table[k]:
+                lines.append(f"| {c} | {table[k][c]:.6g} |")
+        lines.append("")
+    return "\n".join(lines)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--out", required=True)
+    s.add_argument("--title", required=True)
+    s.add_argument("--command", required=True)
+    s.add_argument("--note", default="")
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_dir")
+    t.add_argument("write_dir")
+    t.add_argument("--copy-mib", type=int, required=True)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--command-fetch", required=True)
+    t.add_argument("--command-write", required=True)
+    t.add_argument("--algo", default=None, help="JSON file: kernel name -> algorithmic bytes per launch")
+    q = sub.add_parser("sq")
+    q.add_argument("dirs", nargs="+")
+    q.add_argument("--out", required=True)
+    q.add_argument("--title", required=True)
+    q.add_argument("--command", action="append", required=True)
+    a = ap.parse_args()
+    if a.cmd == "stats":
+        txt = stats_markdown(a.csv, a.title, a.command, a.note)
+    elif a.cmd == "traffic":
+        algo = json.load(open(a.algo)) if a.algo else None
+        txt = traffic_markdown(traffic(a.fetch_dir, a.write_dir, a.copy_mib << 20), a.workload,
+                               a.command_fetch, a.command_write, algo)
+    else:
+        txt = sq_markdown(a.dirs, a.title, a.command)
+    with open(a.out, "w") as f:
+        f.write(txt)
+    print(f"wrote {a.out}")
+
+
+if __name__ == "__main__":
+    main()

@@ -27,6 +27,13 @@ QUEUE = (1, 0)
 PACK_WAVES = (1, 2, 4, 8)
 
 
+def device_key(props) -> str:
+    """the tuning cache's device key: ISA name and compute-unit count (the
+    marketing name is not reported under every tool, e.g. a profiler)"""
+    arch = getattr(props, "gcnArchName", "") or props.name
+    return f"{arch.split(':')[0]}-{props.multi_processor_count}cu"
+
+
 def signature(ps, layout_name: str) -> str:
     st = ps.meta
     return f"cfg{st.get('config')}-n{ps.n}-cells{len(ps.cells)}-tasks{len(ps.tasks)}-{layout_name}"
@@ -150,7 +157,7 @@ def main():
     plan = sph.Plan(ps.cells, ps.tasks, ps.n)
     store = sph.Store(sph.LAYOUTS.index(a.layout), ps.n)
     store.put_all(ps.fields)
-    dev = torch.cuda.get_device_properties(0).name
+    dev = device_key(torch.cuda.get_device_properties(0))
     sig = signature(ps, a.layout)
     log = lambda m: print(f"[tune {time.strftime('%H:%M:%S')}] {m}", file=sys.stderr, flush=True)
     best, times = tune(plan, store, log)
