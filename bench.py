@@ -151,7 +151,7 @@ def main():
     params = sph.default_params()
     stream = torch.cuda.current_stream()
     bufs = {L: sph.cell_buffers(plan, L) for L in range(3)}
-    ws = torch.zeros(1 << 12, dtype=torch.uint8, device="cuda")
+    ws = sph.interact_ws(plan)
 
     def stage(L, s):
         pack, res = bufs[L]

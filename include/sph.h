@@ -119,7 +119,11 @@ typedef struct sph_tuning {
     int32_t window[3];       /* candidate window per wave for density, gradient and
                                 force: 64, 128, 256 or 512 candidates              */
     int32_t pack_waves;      /* waves per block in pack / unpack kernels (1..8)     */
-    int32_t queue;           /* 1 = device work queue, 0 = static stride            */
+    int32_t queue;           /* 0 = static stride; 1 = one device work queue in
+                                descending cost order; 2 = one queue per XCD over
+                                a spatially contiguous share of the tiles (equal
+                                estimated cost each), stealing from the other
+                                shares once its own is drained                     */
     int32_t reserved[2];
 } sph_tuning;
 
@@ -256,11 +260,18 @@ sph_status sph_batched_ws_bytes(const sph_plan *plan, size_t *bytes);
 /* Individual stages (buffers as for the per-task path with P = n rounded up). */
 sph_status sph_pack_cells(const sph_plan *plan, sph_loop loop, const sph_store *store, void *pack_buf,
                           size_t pack_bytes, const sph_tuning *tuning, void *stream);
-/* ws: at least 256 bytes of device memory for the queue counter. */
+/* Workspace of sph_interact_cells for a loop: 256 bytes for the work-queue
+ * counter, then (gradient, force) per-particle planes of the quantities the
+ * pair terms derive from the packed fields (sound speed, m/rho; support and
+ * its inverse, A = P/(Omega rho^2), the Balsara-limited viscosity switch),
+ * computed once per particle by the same launch. */
+sph_status sph_interact_ws_bytes(const sph_plan *plan, sph_loop loop, size_t *bytes);
+/* ws: device memory of ws_bytes >= sph_interact_ws_bytes(loop), 256-byte
+ * aligned, owned by the caller; overwritten. */
 sph_status sph_interact_cells(const sph_plan *plan, sph_loop loop, const void *pack_buf,
                               size_t pack_bytes, const sph_params *params, const sph_tuning *tuning,
                               void *res_buf, size_t res_bytes, int32_t *counts, void *ws,
-                              void *stream);
+                              size_t ws_bytes, void *stream);
 /* out = +0.0f + result (V: the larger of +0.0f and the result). */
 sph_status sph_unpack_cells(const sph_plan *plan, sph_loop loop, const void *res_buf, size_t res_bytes,
                             const sph_store *store, const sph_tuning *tuning, void *stream);

@@ -383,7 +383,7 @@ sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task 
     std::vector<CellRange> cr(ncell);
     std::vector<int32_t> nbr_off(ncell + 1, 0);
     std::vector<Nbr> nbr;
-    std::vector<int32_t> items;
+    std::vector<int32_t> items, items_x;
     std::vector<int32_t> jt_off(ncell + 1, 0);
     std::vector<JTile> jt;
     if (ok) {
@@ -428,7 +428,10 @@ sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task 
         for (int32_t c = 0; c < ncell; ++c) {
             for (int32_t e = nbr_off[c]; e < nbr_off[c + 1]; ++e) {
                 const int32_t nc = nbr[e].cell;
-                for (int32_t t = 0; t < (cells[nc].count + 63) / 64; ++t) jt.push_back(JTile{cr[nc].tile0 + t, e});
+                for (int32_t t = 0; t < (cells[nc].count + 63) / 64; ++t) {
+                    const Chunk &tj = tiles[cr[nc].tile0 + t];
+                    jt.push_back(JTile{tj.slot0, cr[nc].tile0 + t, tj.n, nbr[e].dx, nbr[e].dy, nbr[e].dz, e});
+                }
             }
             jt_off[c + 1] = (int32_t)jt.size();
             p->max_jt = std::max(p->max_jt, jt_off[c + 1] - jt_off[c]);
@@ -445,6 +448,35 @@ sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task 
         std::iota(items.begin(), items.end(), 0);
         std::stable_sort(items.begin(), items.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
         p->ntile = (int32_t)tiles.size();
+        // per-XCD shares: contiguous tile ranges (store order, so spatially
+        // compact) of equal estimated cost, each in descending cost order
+        items_x.resize(tiles.size());
+        std::iota(items_x.begin(), items_x.end(), 0);
+        int64_t total = 0;
+        for (int64_t c : cost) total += c;
+        int64_t run = 0;
+        int32_t r = 0, start = 0;
+        for (int32_t i = 0; i <= p->ntile; ++i) {
+            const bool end = i == p->ntile;
+            if (!end) run += cost[i];
+            // close share r once it holds its fraction of the total (the last takes the rest)
+            while (r < kQueues - 1 && !end && run * kQueues >= total * (r + 1)) {
+                p->xoff[r] = start;
+                p->xlen[r] = i + 1 - start;
+                start = i + 1;
+                ++r;
+            }
+            if (end) {
+                for (; r < kQueues; ++r) {
+                    p->xoff[r] = start;
+                    p->xlen[r] = p->ntile - start;
+                    start = p->ntile;
+                }
+            }
+        }
+        for (int32_t q = 0; q < kQueues; ++q)
+            std::stable_sort(items_x.begin() + p->xoff[q], items_x.begin() + p->xoff[q] + p->xlen[q],
+                             [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
     }
 
     sph_status st;
@@ -459,7 +491,7 @@ sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task 
         p->num_cu = ncu;
     if ((st = upload(&p->d_cells, p->cells)) || (st = upload(&p->d_tasks, p->tasks)) ||
         (st = upload(&p->d_chunks, ch)) || (st = upload(&p->d_tiles, tiles)) || (st = upload(&p->d_cellr, cr)) ||
-        (st = upload(&p->d_nbr, nbr)) || (st = upload(&p->d_nbr_off, nbr_off)) || (st = upload(&p->d_items, items)) ||
+        (st = upload(&p->d_nbr, nbr)) || (st = upload(&p->d_nbr_off, nbr_off)) || (st = upload(&p->d_items, items)) || (st = upload(&p->d_items_x, items_x)) ||
         (st = upload(&p->d_jt_off, jt_off)) || (st = upload(&p->d_jt, jt))) {
         sph_plan_destroy(p);
         return st;
@@ -473,7 +505,7 @@ void sph_plan_destroy(sph_plan *p)
     if (!p) return;
     (void)hipSetDevice(p->device);
     void *ptrs[] = {p->d_cells, p->d_tasks, p->d_chunks, p->d_tiles, p->d_cellr, p->d_nbr,
-                    p->d_nbr_off, p->d_items, p->d_jt_off, p->d_jt, p->d_csr_off, p->d_csr};
+                    p->d_nbr_off, p->d_items, p->d_items_x, p->d_jt_off, p->d_jt, p->d_csr_off, p->d_csr};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -658,6 +690,7 @@ static sph_status check_tuning(const sph_tuning *t)
         if (t->window[k] != 64 && t->window[k] != 128 && t->window[k] != 256 && t->window[k] != 512)
             return fail(SPH_E_ARG, "window must be 64, 128, 256 or 512");
     if (t->pack_waves < 1 || t->pack_waves > 8) return fail(SPH_E_ARG, "pack_waves outside 1..8");
+    if (t->queue < 0 || t->queue > 2) return fail(SPH_E_ARG, "queue must be 0, 1 or 2");
     return SPH_OK;
 }
 
@@ -673,8 +706,18 @@ static sph_status batched_checks(const sph_plan *p, int loop)
 sph_status sph_batched_ws_bytes(const sph_plan *p, size_t *bytes)
 {
     if (!p || !bytes) return fail(SPH_E_ARG, "null argument");
-    // queue counters + the largest pack buffer + the largest result buffer
-    *bytes = 256 + pack_bytes_for(2, p->n, p->ntile) + result_bytes_for(1, p->n);
+    // interaction workspace (queue + derived planes) of the force loop, the
+    // largest pack buffer and the largest result buffer
+    *bytes = interact_ws_bytes_for(2, p->n) + pack_bytes_for(2, p->n, p->ntile) + result_bytes_for(1, p->n);
+    return SPH_OK;
+}
+
+sph_status sph_interact_ws_bytes(const sph_plan *p, sph_loop loop, size_t *bytes)
+{
+    if (!p || !bytes) return fail(SPH_E_ARG, "null argument");
+    sph_status s;
+    if ((s = check_loop(loop))) return s;
+    *bytes = interact_ws_bytes_for(loop, p->n);
     return SPH_OK;
 }
 
@@ -692,13 +735,15 @@ sph_status sph_pack_cells(const sph_plan *p, sph_loop loop, const sph_store *sto
 
 sph_status sph_interact_cells(const sph_plan *p, sph_loop loop, const void *pack_buf, size_t pack_bytes,
                               const sph_params *prm, const sph_tuning *tn, void *res_buf, size_t res_bytes,
-                              int32_t *counts, void *ws, void *stream)
+                              int32_t *counts, void *ws, size_t ws_bytes, void *stream)
 {
     sph_status s;
     if ((s = batched_checks(p, loop)) || (s = check_tuning(tn))) return s;
     if (!prm) return fail(SPH_E_ARG, "params is null");
     if (p->n == 0) return SPH_OK;
     if (!pack_buf || !res_buf || !ws) return fail(SPH_E_ARG, "null buffer or workspace");
+    if (ws_bytes < interact_ws_bytes_for(loop, p->n))
+        return fail(SPH_E_CAPACITY, "workspace needs " + std::to_string(interact_ws_bytes_for(loop, p->n)) + " bytes");
     if (!aligned256(pack_buf) || !aligned256(res_buf) || !aligned256(ws))
         return fail(SPH_E_ARG, "buffer not 256-byte aligned");
     if (pack_bytes < pack_bytes_for(loop, p->n, p->ntile)) return fail(SPH_E_CAPACITY, "pack buffer too small");
@@ -738,9 +783,9 @@ static sph_status step_batched(const sph_plan *p, const sph_store *store, const 
     sph_tuning_default(&def);
     if (!tn) tn = &def;
     char *base = (char *)ws;
-    void *q = base;
-    void *pack = base + 256;
-    void *res = base + 256 + pack_bytes_for(2, p->n, p->ntile);
+    void *q = base;  // queue counter, then the derived planes
+    void *pack = base + interact_ws_bytes_for(2, p->n);
+    void *res = (char *)pack + pack_bytes_for(2, p->n, p->ntile);
     for (int loop = 0; loop < 3; ++loop) {
         if ((s = launch_pack(p, loop, store, true, 0, 0, pack, tn->pack_waves, st))) return s;
         if ((s = launch_interact(p, loop, true, 0, p->ntask, pack, prm, tn, res, nullptr, q, st))) return s;
@@ -866,9 +911,9 @@ sph_status sph_offload_step(const sph_plan *p, const sph_store *host, const sph_
     if (!tn) tn = &def;
     hipStream_t st = (hipStream_t)stream;
     char *base = (char *)ws;
-    void *q = base;
-    void *pack = base + 256;
-    void *res = base + 256 + pack_bytes_for(2, p->n, p->ntile);
+    void *q = base;  // queue counter, then the derived planes
+    void *pack = base + interact_ws_bytes_for(2, p->n);
+    void *res = (char *)pack + pack_bytes_for(2, p->n, p->ntile);
     const LayoutDesc &d = kLayouts[host->layout];
     for (int loop = 0; loop < 3; ++loop) {
         int fl[kMaxSub];

@@ -30,9 +30,21 @@
 //     cells of the cell, each translated into its frame; results are final.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "sph_internal.hpp"
 
 namespace sph {
+
+// compile-time loop: fn(integral_constant<int, I>) for I in [I0, N)
+template <int I, int N, class Fn>
+__device__ __forceinline__ void unroll(Fn &&fn)
+{
+    if constexpr (I < N) {
+        fn(std::integral_constant<int, I>{});
+        unroll<I + 1, N>(fn);
+    }
+}
 
 struct InteractArgs {
     const char *pack;
@@ -45,27 +57,38 @@ struct InteractArgs {
     int64_t slot_base;          // MODE 0
     int64_t nitems;
     const int32_t *items;       // MODE 1: tile order
+    const int32_t *items_x;     // MODE 1: tile order of the per-XCD shares
     const CellRange *cellr;
     const Nbr *nbr;
     const int32_t *nbr_off;
     const int32_t *jt_off;      // MODE 1: per cell j-tile list
     const JTile *jt;
     int32_t *queue;
-    int32_t use_queue;
+    const float *q;             // MODE 1, gradient and force: derived planes
+    int32_t use_queue;          // 0 static stride, 1 one queue, 2 per-XCD shares
+    int32_t xoff[kQueues], xlen[kQueues];  // use_queue 2: shares of items
+
     float gam, beta, eps;
 };
 
-__device__ __forceinline__ float wmin(float v)
+// lane-shuffled copy of v (DPP); rows outside ROW_MASK keep v
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp(float v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-    return v;
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
 }
-__device__ __forceinline__ float wmax(float v)
+
+// maximum over the 64 lanes of a converged wave, returned uniform: quad swaps,
+// half-row and row mirrors, then row broadcasts carry the result to lane 63
+__device__ __forceinline__ float wave_max_u(float v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
+    v = fmaxf(v, dpp<0xB1>(v));       // quad_perm [1,0,3,2]
+    v = fmaxf(v, dpp<0x4E>(v));       // quad_perm [2,3,0,1]
+    v = fmaxf(v, dpp<0x141>(v));      // row_half_mirror
+    v = fmaxf(v, dpp<0x140>(v));      // row_mirror
+    v = fmaxf(v, dpp<0x142, 0xA>(v)); // row_bcast15
+    v = fmaxf(v, dpp<0x143, 0xC>(v)); // row_bcast31
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // wave-scope ordering of LDS traffic between lanes of one wave
@@ -155,7 +178,42 @@ struct Acc {
     int32_t n;
 };
 
-template <int LOOP>
+// Per-particle quantities the pair terms need beyond the packed fields: for
+// the gradient loop {u, m/rho, c}; for the force loop {H, 1/H, A = P/(Omega
+// rho^2), c}, {H^-5 (8/pi), alpha~ = alpha_v B (Balsara), alpha_d, rho} and
+// {u, H^2}.  The batched form computes them once per particle (k_prep) into
+// derived planes; the per-task form computes them when it stages a particle.
+__device__ __forceinline__ float4 derive_gradient(const float4 &p1, const float2 &p2, float g)
+{
+    return make_float4(p2.x, p1.w / p2.y, sqrtf(g * (g - 1.0f) * p2.x), 0.f);
+}
+
+struct ForceDerived {
+    float4 q0, q1;
+    float2 q2;
+};
+
+__device__ __forceinline__ ForceDerived derive_force(const float4 &p0, const float4 &p2, const float4 &p3, float ad,
+                                                     float g, float eps)
+{
+    const float h = p0.w, u = p2.x, rho = p2.y, rdh = p2.z, D = p2.w;
+    const float H = kGammaK * h, ih = 1.0f / H;
+    const float A = (g - 1.0f) * u / (rho + h * rdh * (1.0f / 3.0f));  // P / (Omega rho^2)
+    const float c = sqrtf(g * (g - 1.0f) * u);
+    const float irho = 1.0f / rho;
+    const float div = fabsf(D * irho);
+    const float curl = sqrtf(p3.x * p3.x + p3.y * p3.y + p3.z * p3.z) * irho;
+    const float at = p3.w * div / (div + curl + eps * c / h);
+    ForceDerived f;
+    f.q0 = make_float4(H, ih, A, c);
+    f.q1 = make_float4(kC3 * ih * ih * ih * ih * ih, at, ad, rho);
+    f.q2 = make_float2(u, H * H);
+    return f;
+}
+
+// derived planes of the batched form: float4 planes at q and q + 4P, a float2
+// plane at q + 8P (force); one float4 plane (gradient)
+template <int LOOP, bool PREP>
 __device__ __forceinline__ void load_i(const InteractArgs &a, int64_t slot, bool valid, IData &d)
 {
     d.slot = (int32_t)slot;
@@ -171,110 +229,134 @@ __device__ __forceinline__ void load_i(const InteractArgs &a, int64_t slot, bool
     d.x = p0.x;
     d.y = p0.y;
     d.z = p0.z;
-    d.H = kGammaK * p0.w;
-    d.H2 = d.H * d.H;
-    d.invH = 1.0f / d.H;
     const float g = a.gam;
+    if constexpr (LOOP == 2) {
+        ForceDerived f;
+        if constexpr (PREP) {
+            f.q0 = ((const float4 *)a.q)[slot];
+            f.q1 = ((const float4 *)(a.q + 4 * a.P))[slot];
+            f.q2 = ((const float2 *)(a.q + 8 * a.P))[slot];
+        } else {
+            const float4 p2 = ((const float4 *)(a.pack + a.P * 32))[slot];
+            const float4 p3 = ((const float4 *)(a.pack + a.P * 48))[slot];
+            const float ad = ((const float *)(a.pack + a.P * 64))[slot];
+            f = derive_force(p0, p2, p3, ad, g, a.eps);
+        }
+        d.H = f.q0.x;
+        d.invH = f.q0.y;
+        d.A = f.q0.z;
+        d.c = f.q0.w;
+        d.K5 = f.q1.x;
+        d.at = f.q1.y;
+        d.ad = f.q1.z;
+        d.rho = f.q1.w;
+        d.u = f.q2.x;
+        d.H2 = f.q2.y;
+    } else {
+        d.H = kGammaK * p0.w;
+        d.H2 = d.H * d.H;
+        d.invH = 1.0f / d.H;
+    }
     if constexpr (LOOP >= 1) {
         const float4 p1 = ((const float4 *)(a.pack + a.P * 16))[slot];
         d.vx = p1.x;
         d.vy = p1.y;
         d.vz = p1.z;
         if constexpr (LOOP == 1) {
-            const float2 p2 = ((const float2 *)(a.pack + a.P * 32))[slot];
-            d.u = p2.x;
-        } else {
-            const float4 p2 = ((const float4 *)(a.pack + a.P * 32))[slot];
-            const float4 p3 = ((const float4 *)(a.pack + a.P * 48))[slot];
-            const float ad = ((const float *)(a.pack + a.P * 64))[slot];
-            const float h = p0.w, u = p2.x, rho = p2.y, rdh = p2.z, D = p2.w;
-            d.u = u;
-            d.rho = rho;
-            d.ad = ad;
-            const float ih = d.invH;
-            d.K5 = kC3 * ih * ih * ih * ih * ih;
-            const float omega_rho = rho + h * rdh * (1.0f / 3.0f);  // Omega * rho
-            d.A = (g - 1.0f) * u / omega_rho;
-            const float c = sqrtf(g * (g - 1.0f) * u);
-            const float irho = 1.0f / rho;
-            const float div = fabsf(D * irho);
-            const float curl = sqrtf(p3.x * p3.x + p3.y * p3.y + p3.z * p3.z) * irho;
-            d.at = p3.w * div / (div + curl + a.eps * c / h);
-            d.c = c;
+            float4 q;
+            if constexpr (PREP) q = ((const float4 *)a.q)[slot];
+            else q = derive_gradient(p1, ((const float2 *)(a.pack + a.P * 32))[slot], g);
+            d.u = q.x;
+            d.c = q.z;
         }
-        if constexpr (LOOP == 1) d.c = sqrtf(g * (g - 1.0f) * d.u);
     }
 }
 
-// the packed record of one j particle, held in registers between its load and
-// its staging (loaded one tile ahead of use)
-template <int LOOP>
+// the record of one j particle, held in registers between its load and its
+// staging: packed fields, plus the derived planes in the batched form
+template <int LOOP, bool PREP>
 struct JRec;
-template <>
-struct JRec<0> {
+template <bool PREP>
+struct JRec<0, PREP> {
     float4 p0;
     float m;
 };
 template <>
-struct JRec<1> {
+struct JRec<1, false> {
     float4 p0, p1;
     float2 p2;
 };
 template <>
-struct JRec<2> {
+struct JRec<1, true> {
+    float4 p0, p1, q0;
+};
+template <>
+struct JRec<2, false> {
     float4 p0, p1, p2, p3;
     float ad;
 };
+template <>
+struct JRec<2, true> {
+    float4 p0, p1, q0, q1;
+    float2 q2;
+};
 
-template <int LOOP>
-__device__ __forceinline__ void load_j(const InteractArgs &a, int64_t js, bool ok, JRec<LOOP> &r)
+// loads of one j record; js is always a slot inside the buffer (the caller
+// clamps lanes beyond the tile to its first slot)
+template <int LOOP, bool PREP>
+__device__ __forceinline__ void load_j(const InteractArgs &a, int64_t js, JRec<LOOP, PREP> &r)
 {
-    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    r.p0 = ((const float4 *)a.pack)[js];
     if constexpr (LOOP == 0) {
-        r.p0 = ok ? ((const float4 *)a.pack)[js] : z4;
-        r.m = ok ? ((const float *)(a.pack + a.P * 16))[js] : 0.f;
-    } else if constexpr (LOOP == 1) {
-        r.p0 = ok ? ((const float4 *)a.pack)[js] : z4;
-        r.p1 = ok ? ((const float4 *)(a.pack + a.P * 16))[js] : z4;
-        r.p2 = ok ? ((const float2 *)(a.pack + a.P * 32))[js] : make_float2(0.f, 0.f);
+        r.m = ((const float *)(a.pack + a.P * 16))[js];
     } else {
-        r.p0 = ok ? ((const float4 *)a.pack)[js] : z4;
-        r.p1 = ok ? ((const float4 *)(a.pack + a.P * 16))[js] : z4;
-        r.p2 = ok ? ((const float4 *)(a.pack + a.P * 32))[js] : z4;
-        r.p3 = ok ? ((const float4 *)(a.pack + a.P * 48))[js] : z4;
-        r.ad = ok ? ((const float *)(a.pack + a.P * 64))[js] : 0.f;
+        r.p1 = ((const float4 *)(a.pack + a.P * 16))[js];
+        if constexpr (LOOP == 1 && PREP) {
+            r.q0 = ((const float4 *)a.q)[js];
+        } else if constexpr (LOOP == 1) {
+            r.p2 = ((const float2 *)(a.pack + a.P * 32))[js];
+        } else if constexpr (PREP) {
+            r.q0 = ((const float4 *)a.q)[js];
+            r.q1 = ((const float4 *)(a.q + 4 * a.P))[js];
+            r.q2 = ((const float2 *)(a.q + 8 * a.P))[js];
+        } else {
+            r.p2 = ((const float4 *)(a.pack + a.P * 32))[js];
+            r.p3 = ((const float4 *)(a.pack + a.P * 48))[js];
+            r.ad = ((const float *)(a.pack + a.P * 64))[js];
+        }
     }
 }
 
 // stage candidate j (record r, pack slot js, translated by (tx,ty,tz) and
 // shifted to the i-tile centre (cx,cy,cz)) at LDS index k
-template <int LOOP, int WIN>
+template <int LOOP, bool PREP, int WIN>
 __device__ __forceinline__ void stage_j(const InteractArgs &a, Lds<LOOP, WIN> &L, int k, int64_t js,
-                                        const JRec<LOOP> &r, float tx, float ty, float tz, float cx, float cy,
-                                        float cz)
+                                        const JRec<LOOP, PREP> &r, float tx, float ty, float tz, float cx,
+                                        float cy, float cz)
 {
-    const float g = a.gam;
     const float x = (r.p0.x + tx) - cx, y = (r.p0.y + ty) - cy, z = (r.p0.z + tz) - cz;
     L.jslot[k] = (int32_t)js;
     L.ph[k] = make_float4(x, y, z, -fmaf(z, z, fmaf(y, y, x * x)));
     if constexpr (LOOP == 0) {
         L.m[k] = r.m;
-    } else if constexpr (LOOP == 1) {
-        L.c1[k] = r.p1;
-        L.c2[k] = make_float4(r.p2.x, r.p1.w / r.p2.y, sqrtf(g * (g - 1.0f) * r.p2.x), 0.f);
     } else {
-        const float h = r.p0.w, u = r.p2.x, rho = r.p2.y, rdh = r.p2.z, D = r.p2.w;
-        const float H = kGammaK * h, ih = 1.0f / H;
-        const float A = (g - 1.0f) * u / (rho + h * rdh * (1.0f / 3.0f));
-        const float c = sqrtf(g * (g - 1.0f) * u);
-        const float irho = 1.0f / rho;
-        const float div = fabsf(D * irho);
-        const float curl = sqrtf(r.p3.x * r.p3.x + r.p3.y * r.p3.y + r.p3.z * r.p3.z) * irho;
-        const float at = r.p3.w * div / (div + curl + a.eps * c / h);
-        L.c1[k] = r.p1;
-        L.c2[k] = make_float4(H, ih, A, c);
-        L.c3[k] = make_float4(kC3 * ih * ih * ih * ih * ih, at, r.ad, rho);
-        L.c4[k] = make_float2(u, H * H);
+        L.c1[k] = make_float4(r.p1.x, r.p1.y, r.p1.z, r.p1.w);
+        if constexpr (LOOP == 1) {
+            if constexpr (PREP) L.c2[k] = make_float4(r.q0.x, r.q0.y, r.q0.z, r.q0.w);
+            else L.c2[k] = derive_gradient(r.p1, r.p2, a.gam);
+        } else {
+            ForceDerived f;
+            if constexpr (PREP) {
+                f.q0 = r.q0;
+                f.q1 = r.q1;
+                f.q2 = r.q2;
+            } else {
+                f = derive_force(r.p0, r.p2, r.p3, r.ad, a.gam, a.eps);
+            }
+            L.c2[k] = make_float4(f.q0.x, f.q0.y, f.q0.z, f.q0.w);
+            L.c3[k] = make_float4(f.q1.x, f.q1.y, f.q1.z, f.q1.w);
+            L.c4[k] = make_float2(f.q2.x, f.q2.y);
+        }
     }
 }
 
@@ -402,7 +484,7 @@ __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, 
         const int kn = __builtin_amdgcn_readfirstlane(min(32, nc - kb));
         // shift each candidate's sign bit in: candidate kb + b ends at bit 31 - b
         if (kn == 32) {
-#pragma unroll 16
+#pragma unroll 8
             for (int b = 0; b < 32; ++b)
                 m = __builtin_amdgcn_alignbit(m, __float_as_uint(test_sign<LOOP, WIN>(L, kb + b, dd)), 31);
         } else {
@@ -452,45 +534,78 @@ __device__ __forceinline__ TileInfo bcast(const TileInfo &t, int l)
     return o;
 }
 
-// stage the j particles of one tile that reach the i box; flush when full
-template <int LOOP, int WIN>
-__device__ __forceinline__ void stage_tile(const InteractArgs &a, Lds<LOOP, WIN> &L, int &nc, const TileInfo &t,
-                                           const JRec<LOOP> &r, const IData &d, bool valid, const float4 &lo,
-                                           const float4 &hi, const float4 &cen, Acc &acc)
+// does lane's particle of tile t reach the i-tile box (lo, hi)?
+template <int LOOP, class R>
+__device__ __forceinline__ bool tile_keep(const TileInfo &t, const R &r, const float4 &lo,
+                                          const float4 &hi)
 {
     const int lane = threadIdx.x & 63;
-    const float hmi = lo.w;
-    bool keep = false;
-    if (lane < t.jn) {
-        const float x = r.p0.x + t.tx, y = r.p0.y + t.ty, z = r.p0.z + t.tz;
-        const float ex = fmaxf(fmaxf(lo.x - x, x - hi.x), 0.f);
-        const float ey = fmaxf(fmaxf(lo.y - y, y - hi.y), 0.f);
-        const float ez = fmaxf(fmaxf(lo.z - z, z - hi.z), 0.f);
-        const float reach = LOOP == 2 ? fmaxf(hmi, kGammaK * r.p0.w) : hmi;
-        keep = fmaf(ez, ez, fmaf(ey, ey, ex * ex)) < reach * reach * 1.0001f;
-    }
-    const uint64_t bal = __ballot(keep);
-    const int cnt = __popcll(bal);
-    if (cnt == 0) return;
-    if (nc + cnt > WIN) {
+    if (lane >= t.jn) return false;
+    const float x = r.p0.x + t.tx, y = r.p0.y + t.ty, z = r.p0.z + t.tz;
+    const float ex = fmaxf(fmaxf(lo.x - x, x - hi.x), 0.f);
+    const float ey = fmaxf(fmaxf(lo.y - y, y - hi.y), 0.f);
+    const float ez = fmaxf(fmaxf(lo.z - z, z - hi.z), 0.f);
+    const float reach = LOOP == 2 ? fmaxf(lo.w, kGammaK * r.p0.w) : lo.w;
+    return fmaf(ez, ez, fmaf(ey, ey, ex * ex)) < reach * reach * 1.0001f;
+}
+
+// stage the kept particles of a batch of B loaded tiles, in tile order,
+// flushing the window whenever the next tile's survivors do not fit (one
+// flush call site, so the batch stays in registers)
+template <int LOOP, bool PREP, int WIN, int B>
+__device__ __forceinline__ void stage_batch(const InteractArgs &a, Lds<LOOP, WIN> &L, int &nc,
+                                            const TileInfo (&tb)[B], const JRec<LOOP, PREP> (&rb)[B], const IData &d,
+                                            bool valid, const float4 &lo, const float4 &hi, const float4 &cen,
+                                            Acc &acc)
+{
+    const int lane = threadIdx.x & 63;
+    bool keep[B];
+    uint64_t bal[B];
+    unroll<0, B>([&](auto I) {
+        constexpr int b = decltype(I)::value;
+        keep[b] = tile_keep<LOOP>(tb[b], rb[b], lo, hi);
+        bal[b] = __ballot(keep[b]);
+    });
+    int b0 = 0;
+    for (;;) {
+        bool stop = false;
+        unroll<0, B>([&](auto I) {
+            constexpr int b = decltype(I)::value;
+            if (b >= b0 && !stop) {
+                const int cnt = __popcll(bal[b]);
+                if (nc + cnt > WIN) {
+                    stop = true;
+                } else {
+                    if (keep[b]) {
+                        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[b] >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)bal[b], 0u));
+                        stage_j<LOOP, PREP, WIN>(a, L, nc + rank, tb[b].js0 + lane, rb[b], tb[b].tx, tb[b].ty, tb[b].tz,
+                                           cen.x, cen.y, cen.z);
+                    }
+                    nc += cnt;
+                    b0 = b + 1;
+                }
+            }
+        });
+        if (!stop) break;
         flush<LOOP, WIN>(a, L, nc, d, valid, acc);
         nc = 0;
     }
-    if (keep) {
-        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        stage_j<LOOP, WIN>(a, L, nc + rank, t.js0 + lane, r, t.tx, t.ty, t.tz, cen.x, cen.y, cen.z);
-    }
-    nc = __builtin_amdgcn_readfirstlane(nc + cnt);
 }
+
+// j tiles whose records are loaded together before any of them is staged:
+// one memory round trip per batch instead of per tile
+template <int LOOP>
+constexpr int kJBatch = LOOP == 0 ? 8 : (LOOP == 1 ? 4 : 2);
 
 // gather the candidates of one item's j-tile list (nj tiles) into the window
 template <int LOOP, int MODE, int WIN>
 __device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN> &L, int &nc, const Chunk &ch,
                                           IData &d, bool valid, const float4 &lo, const float4 &hi,
-                                          const float4 &cen, Acc &acc)
+                                          const float4 &cen, float halfdiag, Acc &acc)
 {
-    const float ex = hi.x - lo.x, ey = hi.y - lo.y, ez = hi.z - lo.z;
-    const float halfdiag = 0.5f * sqrtf(fmaxf(ex * ex + ey * ey + ez * ez, 0.f));
+    constexpr int B = kJBatch<LOOP>;
+    constexpr bool PREP = MODE == 1 && LOOP >= 1;
     float hjm = 0.f;  // largest support of the surviving j-tiles so far
     const int lane = threadIdx.x & 63;
     int nj, jt0 = 0;
@@ -505,6 +620,7 @@ __device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN> 
         // 1. lane-parallel cull of up to 64 j-tiles on their stored boxes
         TileInfo ti{0, 0, 0.f, 0.f, 0.f};
         bool ok = false;
+        float hj = 0.f;
         const int q = base + lane;
         if (q < nj) {
             float4 blo, bhi;
@@ -516,58 +632,55 @@ __device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN> 
                 ti.jn = min(64, ch.jn - 64 * q);
             } else {
                 const JTile e = a.jt[jt0 + q];
-                const Nbr nb = a.nbr[e.nbr];
-                const Chunk tj = a.items_chunks[e.tile];
                 blo = a.bounds[2 * (int64_t)e.tile];
                 bhi = a.bounds[2 * (int64_t)e.tile + 1];
-                ti.js0 = tj.slot0;
-                ti.jn = tj.n;
-                ti.tx = nb.dx;
-                ti.ty = nb.dy;
-                ti.tz = nb.dz;
+                ti.js0 = e.slot0;
+                ti.jn = e.n;
+                ti.tx = e.tx;
+                ti.ty = e.ty;
+                ti.tz = e.tz;
             }
             const float gx = fmaxf(fmaxf(blo.x + ti.tx - hi.x, lo.x - (bhi.x + ti.tx)), 0.f);
             const float gy = fmaxf(fmaxf(blo.y + ti.ty - hi.y, lo.y - (bhi.y + ti.ty)), 0.f);
             const float gz = fmaxf(fmaxf(blo.z + ti.tz - hi.z, lo.z - (bhi.z + ti.tz)), 0.f);
             const float reach = LOOP == 2 ? fmaxf(hmi, blo.w) : hmi;
             ok = fmaf(gz, gz, fmaf(gy, gy, gx * gx)) < reach * reach * 1.0001f;
+            hj = blo.w;
         }
         uint64_t m = __ballot(ok);
         if (m == 0) continue;
         if constexpr (LOOP == 2) {
             // candidates of these tiles reach at most max(i-tile support, their tile's support)
-            float hj = 0.f;
-            if (ok) hj = MODE == 0 ? a.bounds[2 * ((int64_t)ch.jchunk0 - a.chunk_base + q)].w
-                                   : a.bounds[2 * (int64_t)a.jt[jt0 + q].tile].w;
-            hjm = fmaxf(hjm, wmax(hj));
+            hjm = fmaxf(hjm, wave_max_u(ok ? hj : 0.f));
             d.rj = halfdiag + 1.001f * fmaxf(hmi, hjm);
         }
-        // 2. stage surviving tiles, the next tile's records loaded ahead
-        int cur = __builtin_ctzll(m);
-        m &= m - 1;
-        TileInfo ct = bcast(ti, cur);
-        JRec<LOOP> cr;
-        load_j<LOOP>(a, ct.js0 + lane, lane < ct.jn, cr);
-        for (;;) {
-            const bool more = m != 0;
-            TileInfo nt = ct;
-            JRec<LOOP> nr;
-            if (more) {
-                const int nx = __builtin_ctzll(m);
-                m &= m - 1;
-                nt = bcast(ti, nx);
-                load_j<LOOP>(a, nt.js0 + lane, lane < nt.jn, nr);
-            }
-            stage_tile<LOOP, WIN>(a, L, nc, ct, cr, d, valid, lo, hi, cen, acc);
-            if (!more) break;
-            ct = nt;
-            cr = nr;
+        // 2. stage the surviving tiles, B tiles' records in flight at a time
+        while (m != 0) {
+            TileInfo tb[B];
+            JRec<LOOP, PREP> rb[B];
+            unroll<0, B>([&](auto I) {
+                constexpr int b = decltype(I)::value;
+                if (m != 0) {
+                    const int idx = __builtin_ctzll(m);
+                    m &= m - 1;
+                    tb[b] = bcast(ti, idx);
+                } else {
+                    tb[b] = TileInfo{0, 0, 0.f, 0.f, 0.f};  // slot 0 is inside every buffer
+                }
+                load_j<LOOP, PREP>(a, tb[b].js0 + (lane < tb[b].jn ? lane : 0), rb[b]);
+            });
+            stage_batch<LOOP, PREP, WIN, B>(a, L, nc, tb, rb, d, valid, lo, hi, cen, acc);
         }
     }
 }
 
+// resident waves per SIMD the register allocation must allow
+template <int LOOP>
+constexpr int kMinWaves = LOOP == 2 ? 3 : 4;
+
 template <int LOOP, int MODE, int WIN>
-__global__ __launch_bounds__(256) void k_interact(InteractArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<LOOP>))) void k_interact(
+    InteractArgs a)
 {
     __shared__ Lds<LOOP, WIN> lds[4];
     const int lane = threadIdx.x & 63;
@@ -575,71 +688,113 @@ __global__ __launch_bounds__(256) void k_interact(InteractArgs a)
     Lds<LOOP, WIN> &L = lds[wv];
     const int64_t wave_id = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + wv));
     const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int qmode = MODE == 1 ? a.use_queue : 0;
+    // the next item is claimed while the current one runs (lane 0's atomic
+    // result stays in a register until the loop head needs it)
+    const int xhome = (int)(blockIdx.x % kQueues);
+    int xr = xhome;  // share being drained (qmode 2)
+    int qv = 0;
+    if (qmode == 1 && lane == 0) qv = atomicAdd(a.queue, 1);
+    if (qmode == 2 && lane == 0) qv = atomicAdd(a.queue + kQueueStride * xr, 1);
     int64_t iter = 0;
     for (;;) {
         int64_t item;
         if (MODE == 0) {
             item = iter == 0 ? wave_id : a.nitems;
-        } else if (a.use_queue) {
-            int v = 0;
-            if (lane == 0) v = atomicAdd(a.queue, 1);
-            item = __builtin_amdgcn_readfirstlane(v);
+        } else if (qmode == 1) {
+            item = __builtin_amdgcn_readfirstlane(qv);
+        } else if (qmode == 2) {
+            const int v = __builtin_amdgcn_readfirstlane(qv);
+            if (v >= a.xlen[xr]) {
+                // this share is drained: move on to the next one, until all are
+                xr = xr + 1 == kQueues ? 0 : xr + 1;
+                if (xr == xhome) break;
+                if (lane == 0) qv = atomicAdd(a.queue + kQueueStride * xr, 1);
+                continue;
+            }
+            item = a.xoff[xr] + v;
         } else {
             item = wave_id + iter * nwaves;
         }
         ++iter;
         if (item >= a.nitems) break;
+        if (qmode == 1 && lane == 0) qv = atomicAdd(a.queue, 1);
+        if (qmode == 2 && lane == 0) qv = atomicAdd(a.queue + kQueueStride * xr, 1);
         Chunk ch;
-        int64_t islot;
+        int64_t islot, bi;
         if (MODE == 0) {
             ch = a.items_chunks[a.chunk_base + item];
             islot = ch.slot0 - a.slot_base + lane;
+            bi = item;
         } else {
-            ch = a.items_chunks[a.items[item]];
+            bi = qmode == 2 ? a.items_x[item] : a.items[item];
+            ch = a.items_chunks[bi];
             islot = ch.slot0 + lane;
         }
+        // the i-tile's box and largest support, as the pack kernel recorded them
+        const float4 lo = a.bounds[2 * bi];
+        const float4 hi = a.bounds[2 * bi + 1];
         const bool valid = lane < ch.n;
         IData d;
-        load_i<LOOP>(a, islot, valid, d);
-        const float inf = __builtin_huge_valf();
-        float4 lo, hi;
-        lo.x = wmin(valid ? d.x : inf);
-        lo.y = wmin(valid ? d.y : inf);
-        lo.z = wmin(valid ? d.z : inf);
-        lo.w = wmax(valid ? d.H : 0.f);
-        hi.x = wmax(valid ? d.x : -inf);
-        hi.y = wmax(valid ? d.y : -inf);
-        hi.z = wmax(valid ? d.z : -inf);
-        hi.w = 0.f;
+        load_i<LOOP, MODE == 1 && LOOP >= 1>(a, islot, valid, d);
         // i positions relative to the tile centre; phase-1 constants
         float4 cen;
         cen.x = 0.5f * (lo.x + hi.x);
         cen.y = 0.5f * (lo.y + hi.y);
         cen.z = 0.5f * (lo.z + hi.z);
         cen.w = 0.f;
-        {
-            const float ex = hi.x - lo.x, ey = hi.y - lo.y, ez = hi.z - lo.z;
-            const float halfdiag = valid ? 0.5f * sqrtf(ex * ex + ey * ey + ez * ez) : 0.f;
-            d.x -= cen.x;
-            d.y -= cen.y;
-            d.z -= cen.z;
-            d.ri = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
-            d.xi2 = fmaf(d.z, d.z, fmaf(d.y, d.y, d.x * d.x));
-            d.rj = halfdiag + 1.001f * lo.w;
-            d.nx2 = -2.0f * d.x;
-            d.ny2 = -2.0f * d.y;
-            d.nz2 = -2.0f * d.z;
-            d.t0 = (d.xi2 - test_delta(d.ri, d.rj)) - d.H2;
-        }
+        const float ex = hi.x - lo.x, ey = hi.y - lo.y, ez = hi.z - lo.z;
+        const float halfdiag = 0.5f * sqrtf(fmaxf(ex * ex + ey * ey + ez * ez, 0.f));
+        d.x -= cen.x;
+        d.y -= cen.y;
+        d.z -= cen.z;
+        d.ri = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+        d.xi2 = fmaf(d.z, d.z, fmaf(d.y, d.y, d.x * d.x));
+        d.rj = halfdiag + 1.001f * lo.w;
+        d.nx2 = -2.0f * d.x;
+        d.ny2 = -2.0f * d.y;
+        d.nz2 = -2.0f * d.z;
+        d.t0 = (d.xi2 - test_delta(d.ri, d.rj)) - d.H2;
         Acc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0};
         int nc = 0;
-        scan_item<LOOP, MODE, WIN>(a, L, nc, ch, d, valid, lo, hi, cen, acc);
+        scan_item<LOOP, MODE, WIN>(a, L, nc, ch, d, valid, lo, hi, cen, halfdiag, acc);
         if (nc > 0) flush<LOOP, WIN>(a, L, nc, d, valid, acc);
         if (valid) write_out<LOOP>(a, d, acc);
     }
 }
 
-__global__ void k_reset_queue(int32_t *q) { *q = 0; }
+__global__ void k_reset_queue(int32_t *q)
+{
+    if (threadIdx.x < kQueues) q[kQueueStride * threadIdx.x] = 0;
+}
+
+struct PrepArgs {
+    const char *pack;
+    int64_t P, n;
+    float *q;
+    float gam, eps;
+};
+
+// the derived planes of the batched form, one thread per particle
+template <int LOOP>
+__global__ __launch_bounds__(256) void k_prep(PrepArgs a)
+{
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= a.n) return;
+    const float4 p1 = ((const float4 *)(a.pack + a.P * 16))[s];
+    if constexpr (LOOP == 1) {
+        ((float4 *)a.q)[s] = derive_gradient(p1, ((const float2 *)(a.pack + a.P * 32))[s], a.gam);
+    } else {
+        const float4 p0 = ((const float4 *)a.pack)[s];
+        const float4 p2 = ((const float4 *)(a.pack + a.P * 32))[s];
+        const float4 p3 = ((const float4 *)(a.pack + a.P * 48))[s];
+        const float ad = ((const float *)(a.pack + a.P * 64))[s];
+        const ForceDerived f = derive_force(p0, p2, p3, ad, a.gam, a.eps);
+        ((float4 *)a.q)[s] = f.q0;
+        ((float4 *)(a.q + 4 * a.P))[s] = f.q1;
+        ((float2 *)(a.q + 8 * a.P))[s] = f.q2;
+    }
+}
 
 template <int LOOP, int MODE, int WIN>
 static void launch_one(const InteractArgs &a, unsigned grid, hipStream_t st)
@@ -693,6 +848,11 @@ sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, 
         a.P = round_slots(p->n);
         a.items_chunks = p->d_tiles;
         a.items = p->d_items;
+        a.items_x = p->d_items_x;
+        for (int q = 0; q < kQueues; ++q) {
+            a.xoff[q] = p->xoff[q];
+            a.xlen[q] = p->xlen[q];
+        }
         a.nitems = p->ntile;
         a.cellr = p->d_cellr;
         a.nbr = p->d_nbr;
@@ -706,8 +866,16 @@ sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, 
         grid = (unsigned)std::min<int64_t>((int64_t)tn->blocks_per_cu * p->num_cu, (a.nitems + 3) / 4);
         win = tn->window[loop];
         if (a.use_queue) {
-            hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, st, a.queue);
+            hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, a.queue);
             SPH_CHECK_LAUNCH("queue reset launch");
+        }
+        if (loop >= 1) {
+            PrepArgs pa{a.pack, a.P, p->n, (float *)((char *)ws + kQueueBytes), a.gam, a.eps};
+            a.q = pa.q;
+            const unsigned pg = (unsigned)((p->n + 255) / 256);
+            if (loop == 1) hipLaunchKernelGGL(k_prep<1>, dim3(pg), dim3(256), 0, st, pa);
+            else hipLaunchKernelGGL(k_prep<2>, dim3(pg), dim3(256), 0, st, pa);
+            SPH_CHECK_LAUNCH("derived-plane launch");
         }
     }
     if (loop == 0) return cells ? launch_win<0, 1>(a, win, grid, st) : launch_win<0, 0>(a, win, grid, st);

@@ -63,12 +63,17 @@ struct CellRange {
     int32_t tile0;  // first tile of the cell
 };
 
-// One entry of a cell's flattened j-tile list: a tile of a neighbour cell and
-// the neighbour entry whose translation moves it into the cell's frame.
+// One entry of a cell's flattened j-tile list: a tile of a neighbour cell,
+// where its particles sit, and the float32 translation (of the neighbour
+// entry) that moves its cell-relative offsets into the cell's frame.
 struct JTile {
-    int32_t tile;
-    int32_t nbr;
+    int64_t slot0;     // first particle of the tile
+    int32_t tile;      // tile index (its bounds follow the pack planes)
+    int32_t n;         // particles in the tile (1..64)
+    float tx, ty, tz;  // translation
+    int32_t nbr;       // neighbour entry
 };
+static_assert(sizeof(JTile) == 32, "j-tile layout");
 
 }  // namespace sph
 
@@ -93,6 +98,8 @@ struct sph_plan {
     sph::Nbr *d_nbr = nullptr;
     int32_t *d_nbr_off = nullptr;
     int32_t *d_items = nullptr;      // tiles in descending cost order
+    int32_t *d_items_x = nullptr;    // per-XCD shares, each in descending cost order
+    int32_t xoff[8] = {0}, xlen[8] = {0};
     int32_t *d_jt_off = nullptr;     // per cell: first entry of its j-tile list
     sph::JTile *d_jt = nullptr;      // flattened j-tiles of every cell's neighbours
     int32_t max_jt = 0;
@@ -106,6 +113,12 @@ struct sph_plan {
 namespace sph {
 
 inline int64_t round_slots(int64_t n) { return (n + 63) / 64 * 64; }
+
+// work-queue shares of the batched form: one per XCD of the MI355X (blocks are
+// dispatched to the XCDs round robin, so block b runs on XCD b mod 8); each
+// share's counter sits in its own 32-byte sector of the queue area
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 8;  // int32 counters
 
 // floats per slot in each pack plane, per loop
 constexpr int kPackPlanes[3] = {2, 3, 5};
@@ -142,6 +155,16 @@ inline size_t pack_bytes_for(int loop, int64_t nslot, int64_t nchunk)
 inline size_t result_bytes_for(int loop, int64_t nslot)
 {
     return (size_t)round_slots(nslot) * 4 * kResPlanes[loop];
+}
+// workspace of a batched interaction launch: the queue counter, then the
+// derived per-particle planes of the gradient (1 float4) or force (2 float4 +
+// 1 float2) loop
+constexpr size_t kQueueBytes = 256;
+static_assert(kQueues * kQueueStride * sizeof(int32_t) <= kQueueBytes, "queue counters");
+constexpr int kDerivedFloats[3] = {0, 4, 10};
+inline size_t interact_ws_bytes_for(int loop, int64_t n)
+{
+    return kQueueBytes + (size_t)round_slots(n) * 4 * kDerivedFloats[loop];
 }
 
 // ---------------------------------------------------------------------------

@@ -83,7 +83,8 @@ _SIGS = {
     "sph_tuning_default": ([vp], None),
     "sph_batched_ws_bytes": ([vp, C.POINTER(sz)], i32),
     "sph_pack_cells": ([vp, i32, vp, vp, sz, vp, vp], i32),
-    "sph_interact_cells": ([vp, i32, vp, sz, vp, vp, vp, sz, vp, vp, vp], i32),
+    "sph_interact_ws_bytes": ([vp, i32, C.POINTER(sz)], i32),
+    "sph_interact_cells": ([vp, i32, vp, sz, vp, vp, vp, sz, vp, vp, sz, vp], i32),
     "sph_unpack_cells": ([vp, i32, vp, sz, vp, vp, vp], i32),
     "sph_step_batched": ([vp, vp, vp, vp, vp, sz, vp], i32),
     "sph_graph_capture": ([vp, vp, vp, vp, vp, sz, C.POINTER(vp)], i32),
@@ -370,11 +371,17 @@ def sph_pack_cells(plan, loop: int, store, buf, tuning=None, stream=None):
                                 C.byref(tuning) if tuning else None, _stream(stream)), "sph_pack_cells")
 
 
+def sph_interact_ws_bytes(plan, loop: int) -> int:
+    b = sz()
+    _check(lib().sph_interact_ws_bytes(_h(plan), loop, C.byref(b)), "sph_interact_ws_bytes")
+    return b.value
+
+
 def sph_interact_cells(plan, loop: int, buf, res, ws, params=None, tuning=None, counts=None, stream=None):
     p = params if params is not None else default_params()
     _check(lib().sph_interact_cells(_h(plan), loop, _ptr(buf), _nbytes(buf), C.byref(p),
                                     C.byref(tuning) if tuning else None, _ptr(res), _nbytes(res), _ptr(counts),
-                                    _ptr(ws), _stream(stream)), "sph_interact_cells")
+                                    _ptr(ws), _nbytes(ws), _stream(stream)), "sph_interact_cells")
 
 
 def sph_unpack_cells(plan, loop: int, res, store, tuning=None, stream=None):
@@ -436,6 +443,12 @@ def alloc_range_buffers(plan: Plan, loop: int, t0: int, t1: int, device="cuda"):
     pack = torch.empty(max(pb, 256), dtype=torch.uint8, device=device)
     res = torch.empty(max(rb, 256), dtype=torch.uint8, device=device)
     return ns, pack, res
+
+
+def interact_ws(plan: Plan, loop: int = 2, device="cuda"):
+    """Workspace of sph_interact_cells (the force loop's covers every loop)."""
+    import torch
+    return torch.zeros(sph_interact_ws_bytes(plan, loop), dtype=torch.uint8, device=device)
 
 
 def cell_buffers(plan: Plan, loop: int, device="cuda"):

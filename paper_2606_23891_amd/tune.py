@@ -23,7 +23,7 @@ CACHE = os.path.join(HERE, "tuning_cache.json")
 
 WINDOWS = {0: (128, 256, 512), 1: (128, 256, 512), 2: (64, 128, 256)}
 BLOCKS_PER_CU = (2, 4, 8, 16)
-QUEUE = (1, 0)
+QUEUE = (2, 1, 0)
 PACK_WAVES = (1, 2, 4, 8)
 
 
@@ -81,7 +81,7 @@ def tune(plan, store, log=print):
 
     from . import sph
 
-    ws = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+    ws = sph.interact_ws(plan)
     params = sph.default_params()
     best = {"window": [256, 256, 128], "blocks_per_cu": 8, "queue": 1, "pack_waves": 4}
     times = {}

@@ -66,7 +66,7 @@ def slot_particles(plan: sph.Plan, t0: int, t1: int) -> np.ndarray:
 def run_batched_loop(plan: sph.Plan, store: sph.Store, loop: int, tuning=None, counts: bool = False):
     import torch
     pack, res = sph.cell_buffers(plan, loop)
-    ws = torch.zeros(1024, dtype=torch.uint8, device="cuda")
+    ws = sph.interact_ws(plan, loop)
     cbuf = torch.zeros(plan.n, dtype=torch.int32, device="cuda") if counts else None
     sph.sph_pack_cells(plan, loop, store, pack, tuning)
     sph.sph_interact_cells(plan, loop, pack, res, ws, tuning=tuning, counts=cbuf)

@@ -143,6 +143,10 @@ def _check_loops(ps, layout, mode, rows=None, bundle=1):
         log(f"loops {mode} layout={layout} loop={loop} n={ps.n}")
         if mode == "per_task":
             cnt = run_per_task(plan, st, loop, len(ps.tasks), bundle=bundle, counts=True)
+        elif mode == "batched_xcd":
+            t = sph.default_tuning()
+            t.queue = 2
+            cnt = run_batched_loop(plan, st, loop, tuning=t, counts=True)
         else:
             cnt = run_batched_loop(plan, st, loop, counts=True)
         g = outputs(st, loop)
@@ -175,7 +179,7 @@ def test_loops_multitile_cells(mode):
     _check_loops(ps, 0, mode, rows=rows, bundle=64)
 
 
-@pytest.mark.parametrize("mode", ["per_task", "batched"])
+@pytest.mark.parametrize("mode", ["per_task", "batched", "batched_xcd"])
 def test_loops_octree_uneven(mode):
     ps = inputs.make_config(3, n_side=24)
     _check_loops(ps, 4, mode, bundle=16)
@@ -191,3 +195,26 @@ def test_density_closed_form_lattice():
     run_batched_loop(plan, st, 0)
     np.testing.assert_allclose(st.get("rho").astype(np.float64), 1.0039807860264176, rtol=1e-5)
     plan.close()
+
+
+def test_batched_work_distribution_bitwise():
+    """every tile's sums are formed by one wave in a fixed order, so the
+    outputs cannot depend on how tiles are handed out: static stride, one
+    queue and per-XCD shares, at two grid sizes, agree bit for bit"""
+    import torch
+
+    ps = inputs.make_config(3, n_side=24)
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    outs = []
+    for queue, bpc in ((0, 1), (1, 4), (2, 2), (2, 16)):
+        log(f"work distribution queue={queue} blocks/cu={bpc}")
+        st = device_store(ps, 4)
+        t = sph.default_tuning()
+        t.queue, t.blocks_per_cu = queue, bpc
+        for loop in range(3):
+            run_batched_loop(plan, st, loop, tuning=t)
+        torch.cuda.synchronize()
+        outs.append(st.raw())
+    plan.close()
+    for o in outs[1:]:
+        assert o == outs[0]
