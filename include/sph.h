@@ -115,9 +115,10 @@ typedef struct sph_params {
 
 /* Launch parameters of the batched form (sph_tuning_default fills them). */
 typedef struct sph_tuning {
-    int32_t blocks_per_cu;   /* persistent grid = blocks_per_cu x CU count (1..64)  */
+    int32_t blocks_per_cu;   /* persistent grid = 4 x blocks_per_cu x CU count waves
+                                of the interaction kernels (1..64)                 */
     int32_t window[3];       /* candidate window per wave for density, gradient and
-                                force: 64, 128, 256 or 512 candidates              */
+                                force: 128, 256 or 512 candidates (512: not force) */
     int32_t pack_waves;      /* waves per block in pack / unpack kernels (1..8)     */
     int32_t queue;           /* 0 = static stride; 1 = one device work queue in
                                 descending cost order; 2 = one queue per XCD over

@@ -687,8 +687,8 @@ static sph_status check_tuning(const sph_tuning *t)
     if (!t) return SPH_OK;
     if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return fail(SPH_E_ARG, "blocks_per_cu outside 1..64");
     for (int k = 0; k < 3; ++k)
-        if (t->window[k] != 64 && t->window[k] != 128 && t->window[k] != 256 && t->window[k] != 512)
-            return fail(SPH_E_ARG, "window must be 64, 128, 256 or 512");
+        if (t->window[k] != 128 && t->window[k] != 256 && t->window[k] != 512)
+            return fail(SPH_E_ARG, "window must be 128, 256 or 512");
     if (t->pack_waves < 1 || t->pack_waves > 8) return fail(SPH_E_ARG, "pack_waves outside 1..8");
     if (t->queue < 0 || t->queue > 2) return fail(SPH_E_ARG, "queue must be 0, 1 or 2");
     return SPH_OK;

@@ -46,6 +46,14 @@ __device__ __forceinline__ void unroll(Fn &&fn)
     }
 }
 
+// compile-time loop threading a value: s = fn(integral_constant<int, I>, s)
+template <int I, int N, class S, class Fn>
+__device__ __forceinline__ S unroll_fold(S s, Fn &&fn)
+{
+    if constexpr (I < N) return unroll_fold<I + 1, N>(fn(std::integral_constant<int, I>{}, s), fn);
+    else return s;
+}
+
 struct InteractArgs {
     const char *pack;
     int64_t P;
@@ -131,7 +139,6 @@ template <int WIN>
 struct Lds<0, WIN> {
     float4 ph[WIN];  // x y z -|x|^2
     float m[WIN];
-    int32_t jslot[WIN];
     uint32_t mask[WIN / 32][64];
 };
 template <int WIN>
@@ -335,7 +342,7 @@ __device__ __forceinline__ void stage_j(const InteractArgs &a, Lds<LOOP, WIN> &L
                                         float cy, float cz)
 {
     const float x = (r.p0.x + tx) - cx, y = (r.p0.y + ty) - cy, z = (r.p0.z + tz) - cz;
-    L.jslot[k] = (int32_t)js;
+    if constexpr (LOOP >= 1) L.jslot[k] = (int32_t)js;  // density includes j = i
     L.ph[k] = make_float4(x, y, z, -fmaf(z, z, fmaf(y, y, x * x)));
     if constexpr (LOOP == 0) {
         L.m[k] = r.m;
@@ -374,16 +381,59 @@ __device__ __forceinline__ float test_sign(const Lds<LOOP, WIN> &L, int k, const
     return fmaf(d.nx2, q.x, fmaf(d.ny2, q.y, fmaf(d.nz2, q.z, t)));
 }
 
+// One staged candidate as phase 2 holds it in registers: its position in the
+// i-tile frame and what the pair term reads of it.
+template <int LOOP>
+struct Cand;
+template <>
+struct Cand<0> {
+    float x, y, z, m;
+};
+template <>
+struct Cand<1> {
+    float x, y, z;
+    int32_t js;
+    float4 c1, c2;  // v m | u m/rho c -
+};
+template <>
+struct Cand<2> {
+    float x, y, z;
+    int32_t js;
+    float4 c1, c2, c3;  // v m | H 1/H A c | K5 alpha~ alpha_d rho
+    float2 c4;          // u H^2
+};
+
 template <int LOOP, int WIN>
-__device__ __forceinline__ void pair(const InteractArgs &a, const Lds<LOOP, WIN> &L, int k, const IData &d,
-                                     Acc &acc)
+__device__ __forceinline__ Cand<LOOP> cand_load(const Lds<LOOP, WIN> &L, int k)
 {
-    const float4 c0 = L.ph[k];
-    const float rx = d.x - c0.x, ry = d.y - c0.y, rz = d.z - c0.z;
+    Cand<LOOP> c;
+    const float4 p = L.ph[k];
+    c.x = p.x;
+    c.y = p.y;
+    c.z = p.z;
+    if constexpr (LOOP == 0) {
+        c.m = L.m[k];
+    } else {
+        c.js = L.jslot[k];
+        c.c1 = L.c1[k];
+        c.c2 = L.c2[k];
+        if constexpr (LOOP == 2) {
+            c.c3 = L.c3[k];
+            c.c4 = L.c4[k];
+        }
+    }
+    return c;
+}
+
+// the pair term of lane's particle i with candidate c, after the exact support test
+template <int LOOP>
+__device__ __forceinline__ void pair(const InteractArgs &a, const Cand<LOOP> &c, const IData &d, Acc &acc)
+{
+    const float rx = d.x - c.x, ry = d.y - c.y, rz = d.z - c.z;
     const float r2 = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
     if constexpr (LOOP == 0) {
         if (!(r2 < d.H2)) return;  // the exact criterion
-        const float mj = L.m[k];
+        const float mj = c.m;
         const float r = fast_sqrt(r2);
         const float q = r * d.invH;
         float w, dw;
@@ -393,20 +443,20 @@ __device__ __forceinline__ void pair(const InteractArgs &a, const Lds<LOOP, WIN>
         acc.s2 += w;                                       // sum w
         acc.n++;
     } else {
-        if (L.jslot[k] == d.slot) return;  // j != i
+        if (c.js == d.slot) return;  // j != i
         if constexpr (LOOP == 1) {
             if (!(r2 < d.H2)) return;
         } else {
-            if (!(r2 < fmaxf(d.H2, L.c4[k].y))) return;
+            if (!(r2 < fmaxf(d.H2, c.c4.y))) return;
         }
-        const float4 c1 = L.c1[k];
+        const float4 c1 = c.c1;
         const float vx = d.vx - c1.x, vy = d.vy - c1.y, vz = d.vz - c1.z;
         const float invr = r2 > 0.f ? fast_rsq(r2) : 0.f;
         const float r = r2 * invr;
         const float dot = fmaf(vz, rz, fmaf(vy, ry, vx * rx));
         const float mu = fminf(dot * invr, 0.0f);
         if constexpr (LOOP == 1) {
-            const float4 c2 = L.c2[k];  // u m/rho c
+            const float4 c2 = c.c2;  // u m/rho c
             const float f = spline_f(r * d.invH, d.H * invr);    // w'/q
             const float mf = c1.w * f;
             acc.s0 = fmaf(mf, dot, acc.s0);                                   // D
@@ -417,9 +467,9 @@ __device__ __forceinline__ void pair(const InteractArgs &a, const Lds<LOOP, WIN>
             acc.s5 = fmaxf(acc.s5, d.c + c2.z - a.beta * mu);                 // V
             acc.n++;
         } else {
-            const float4 c2 = L.c2[k];  // H 1/H A c
-            const float4 c3 = L.c3[k];  // K5 at ad rho
-            const float2 c4 = L.c4[k];  // u H^2
+            const float4 c2 = c.c2;  // H 1/H A c
+            const float4 c3 = c.c3;  // K5 at ad rho
+            const float2 c4 = c.c4;  // u H^2
             const float uj = c4.x;
             const float fi = r2 < d.H2 ? d.K5 * spline_f(r * d.invH, d.H * invr) : 0.0f;
             const float fj = r2 < c4.y ? c3.x * spline_f(r * c2.y, c2.x * invr) : 0.0f;
@@ -467,10 +517,11 @@ __device__ __forceinline__ void write_out(const InteractArgs &a, const IData &d,
     if (a.counts) a.counts[s] = acc.n;
 }
 
-// test every staged candidate against every lane, then walk each lane's hits
+// test every staged candidate against every lane (phase 1: one bit per lane
+// and candidate, in LDS), then let each lane walk its own hits (phase 2)
 template <int LOOP, int WIN>
 __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, int nc, const IData &d,
-                                   bool valid, Acc &acc)
+                                      bool valid, Acc &acc)
 {
     const int lane = threadIdx.x & 63;
     wave_sync();
@@ -508,7 +559,7 @@ __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, 
         if (act) {
             const int b = __builtin_clz(cur);
             cur &= ~(0x80000000u >> b);
-            pair<LOOP, WIN>(a, L, 32 * w + b, d, acc);
+            pair<LOOP>(a, cand_load<LOOP, WIN>(L, 32 * w + b), d, acc);
         }
     }
     wave_sync();
@@ -566,37 +617,44 @@ __device__ __forceinline__ void stage_batch(const InteractArgs &a, Lds<LOOP, WIN
         keep[b] = tile_keep<LOOP>(tb[b], rb[b], lo, hi);
         bal[b] = __ballot(keep[b]);
     });
-    int b0 = 0;
+    // staging state threaded through the unrolled tiles: first tile not yet
+    // staged, whether it did not fit, and the window count
+    struct St {
+        int b0, stop, nc;
+    };
+    St st{0, 0, nc};
     for (;;) {
-        bool stop = false;
-        unroll<0, B>([&](auto I) {
+        st.stop = 0;
+        st = unroll_fold<0, B>(st, [&](auto I, St s) {
             constexpr int b = decltype(I)::value;
-            if (b >= b0 && !stop) {
+            if (b >= s.b0 && !s.stop) {
                 const int cnt = __popcll(bal[b]);
-                if (nc + cnt > WIN) {
-                    stop = true;
+                if (s.nc + cnt > WIN) {
+                    s.stop = 1;
                 } else {
                     if (keep[b]) {
                         const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[b] >> 32),
                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal[b], 0u));
-                        stage_j<LOOP, PREP, WIN>(a, L, nc + rank, tb[b].js0 + lane, rb[b], tb[b].tx, tb[b].ty, tb[b].tz,
-                                           cen.x, cen.y, cen.z);
+                        stage_j<LOOP, PREP, WIN>(a, L, s.nc + rank, tb[b].js0 + lane, rb[b], tb[b].tx, tb[b].ty,
+                                                 tb[b].tz, cen.x, cen.y, cen.z);
                     }
-                    nc += cnt;
-                    b0 = b + 1;
+                    s.nc = __builtin_amdgcn_readfirstlane(s.nc + cnt);
+                    s.b0 = b + 1;
                 }
             }
+            return s;
         });
-        if (!stop) break;
-        flush<LOOP, WIN>(a, L, nc, d, valid, acc);
-        nc = 0;
+        if (!__builtin_amdgcn_readfirstlane(st.stop)) break;
+        flush<LOOP, WIN>(a, L, st.nc, d, valid, acc);
+        st.nc = 0;
     }
+    nc = st.nc;
 }
 
 // j tiles whose records are loaded together before any of them is staged:
 // one memory round trip per batch instead of per tile
 template <int LOOP>
-constexpr int kJBatch = LOOP == 0 ? 8 : (LOOP == 1 ? 4 : 2);
+constexpr int kJBatch = LOOP == 0 ? 4 : 2;
 
 // gather the candidates of one item's j-tile list (nj tiles) into the window
 template <int LOOP, int MODE, int WIN>
@@ -678,16 +736,17 @@ __device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN> 
 template <int LOOP>
 constexpr int kMinWaves = LOOP == 2 ? 3 : 4;
 
+// One wave per workgroup: the waves share nothing, and one-wave workgroups
+// let the CU pack as many LDS windows as fit (a wave's window is its only
+// LDS), instead of rounding down to whole four-window groups.
 template <int LOOP, int MODE, int WIN>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<LOOP>))) void k_interact(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<LOOP>))) void k_interact(
     InteractArgs a)
 {
-    __shared__ Lds<LOOP, WIN> lds[4];
+    __shared__ Lds<LOOP, WIN> L;
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    Lds<LOOP, WIN> &L = lds[wv];
-    const int64_t wave_id = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + wv));
-    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int64_t wave_id = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
+    const int64_t nwaves = (int64_t)gridDim.x;
     const int qmode = MODE == 1 ? a.use_queue : 0;
     // the next item is claimed while the current one runs (lane 0's atomic
     // result stays in a register until the loop head needs it)
@@ -799,14 +858,13 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
 template <int LOOP, int MODE, int WIN>
 static void launch_one(const InteractArgs &a, unsigned grid, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_interact<LOOP, MODE, WIN>), dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_interact<LOOP, MODE, WIN>), dim3(grid), dim3(64), 0, st, a);
 }
 
 template <int LOOP, int MODE>
 static sph_status launch_win(const InteractArgs &a, int win, unsigned grid, hipStream_t st)
 {
     switch (win) {
-    case 64: launch_one<LOOP, MODE, 64>(a, grid, st); break;
     case 128: launch_one<LOOP, MODE, 128>(a, grid, st); break;
     case 256: launch_one<LOOP, MODE, 256>(a, grid, st); break;
     case 512:
@@ -841,9 +899,9 @@ sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, 
         a.nitems = p->chunk_off[t1] - p->chunk_off[t0];
         a.bounds = (const float4 *)(a.pack + a.P * 4 * kPackFloats[loop]);
         if (a.nitems == 0) return SPH_OK;
-        grid = (unsigned)((a.nitems + 3) / 4);
-        win = loop == 0 ? 128 : (loop == 1 ? 128 : 64);
-        if (p->max_cell > 64) win = loop == 2 ? 128 : 256;
+        grid = (unsigned)a.nitems;
+        win = 128;
+        if (p->max_cell > 64 && loop < 2) win = 256;
     } else {
         a.P = round_slots(p->n);
         a.items_chunks = p->d_tiles;
@@ -863,7 +921,8 @@ sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, 
         a.queue = (int32_t *)ws;
         a.use_queue = tn->queue;
         if (a.nitems == 0) return SPH_OK;
-        grid = (unsigned)std::min<int64_t>((int64_t)tn->blocks_per_cu * p->num_cu, (a.nitems + 3) / 4);
+        // blocks_per_cu counts groups of four waves
+        grid = (unsigned)std::min<int64_t>((int64_t)tn->blocks_per_cu * 4 * p->num_cu, a.nitems);
         win = tn->window[loop];
         if (a.use_queue) {
             hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, a.queue);

@@ -21,7 +21,7 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning_cache.json")
 
-WINDOWS = {0: (128, 256, 512), 1: (128, 256, 512), 2: (64, 128, 256)}
+WINDOWS = {0: (128, 256, 512), 1: (128, 256, 512), 2: (128, 256)}
 BLOCKS_PER_CU = (2, 4, 8, 16)
 QUEUE = (2, 1, 0)
 PACK_WAVES = (1, 2, 4, 8)
