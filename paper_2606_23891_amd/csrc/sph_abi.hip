@@ -424,11 +424,19 @@ sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task 
                                      (float)(a.loc[2] - k.shift[2] - b.loc[2])};
         }
         for (int32_t c = 0; c < ncell; ++c) p->max_nbr = std::max(p->max_nbr, deg[c]);
-        // flattened j-tile lists: every tile of every neighbour entry, in entry order
+        // flattened j-tile lists: every tile of every neighbour entry, tile
+        // index major (the first tile of every entry, then the second, ...), so
+        // that the tiles staged into one candidate window come from all
+        // directions and every lane finds a similar share of its neighbours
+        // in each window
         for (int32_t c = 0; c < ncell; ++c) {
-            for (int32_t e = nbr_off[c]; e < nbr_off[c + 1]; ++e) {
-                const int32_t nc = nbr[e].cell;
-                for (int32_t t = 0; t < (cells[nc].count + 63) / 64; ++t) {
+            int32_t tmax = 0;
+            for (int32_t e = nbr_off[c]; e < nbr_off[c + 1]; ++e)
+                tmax = std::max(tmax, (cells[nbr[e].cell].count + 63) / 64);
+            for (int32_t t = 0; t < tmax; ++t) {
+                for (int32_t e = nbr_off[c]; e < nbr_off[c + 1]; ++e) {
+                    const int32_t nc = nbr[e].cell;
+                    if (t >= (cells[nc].count + 63) / 64) continue;
                     const Chunk &tj = tiles[cr[nc].tile0 + t];
                     jt.push_back(JTile{tj.slot0, cr[nc].tile0 + t, tj.n, nbr[e].dx, nbr[e].dy, nbr[e].dz, e});
                 }
