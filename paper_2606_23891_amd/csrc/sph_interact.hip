@@ -370,15 +370,14 @@ __device__ __forceinline__ void stage_j(const InteractArgs &a, Lds<LOOP, WIN> &L
 // Phase-1 test of candidate k, as a sign: the result is negative when
 // |x_i - x_j|^2 < H^2 + delta_i, evaluated as |x_i|^2 - delta_i - H^2 + |x_j|^2 -
 // 2 x_i.x_j with delta_i covering the rounding of these four operations, so the
-// hits are a superset of the exact test that the pair term applies again.
+// hits are a superset of the exact test that the pair term applies again.  For
+// the force loop H^2 is max(H_i^2, Hw^2) with Hw the largest support of the
+// window's tiles, which bounds max(H_i, H_j) for every staged j.
 template <int LOOP, int WIN>
 __device__ __forceinline__ float test_sign(const Lds<LOOP, WIN> &L, int k, const IData &d)
 {
     const float4 q = L.ph[k];
-    float t;
-    if constexpr (LOOP == 2) t = (d.t0 - fmaxf(d.H2, L.c4[k].y)) - q.w;
-    else t = d.t0 - q.w;
-    return fmaf(d.nx2, q.x, fmaf(d.ny2, q.y, fmaf(d.nz2, q.z, t)));
+    return fmaf(d.nx2, q.x, fmaf(d.ny2, q.y, fmaf(d.nz2, q.z, d.t0 - q.w)));
 }
 
 // One staged candidate as phase 2 holds it in registers: its position in the
@@ -520,7 +519,7 @@ __device__ __forceinline__ void write_out(const InteractArgs &a, const IData &d,
 // test every staged candidate against every lane (phase 1: one bit per lane
 // and candidate, in LDS), then let each lane walk its own hits (phase 2)
 template <int LOOP, int WIN>
-__device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, int nc, const IData &d,
+__device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, int nc, float hw, const IData &d,
                                       bool valid, Acc &acc)
 {
     const int lane = threadIdx.x & 63;
@@ -528,7 +527,7 @@ __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, 
     nc = __builtin_amdgcn_readfirstlane(nc);
     const int nw = (nc + 31) >> 5;
     IData dd = d;
-    if constexpr (LOOP == 2) dd.t0 = dd.xi2 - test_delta(dd.ri, dd.rj);
+    if constexpr (LOOP == 2) dd.t0 = (dd.xi2 - test_delta(dd.ri, dd.rj)) - fmaxf(dd.H2, hw * hw);
     for (int w = 0; w < nw; ++w) {
         uint32_t m = 0;
         const int kb = 32 * w;
@@ -570,6 +569,7 @@ struct TileInfo {
     int64_t js0;
     int32_t jn;
     float tx, ty, tz;
+    float hm;  // largest support in the tile
 };
 
 __device__ __forceinline__ TileInfo bcast(const TileInfo &t, int l)
@@ -582,6 +582,7 @@ __device__ __forceinline__ TileInfo bcast(const TileInfo &t, int l)
     o.tx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t.tx), l));
     o.ty = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t.ty), l));
     o.tz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t.tz), l));
+    o.hm = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t.hm), l));
     return o;
 }
 
@@ -604,7 +605,7 @@ __device__ __forceinline__ bool tile_keep(const TileInfo &t, const R &r, const f
 // flushing the window whenever the next tile's survivors do not fit (one
 // flush call site, so the batch stays in registers)
 template <int LOOP, bool PREP, int WIN, int B>
-__device__ __forceinline__ void stage_batch(const InteractArgs &a, Lds<LOOP, WIN> &L, int &nc,
+__device__ __forceinline__ void stage_batch(const InteractArgs &a, Lds<LOOP, WIN> &L, int &nc, float &hw,
                                             const TileInfo (&tb)[B], const JRec<LOOP, PREP> (&rb)[B], const IData &d,
                                             bool valid, const float4 &lo, const float4 &hi, const float4 &cen,
                                             Acc &acc)
@@ -621,8 +622,9 @@ __device__ __forceinline__ void stage_batch(const InteractArgs &a, Lds<LOOP, WIN
     // staged, whether it did not fit, and the window count
     struct St {
         int b0, stop, nc;
+        float hw;  // largest support of the staged tiles (force)
     };
-    St st{0, 0, nc};
+    St st{0, 0, nc, hw};
     for (;;) {
         st.stop = 0;
         st = unroll_fold<0, B>(st, [&](auto I, St s) {
@@ -639,16 +641,19 @@ __device__ __forceinline__ void stage_batch(const InteractArgs &a, Lds<LOOP, WIN
                                                  tb[b].tz, cen.x, cen.y, cen.z);
                     }
                     s.nc = __builtin_amdgcn_readfirstlane(s.nc + cnt);
+                    if (cnt > 0) s.hw = fmaxf(s.hw, tb[b].hm);
                     s.b0 = b + 1;
                 }
             }
             return s;
         });
         if (!__builtin_amdgcn_readfirstlane(st.stop)) break;
-        flush<LOOP, WIN>(a, L, st.nc, d, valid, acc);
+        flush<LOOP, WIN>(a, L, st.nc, st.hw, d, valid, acc);
         st.nc = 0;
+        st.hw = 0.f;
     }
     nc = st.nc;
+    hw = st.hw;
 }
 
 // j tiles whose records are loaded together before any of them is staged:
@@ -658,7 +663,8 @@ constexpr int kJBatch = LOOP == 0 ? 4 : 2;
 
 // gather the candidates of one item's j-tile list (nj tiles) into the window
 template <int LOOP, int MODE, int WIN>
-__device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN> &L, int &nc, const Chunk &ch,
+__device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN> &L, int &nc, float &hw,
+                                          const Chunk &ch,
                                           IData &d, bool valid, const float4 &lo, const float4 &hi,
                                           const float4 &cen, float halfdiag, Acc &acc)
 {
@@ -676,7 +682,7 @@ __device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN> 
     const float hmi = lo.w;
     for (int base = 0; base < nj; base += 64) {
         // 1. lane-parallel cull of up to 64 j-tiles on their stored boxes
-        TileInfo ti{0, 0, 0.f, 0.f, 0.f};
+        TileInfo ti{0, 0, 0.f, 0.f, 0.f, 0.f};
         bool ok = false;
         float hj = 0.f;
         const int q = base + lane;
@@ -704,6 +710,7 @@ __device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN> 
             const float reach = LOOP == 2 ? fmaxf(hmi, blo.w) : hmi;
             ok = fmaf(gz, gz, fmaf(gy, gy, gx * gx)) < reach * reach * 1.0001f;
             hj = blo.w;
+            ti.hm = blo.w;
         }
         uint64_t m = __ballot(ok);
         if (m == 0) continue;
@@ -723,18 +730,18 @@ __device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN> 
                     m &= m - 1;
                     tb[b] = bcast(ti, idx);
                 } else {
-                    tb[b] = TileInfo{0, 0, 0.f, 0.f, 0.f};  // slot 0 is inside every buffer
+                    tb[b] = TileInfo{0, 0, 0.f, 0.f, 0.f, 0.f};  // slot 0 is inside every buffer
                 }
                 load_j<LOOP, PREP>(a, tb[b].js0 + (lane < tb[b].jn ? lane : 0), rb[b]);
             });
-            stage_batch<LOOP, PREP, WIN, B>(a, L, nc, tb, rb, d, valid, lo, hi, cen, acc);
+            stage_batch<LOOP, PREP, WIN, B>(a, L, nc, hw, tb, rb, d, valid, lo, hi, cen, acc);
         }
     }
 }
 
 // resident waves per SIMD the register allocation must allow
 template <int LOOP>
-constexpr int kMinWaves = LOOP == 2 ? 3 : 4;
+constexpr int kMinWaves = LOOP == 0 ? 5 : 4;
 
 // One wave per workgroup: the waves share nothing, and one-wave workgroups
 // let the CU pack as many LDS windows as fit (a wave's window is its only
@@ -816,8 +823,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<LO
         d.t0 = (d.xi2 - test_delta(d.ri, d.rj)) - d.H2;
         Acc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0};
         int nc = 0;
-        scan_item<LOOP, MODE, WIN>(a, L, nc, ch, d, valid, lo, hi, cen, halfdiag, acc);
-        if (nc > 0) flush<LOOP, WIN>(a, L, nc, d, valid, acc);
+        float hw = 0.f;
+        scan_item<LOOP, MODE, WIN>(a, L, nc, hw, ch, d, valid, lo, hi, cen, halfdiag, acc);
+        if (nc > 0) flush<LOOP, WIN>(a, L, nc, hw, d, valid, acc);
         if (valid) write_out<LOOP>(a, d, acc);
     }
 }
