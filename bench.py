@@ -76,15 +76,17 @@ def parse():
 TRAFFIC_SUMMARY = "hbm_traffic_gresho256.md"
 
 
-def stage_kernel(stage, layout, tuning):
-    """the kernel a batched stage launches (its demangled name)"""
+def stage_kernels(stage, layout, tuning):
+    """the kernels a batched stage launches (demangled names; the queue reset
+    of the interaction stages, a one-thread kernel, is left out)"""
     for L, nm in LOOP_NAME.items():
         if stage == f"pack_{nm}":
-            return f"void sph::k_pack<{layout}, {L}>(sph::PackArgs)"
+            return [f"void sph::k_pack<{layout}, {L}>(sph::PackArgs)"]
         if stage == f"unpack_{nm}":
-            return f"void sph::k_unpack_chunks<{layout}, {L}, true>(sph::UnpackArgs)"
+            return [f"void sph::k_unpack_chunks<{layout}, {L}, true>(sph::UnpackArgs)"]
         if stage == nm:
-            return f"void sph::k_interact<{L}, 1, {tuning.window[L]}>(sph::InteractArgs)"
+            k = [f"void sph::k_interact<{L}, 1, {tuning.window[L]}>(sph::InteractArgs)"]
+            return ([f"void sph::k_prep<{L}>(sph::PrepArgs)"] if L >= 1 else []) + k
     raise KeyError(stage)
 
 
@@ -235,9 +237,11 @@ def main():
 
     wl = f"{workload_name(a.config, ps)}; {a.layout}"
     tr = profiling.load_traffic(os.path.join(ROOT, "profiles", TRAFFIC_SUMMARY), wl)
-    kname = stage_kernel(dom, layout, tuning)
-    roof["traffic"] = tr["kernels"][kname]["bytes"] if tr and kname in tr["kernels"] else None
-    roof["traffic_unit"] = "bytes per launch"
+    knames = stage_kernels(dom, layout, tuning)
+    roof["kernels"] = knames
+    roof["traffic"] = (sum(tr["kernels"][k]["bytes"] for k in knames)
+                       if tr and all(k in tr["kernels"] for k in knames) else None)
+    roof["traffic_unit"] = "bytes per launch of the stage's kernels"
     roof["algorithmic_bytes"] = stage_bytes(dom, n)
 
     out = {
@@ -452,17 +456,17 @@ def cpu_baseline(ps, store, budget_s):
     R = store.get("rot_v").astype(np.float64)
     rng = np.random.default_rng(0)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    # grow a probe until it runs long enough to time, then size the sample to the budget
-    nrow, t1 = 8, 0.0
-    while nrow < ps.n:
-        rows = rng.choice(ps.n, nrow, replace=False)
+    # two probes give the per-row cost apart from the per-call overhead (the
+    # oracle converts its whole input on every call); size the sample to the budget
+    times = []
+    for nr in (8, 40):
+        rows = rng.choice(ps.n, nr, replace=False)
         t0 = time.perf_counter()
         _oracle_rows(oracle, f, rho, rdh, D, R, rows)
-        t1 = time.perf_counter() - t0
-        if t1 >= 0.5 or t1 >= budget_s / 4:
-            break
-        nrow *= 4
-    nrow = int(max(8, min(ps.n, nrow * budget_s / max(t1, 1e-3))))
+        times.append(time.perf_counter() - t0)
+    per_row = max((times[1] - times[0]) / 32, 1e-6)
+    overhead = max(times[0] - 8 * per_row, 0.0)
+    nrow = int(max(8, min(ps.n, (budget_s - overhead) / per_row)))
     rows = rng.choice(ps.n, nrow, replace=False)
     t0 = time.perf_counter()
     c = _oracle_rows(oracle, f, rho, rdh, D, R, rows)
