@@ -456,21 +456,18 @@ def cpu_baseline(ps, store, budget_s):
     R = store.get("rot_v").astype(np.float64)
     rng = np.random.default_rng(0)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    # two probes give the per-row cost apart from the per-call overhead (the
-    # oracle converts its whole input on every call); size the sample to the budget
-    times = []
-    for nr in (8, 40):
-        rows = rng.choice(ps.n, nr, replace=False)
+    # grow the sample until one run takes at least half the budget (the oracle
+    # converts its whole input on every call, so short runs are overhead) and
+    # report that run
+    nrow = 32
+    while True:
+        rows = rng.choice(ps.n, nrow, replace=False)
         t0 = time.perf_counter()
-        _oracle_rows(oracle, f, rho, rdh, D, R, rows)
-        times.append(time.perf_counter() - t0)
-    per_row = max((times[1] - times[0]) / 32, 1e-6)
-    overhead = max(times[0] - 8 * per_row, 0.0)
-    nrow = int(max(8, min(ps.n, (budget_s - overhead) / per_row)))
-    rows = rng.choice(ps.n, nrow, replace=False)
-    t0 = time.perf_counter()
-    c = _oracle_rows(oracle, f, rho, rdh, D, R, rows)
-    dt = time.perf_counter() - t0
+        c = _oracle_rows(oracle, f, rho, rdh, D, R, rows)
+        dt = time.perf_counter() - t0
+        if dt >= 0.5 * budget_s or nrow >= ps.n:
+            break
+        nrow = int(min(ps.n, nrow * min(8.0, max(2.0, 0.8 * budget_s / dt))))
     return {"value": c / dt, "unit": "pair interactions/s", "cores": cores, "kind": "oracle",
             "sample": f"{nrow} random particles of the workload, density+gradient+force, each summed by "
                       f"brute force over all {ps.n} particles in FP64 ({dt:.1f} s)",
