@@ -99,6 +99,17 @@ __device__ __forceinline__ float wave_max_u(float v)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+__device__ __forceinline__ float wave_min_u(float v)
+{
+    v = fminf(v, dpp<0xB1>(v));
+    v = fminf(v, dpp<0x4E>(v));
+    v = fminf(v, dpp<0x141>(v));
+    v = fminf(v, dpp<0x140>(v));
+    v = fminf(v, dpp<0x142, 0xA>(v));
+    v = fminf(v, dpp<0x143, 0xC>(v));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // wave-scope ordering of LDS traffic between lanes of one wave
 __device__ __forceinline__ void wave_sync()
 {
@@ -168,6 +179,7 @@ struct IData {
     float t0;                       // |x|^2 - delta - H^2 (density, gradient) or |x|^2 - delta (force)
     float ri, xi2;                  // |x| and |x|^2
     float rj;                       // bound on |x_j| of staged candidates (tile centre frame)
+    float hmin;                     // smallest support of the i-tile (uniform)
     int32_t slot;
 };
 
@@ -373,11 +385,37 @@ __device__ __forceinline__ void stage_j(const InteractArgs &a, Lds<LOOP, WIN> &L
 // hits are a superset of the exact test that the pair term applies again.  For
 // the force loop H^2 is max(H_i^2, Hw^2) with Hw the largest support of the
 // window's tiles, which bounds max(H_i, H_j) for every staged j.
-template <int LOOP, int WIN>
+template <int LOOP, int WIN, bool PERCAND = false>
 __device__ __forceinline__ float test_sign(const Lds<LOOP, WIN> &L, int k, const IData &d)
 {
     const float4 q = L.ph[k];
-    return fmaf(d.nx2, q.x, fmaf(d.ny2, q.y, fmaf(d.nz2, q.z, d.t0 - q.w)));
+    float t;
+    if constexpr (PERCAND) t = (d.t0 - fmaxf(d.H2, L.c4[k].y)) - q.w;
+    else t = d.t0 - q.w;
+    return fmaf(d.nx2, q.x, fmaf(d.ny2, q.y, fmaf(d.nz2, q.z, t)));
+}
+
+// phase 1 over the nw words of a window: one 32-bit mask per word and lane
+template <int LOOP, int WIN, bool PERCAND>
+__device__ __forceinline__ void test_words(Lds<LOOP, WIN> &L, int nc, int nw, const IData &dd, bool valid)
+{
+    const int lane = threadIdx.x & 63;
+    for (int w = 0; w < nw; ++w) {
+        uint32_t m = 0;
+        const int kb = 32 * w;
+        const int kn = __builtin_amdgcn_readfirstlane(min(32, nc - kb));
+        // shift each candidate's sign bit in: candidate kb + b ends at bit 31 - b
+        if (kn == 32) {
+#pragma unroll 8
+            for (int b = 0; b < 32; ++b)
+                m = __builtin_amdgcn_alignbit(m, __float_as_uint(test_sign<LOOP, WIN, PERCAND>(L, kb + b, dd)), 31);
+        } else {
+            for (int b = 0; b < kn; ++b)
+                m = __builtin_amdgcn_alignbit(m, __float_as_uint(test_sign<LOOP, WIN, PERCAND>(L, kb + b, dd)), 31);
+            m <<= (32 - kn);
+        }
+        L.mask[w][lane] = valid ? m : 0u;
+    }
 }
 
 // One staged candidate as phase 2 holds it in registers: its position in the
@@ -527,22 +565,20 @@ __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, 
     nc = __builtin_amdgcn_readfirstlane(nc);
     const int nw = (nc + 31) >> 5;
     IData dd = d;
-    if constexpr (LOOP == 2) dd.t0 = (dd.xi2 - test_delta(dd.ri, dd.rj)) - fmaxf(dd.H2, hw * hw);
-    for (int w = 0; w < nw; ++w) {
-        uint32_t m = 0;
-        const int kb = 32 * w;
-        const int kn = __builtin_amdgcn_readfirstlane(min(32, nc - kb));
-        // shift each candidate's sign bit in: candidate kb + b ends at bit 31 - b
-        if (kn == 32) {
-#pragma unroll 8
-            for (int b = 0; b < 32; ++b)
-                m = __builtin_amdgcn_alignbit(m, __float_as_uint(test_sign<LOOP, WIN>(L, kb + b, dd)), 31);
+    if constexpr (LOOP == 2) {
+        // the force loop's support is max(H_i, H_j): when no lane's support is
+        // much below the window's largest Hw, max(H_i, Hw) costs nothing in
+        // extra hits and saves a per-candidate maximum; otherwise (mixed
+        // scales) the test takes each candidate's own H_j
+        dd.t0 = dd.xi2 - test_delta(dd.ri, dd.rj);
+        if (hw <= 1.02f * dd.hmin) {
+            dd.t0 -= fmaxf(dd.H2, hw * hw);
+            test_words<LOOP, WIN, false>(L, nc, nw, dd, valid);
         } else {
-            for (int b = 0; b < kn; ++b)
-                m = __builtin_amdgcn_alignbit(m, __float_as_uint(test_sign<LOOP, WIN>(L, kb + b, dd)), 31);
-            m <<= (32 - kn);
+            test_words<LOOP, WIN, true>(L, nc, nw, dd, valid);
         }
-        L.mask[w][lane] = valid ? m : 0u;
+    } else {
+        test_words<LOOP, WIN, false>(L, nc, nw, dd, valid);
     }
     wave_sync();
     if (nw == 0) return;
@@ -817,6 +853,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<LO
         d.ri = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
         d.xi2 = fmaf(d.z, d.z, fmaf(d.y, d.y, d.x * d.x));
         d.rj = halfdiag + 1.001f * lo.w;
+        if constexpr (LOOP == 2) d.hmin = wave_min_u(valid ? d.H : __builtin_huge_valf());
         d.nx2 = -2.0f * d.x;
         d.ny2 = -2.0f * d.y;
         d.nz2 = -2.0f * d.z;
