@@ -1,0 +1,74 @@
+"""Host-side tooling without a GPU: the rocprofv3 counter summaries that bench
+reports traffic from, and the tuning cache keys."""
+import csv
+import json
+import os
+import types
+
+import pytest
+
+from paper_2606_23891_amd import profiling, tune
+
+COPY = 'void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel_cuda(...)>(...)'
+FORCE = "void sph::k_interact<2, 1, 128>(sph::InteractArgs)"
+PREP = "void sph::k_prep<2>(sph::PrepArgs)"
+
+
+def _write_run(d, counter, values):
+    os.makedirs(d, exist_ok=True)
+    cols = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    with open(os.path.join(d, "x_counter_collection.csv"), "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=cols)
+        w.writeheader()
+        for i, (k, v) in enumerate(values):
+            w.writerow({"Dispatch_Id": i, "Kernel_Name": k, "Counter_Name": counter, "Counter_Value": v})
+
+
+def test_traffic_calibration_and_reload(tmp_path):
+    gib = 1 << 30
+    # the copy reads 1 GiB but the fetch counter shows half of it; the write counter is exact
+    _write_run(tmp_path / "f", "FETCH_SIZE", [(COPY, gib / 2048), (FORCE, 1000.0), (FORCE, 3000.0), (PREP, 512.0)])
+    _write_run(tmp_path / "w", "WRITE_SIZE", [(COPY, gib / 1024), (FORCE, 100.0), (FORCE, 100.0), (PREP, 256.0)])
+    t = profiling.traffic(str(tmp_path / "f"), str(tmp_path / "w"), gib)
+    assert t["fetch_factor"] == pytest.approx(2.0) and t["write_factor"] == pytest.approx(1.0)
+    k = t["kernels"][FORCE]
+    assert k["dispatches"] == 2
+    assert k["fetch_bytes"] == pytest.approx(2000.0 * 1024 * 2)   # mean KiB x 1024 x factor
+    assert k["write_bytes"] == pytest.approx(100.0 * 1024)
+    assert COPY not in t["kernels"]                                 # only the library's kernels
+    md = profiling.traffic_markdown(t, "wl", "cmd f", "cmd w", {FORCE: 1e6})
+    p = tmp_path / "summary.md"
+    p.write_text(md)
+    back = profiling.load_traffic(str(p), "wl")
+    assert back is not None and back["kernels"][FORCE]["bytes"] == pytest.approx(k["bytes"])
+    assert profiling.load_traffic(str(p), "another workload") is None
+    # a summary taken from other kernel sources is not reported
+    p.write_text(md.replace(profiling.source_hash(), "0" * 16))
+    assert profiling.load_traffic(str(p), "wl") is None
+
+
+def test_traffic_needs_exactly_one_calibration_copy(tmp_path):
+    _write_run(tmp_path / "f", "FETCH_SIZE", [(FORCE, 1.0)])
+    _write_run(tmp_path / "w", "WRITE_SIZE", [(FORCE, 1.0)])
+    with pytest.raises(RuntimeError):
+        profiling.traffic(str(tmp_path / "f"), str(tmp_path / "w"), 1 << 30)
+
+
+def test_tuning_cache_keys_and_apply(tmp_path, monkeypatch):
+    props = types.SimpleNamespace(gcnArchName="gfx950:sramecc+:xnack-", name="", multi_processor_count=256)
+    assert tune.device_key(props) == "gfx950-256cu"
+    ps = types.SimpleNamespace(meta={"config": 2}, n=16, cells=[0, 1], tasks=[0, 1, 2])
+    sig = tune.signature(ps, "SOA")
+    assert sig == "cfg2-n16-cells2-tasks3-SOA"
+    cache = tmp_path / "cache.json"
+    cache.write_text(json.dumps({"gfx950-256cu": {sig: {"window": [512, 256, 128], "blocks_per_cu": 2,
+                                                         "queue": 2, "pack_waves": 8}}}))
+    monkeypatch.setattr(tune, "CACHE", str(cache))
+    entry = tune.load("gfx950-256cu", sig)
+    assert tune.load("gfx942-304cu", sig) is None
+
+    class T:
+        window = [0, 0, 0]
+        blocks_per_cu = pack_waves = queue = 0
+    t = tune.apply(T(), entry)
+    assert list(t.window) == [512, 256, 128] and (t.blocks_per_cu, t.queue, t.pack_waves) == (2, 2, 8)
