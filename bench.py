@@ -85,7 +85,7 @@ def stage_kernels(stage, layout, tuning):
         if stage == f"unpack_{nm}":
             return [f"void sph::k_unpack_chunks<{layout}, {L}, true>(sph::UnpackArgs)"]
         if stage == nm:
-            k = [f"void sph::k_interact<{L}, 1, {tuning.window[L]}>(sph::InteractArgs)"]
+            k = [f"void sph::k_interact<{L}, 1, {tuning.window[L]}, false>(sph::InteractArgs)"]
             return ([f"void sph::k_prep<{L}>(sph::PrepArgs)"] if L >= 1 else []) + k
     raise KeyError(stage)
 

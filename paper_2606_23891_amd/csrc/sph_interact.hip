@@ -142,7 +142,10 @@ __device__ __forceinline__ float spline_f(float q, float H_over_r)
 // ---------------------------------------------------------------------------
 // LDS candidate window of one wave.  ph holds, per candidate, the position
 // relative to the i-tile centre and -|x|^2 (the phase-1 test reads only ph,
-// plus H^2 for the force loop); the other planes feed the pair term.
+// plus H^2 for the force loop); the other planes feed the pair term.  Every
+// plane of the gradient and force windows has a 16-byte stride, so one
+// address serves all reads of a candidate; the candidate's pack slot rides in
+// a spare component.
 template <int LOOP, int WIN>
 struct Lds;
 
@@ -156,8 +159,7 @@ template <int WIN>
 struct Lds<1, WIN> {
     float4 ph[WIN];  // x y z -|x|^2
     float4 c1[WIN];  // vx vy vz m
-    float4 c2[WIN];  // u m/rho c -
-    int32_t jslot[WIN];
+    float4 c2[WIN];  // u m/rho c slot(bits)
     uint32_t mask[WIN / 32][64];
 };
 template <int WIN>
@@ -166,8 +168,7 @@ struct Lds<2, WIN> {
     float4 c1[WIN];  // vx vy vz m
     float4 c2[WIN];  // H 1/H A c
     float4 c3[WIN];  // K5 alpha~ alpha_d rho
-    float2 c4[WIN];  // u H^2
-    int32_t jslot[WIN];
+    float4 c4[WIN];  // u H^2 slot(bits) -
     uint32_t mask[WIN / 32][64];
 };
 
@@ -354,15 +355,17 @@ __device__ __forceinline__ void stage_j(const InteractArgs &a, Lds<LOOP, WIN> &L
                                         float cy, float cz)
 {
     const float x = (r.p0.x + tx) - cx, y = (r.p0.y + ty) - cy, z = (r.p0.z + tz) - cz;
-    if constexpr (LOOP >= 1) L.jslot[k] = (int32_t)js;  // density includes j = i
+    [[maybe_unused]] const float jsb = __int_as_float((int32_t)js);  // the slot, for the j != i test
     L.ph[k] = make_float4(x, y, z, -fmaf(z, z, fmaf(y, y, x * x)));
     if constexpr (LOOP == 0) {
         L.m[k] = r.m;
     } else {
         L.c1[k] = make_float4(r.p1.x, r.p1.y, r.p1.z, r.p1.w);
         if constexpr (LOOP == 1) {
-            if constexpr (PREP) L.c2[k] = make_float4(r.q0.x, r.q0.y, r.q0.z, r.q0.w);
-            else L.c2[k] = derive_gradient(r.p1, r.p2, a.gam);
+            float4 q;
+            if constexpr (PREP) q = r.q0;
+            else q = derive_gradient(r.p1, r.p2, a.gam);
+            L.c2[k] = make_float4(q.x, q.y, q.z, jsb);
         } else {
             ForceDerived f;
             if constexpr (PREP) {
@@ -374,7 +377,7 @@ __device__ __forceinline__ void stage_j(const InteractArgs &a, Lds<LOOP, WIN> &L
             }
             L.c2[k] = make_float4(f.q0.x, f.q0.y, f.q0.z, f.q0.w);
             L.c3[k] = make_float4(f.q1.x, f.q1.y, f.q1.z, f.q1.w);
-            L.c4[k] = make_float2(f.q2.x, f.q2.y);
+            L.c4[k] = make_float4(f.q2.x, f.q2.y, jsb, 0.f);
         }
     }
 }
@@ -451,25 +454,36 @@ __device__ __forceinline__ Cand<LOOP> cand_load(const Lds<LOOP, WIN> &L, int k)
     if constexpr (LOOP == 0) {
         c.m = L.m[k];
     } else {
-        c.js = L.jslot[k];
         c.c1 = L.c1[k];
         c.c2 = L.c2[k];
-        if constexpr (LOOP == 2) {
+        if constexpr (LOOP == 1) {
+            c.js = __float_as_int(c.c2.w);
+        } else {
             c.c3 = L.c3[k];
-            c.c4 = L.c4[k];
+            const float4 c4 = L.c4[k];
+            c.c4 = make_float2(c4.x, c4.y);
+            c.js = __float_as_int(c4.z);
         }
     }
     return c;
 }
 
-// the pair term of lane's particle i with candidate c, after the exact support test
-template <int LOOP>
+// the pair term of lane's particle i with candidate c.  The counting variant
+// (CNT) applies the exact support test and the j != i test before anything
+// else and counts the pair.  Without counts most of these tests are not
+// needed: beyond a support the clamped spline gives w = w' = 0 exactly, so such
+// a candidate adds zeros, and for j = i (r = 0) every gradient and force term
+// carries a factor r, v_ij or u_i - u_j that is zero; only the gradient loop's
+// signal-velocity maximum still needs both tests.
+template <int LOOP, bool CNT>
 __device__ __forceinline__ void pair(const InteractArgs &a, const Cand<LOOP> &c, const IData &d, Acc &acc)
 {
     const float rx = d.x - c.x, ry = d.y - c.y, rz = d.z - c.z;
     const float r2 = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
     if constexpr (LOOP == 0) {
-        if (!(r2 < d.H2)) return;  // the exact criterion
+        if constexpr (CNT) {
+            if (!(r2 < d.H2)) return;  // the exact criterion
+        }
         const float mj = c.m;
         const float r = fast_sqrt(r2);
         const float q = r * d.invH;
@@ -478,22 +492,25 @@ __device__ __forceinline__ void pair(const InteractArgs &a, const Cand<LOOP> &c,
         acc.s0 = fmaf(mj, w, acc.s0);                      // sum m w
         acc.s1 = fmaf(mj, fmaf(q, dw, 3.0f * w), acc.s1);  // sum m (3w + q w')
         acc.s2 += w;                                       // sum w
-        acc.n++;
+        if constexpr (CNT) acc.n++;
     } else {
-        if (c.js == d.slot) return;  // j != i
-        if constexpr (LOOP == 1) {
-            if (!(r2 < d.H2)) return;
-        } else {
-            if (!(r2 < fmaxf(d.H2, c.c4.y))) return;
+        if constexpr (CNT) {
+            if (c.js == d.slot) return;  // j != i
+            if constexpr (LOOP == 1) {
+                if (!(r2 < d.H2)) return;
+            } else {
+                if (!(r2 < fmaxf(d.H2, c.c4.y))) return;
+            }
         }
         const float4 c1 = c.c1;
         const float vx = d.vx - c1.x, vy = d.vy - c1.y, vz = d.vz - c1.z;
-        const float invr = r2 > 0.f ? fast_rsq(r2) : 0.f;
+        // r = 0 (j = i, or coincident particles) gives a finite 1/r and r = 0
+        const float invr = fast_rsq(fmaxf(r2, 0x1p-126f));
         const float r = r2 * invr;
         const float dot = fmaf(vz, rz, fmaf(vy, ry, vx * rx));
         const float mu = fminf(dot * invr, 0.0f);
         if constexpr (LOOP == 1) {
-            const float4 c2 = c.c2;  // u m/rho c
+            const float4 c2 = c.c2;  // u m/rho c slot
             const float f = spline_f(r * d.invH, d.H * invr);    // w'/q
             const float mf = c1.w * f;
             acc.s0 = fmaf(mf, dot, acc.s0);                                   // D
@@ -501,15 +518,26 @@ __device__ __forceinline__ void pair(const InteractArgs &a, const Cand<LOOP> &c,
             acc.s2 = fmaf(mf, fmaf(vz, rx, -vx * rz), acc.s2);
             acc.s3 = fmaf(mf, fmaf(vx, ry, -vy * rx), acc.s3);
             acc.s4 = fmaf(c2.y * (d.u - c2.x), f, acc.s4);                    // L / 2
-            acc.s5 = fmaxf(acc.s5, d.c + c2.z - a.beta * mu);                 // V
-            acc.n++;
+            const float vs = d.c + c2.z - a.beta * mu;
+            if constexpr (CNT) {
+                acc.s5 = fmaxf(acc.s5, vs);                                   // V
+                acc.n++;
+            } else {
+                if (c.js != d.slot && r2 < d.H2) acc.s5 = fmaxf(acc.s5, vs);
+            }
         } else {
             const float4 c2 = c.c2;  // H 1/H A c
             const float4 c3 = c.c3;  // K5 at ad rho
             const float2 c4 = c.c4;  // u H^2
             const float uj = c4.x;
-            const float fi = r2 < d.H2 ? d.K5 * spline_f(r * d.invH, d.H * invr) : 0.0f;
-            const float fj = r2 < c4.y ? c3.x * spline_f(r * c2.y, c2.x * invr) : 0.0f;
+            float fi, fj;
+            if constexpr (CNT) {
+                fi = r2 < d.H2 ? d.K5 * spline_f(r * d.invH, d.H * invr) : 0.0f;
+                fj = r2 < c4.y ? c3.x * spline_f(r * c2.y, c2.x * invr) : 0.0f;
+            } else {
+                fi = d.K5 * spline_f(r * d.invH, d.H * invr);
+                fj = c3.x * spline_f(r * c2.y, c2.x * invr);
+            }
             const float fb = 0.5f * (fi + fj);
             const float vsig = d.c + c2.w - a.beta * mu;
             const float irb = fast_rcp(0.5f * (d.rho + c3.w));
@@ -522,12 +550,12 @@ __device__ __forceinline__ void pair(const InteractArgs &a, const Cand<LOOP> &c,
             acc.s2 = fmaf(-ms, rz, acc.s2);
             const float cond = 0.5f * (d.ad + c3.z) * fabsf(dot) * (d.u - uj) * fb * irb;
             acc.s3 = fmaf(mj, fmaf(d.A * fi, dot, fmaf(0.5f * Pi * fb, dot, cond)), acc.s3);
-            acc.n++;
+            if constexpr (CNT) acc.n++;
         }
     }
 }
 
-template <int LOOP>
+template <int LOOP, bool CNT>
 __device__ __forceinline__ void write_out(const InteractArgs &a, const IData &d, const Acc &acc)
 {
     float *r = a.res;
@@ -551,12 +579,12 @@ __device__ __forceinline__ void write_out(const InteractArgs &a, const IData &d,
         r[2 * P + s] = acc.s2;
         r[3 * P + s] = acc.s3;
     }
-    if (a.counts) a.counts[s] = acc.n;
+    if constexpr (CNT) a.counts[s] = acc.n;
 }
 
 // test every staged candidate against every lane (phase 1: one bit per lane
 // and candidate, in LDS), then let each lane walk its own hits (phase 2)
-template <int LOOP, int WIN>
+template <int LOOP, int WIN, bool CNT>
 __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, int nc, float hw, const IData &d,
                                       bool valid, Acc &acc)
 {
@@ -594,7 +622,7 @@ __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, 
         if (act) {
             const int b = __builtin_clz(cur);
             cur &= ~(0x80000000u >> b);
-            pair<LOOP>(a, cand_load<LOOP, WIN>(L, 32 * w + b), d, acc);
+            pair<LOOP, CNT>(a, cand_load<LOOP, WIN>(L, 32 * w + b), d, acc);
         }
     }
     wave_sync();
@@ -640,7 +668,7 @@ __device__ __forceinline__ bool tile_keep(const TileInfo &t, const R &r, const f
 // stage the kept particles of a batch of B loaded tiles, in tile order,
 // flushing the window whenever the next tile's survivors do not fit (one
 // flush call site, so the batch stays in registers)
-template <int LOOP, bool PREP, int WIN, int B>
+template <int LOOP, bool PREP, int WIN, int B, bool CNT>
 __device__ __forceinline__ void stage_batch(const InteractArgs &a, Lds<LOOP, WIN> &L, int &nc, float &hw,
                                             const TileInfo (&tb)[B], const JRec<LOOP, PREP> (&rb)[B], const IData &d,
                                             bool valid, const float4 &lo, const float4 &hi, const float4 &cen,
@@ -684,7 +712,7 @@ __device__ __forceinline__ void stage_batch(const InteractArgs &a, Lds<LOOP, WIN
             return s;
         });
         if (!__builtin_amdgcn_readfirstlane(st.stop)) break;
-        flush<LOOP, WIN>(a, L, st.nc, st.hw, d, valid, acc);
+        flush<LOOP, WIN, CNT>(a, L, st.nc, st.hw, d, valid, acc);
         st.nc = 0;
         st.hw = 0.f;
     }
@@ -698,7 +726,7 @@ template <int LOOP>
 constexpr int kJBatch = LOOP == 0 ? 4 : 2;
 
 // gather the candidates of one item's j-tile list (nj tiles) into the window
-template <int LOOP, int MODE, int WIN>
+template <int LOOP, int MODE, int WIN, bool CNT>
 __device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN> &L, int &nc, float &hw,
                                           const Chunk &ch,
                                           IData &d, bool valid, const float4 &lo, const float4 &hi,
@@ -770,7 +798,7 @@ __device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN> 
                 }
                 load_j<LOOP, PREP>(a, tb[b].js0 + (lane < tb[b].jn ? lane : 0), rb[b]);
             });
-            stage_batch<LOOP, PREP, WIN, B>(a, L, nc, hw, tb, rb, d, valid, lo, hi, cen, acc);
+            stage_batch<LOOP, PREP, WIN, B, CNT>(a, L, nc, hw, tb, rb, d, valid, lo, hi, cen, acc);
         }
     }
 }
@@ -782,7 +810,7 @@ constexpr int kMinWaves = LOOP == 0 ? 5 : 4;
 // One wave per workgroup: the waves share nothing, and one-wave workgroups
 // let the CU pack as many LDS windows as fit (a wave's window is its only
 // LDS), instead of rounding down to whole four-window groups.
-template <int LOOP, int MODE, int WIN>
+template <int LOOP, int MODE, int WIN, bool CNT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<LOOP>))) void k_interact(
     InteractArgs a)
 {
@@ -861,9 +889,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<LO
         Acc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0};
         int nc = 0;
         float hw = 0.f;
-        scan_item<LOOP, MODE, WIN>(a, L, nc, hw, ch, d, valid, lo, hi, cen, halfdiag, acc);
-        if (nc > 0) flush<LOOP, WIN>(a, L, nc, hw, d, valid, acc);
-        if (valid) write_out<LOOP>(a, d, acc);
+        scan_item<LOOP, MODE, WIN, CNT>(a, L, nc, hw, ch, d, valid, lo, hi, cen, halfdiag, acc);
+        if (nc > 0) flush<LOOP, WIN, CNT>(a, L, nc, hw, d, valid, acc);
+        if (valid) write_out<LOOP, CNT>(a, d, acc);
     }
 }
 
@@ -900,10 +928,12 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
     }
 }
 
+// the counting variant runs only when the caller asks for pair counts
 template <int LOOP, int MODE, int WIN>
 static void launch_one(const InteractArgs &a, unsigned grid, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_interact<LOOP, MODE, WIN>), dim3(grid), dim3(64), 0, st, a);
+    if (a.counts) hipLaunchKernelGGL((k_interact<LOOP, MODE, WIN, true>), dim3(grid), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL((k_interact<LOOP, MODE, WIN, false>), dim3(grid), dim3(64), 0, st, a);
 }
 
 template <int LOOP, int MODE>

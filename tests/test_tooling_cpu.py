@@ -10,7 +10,7 @@ import pytest
 from paper_2606_23891_amd import profiling, tune
 
 COPY = 'void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel_cuda(...)>(...)'
-FORCE = "void sph::k_interact<2, 1, 128>(sph::InteractArgs)"
+FORCE = "void sph::k_interact<2, 1, 128, false>(sph::InteractArgs)"
 PREP = "void sph::k_prep<2>(sph::PrepArgs)"
 
 
