@@ -166,16 +166,16 @@ template <int WIN>
 struct Lds<2, WIN> {
     float4 ph[WIN];  // x y z -|x|^2
     float4 c1[WIN];  // vx vy vz m
-    float4 c2[WIN];  // H 1/H A c
-    float4 c3[WIN];  // K5 alpha~ alpha_d rho
-    float4 c4[WIN];  // u H^2 slot(bits) -
+    float4 c2[WIN];  // 1/H kA nkB kD
+    float4 c3[WIN];  // A2 c atq adh
+    float4 c4[WIN];  // rh u H^2 slot(bits)
     uint32_t mask[WIN / 32][64];
 };
 
 struct IData {
     float x, y, z, H, H2, invH;    // position relative to the i-tile centre
     float vx, vy, vz, u, c;
-    float K5, A, at, ad, rho;
+    float kA, nkB, kD, A2, atq, adh, rh;  // force: see derive_force
     float nx2, ny2, nz2;            // -2 x, -2 y, -2 z (phase-1 test)
     float t0;                       // |x|^2 - delta - H^2 (density, gradient) or |x|^2 - delta (force)
     float ri, xi2;                  // |x| and |x|^2
@@ -199,20 +199,31 @@ struct Acc {
 };
 
 // Per-particle quantities the pair terms need beyond the packed fields: for
-// the gradient loop {u, m/rho, c}; for the force loop {H, 1/H, A = P/(Omega
-// rho^2), c}, {H^-5 (8/pi), alpha~ = alpha_v B (Balsara), alpha_d, rho} and
-// {u, H^2}.  The batched form computes them once per particle (k_prep) into
-// derived planes; the per-task form computes them when it stages a particle.
+// the gradient loop {u, m/rho, c}; for the force loop the factors of the pair
+// term with its constants folded in (see derive_force).  The batched form
+// computes them once per particle (k_prep) into derived planes; the per-task
+// form computes them when it stages a particle.
 __device__ __forceinline__ float4 derive_gradient(const float4 &p1, const float2 &p2, float g)
 {
     return make_float4(p2.x, p1.w / p2.y, sqrtf(g * (g - 1.0f) * p2.x), 0.f);
 }
 
 struct ForceDerived {
-    float4 q0, q1;
-    float2 q2;
+    float4 q0, q1, q2;
 };
 
+// The force pair term needs, per particle, K = H^-5 (8/pi) (the spline's
+// normalisation), A = P / (Omega rho^2) with P = (gamma - 1) rho u and the
+// grad-h factor Omega = 1 + (h/3rho) drho/dh, the sound speed c, the
+// Balsara-limited viscosity alpha~ = alpha_v |div v| / (|div v| + |curl v| +
+// eps c / h), alpha_d, rho and u.  Half the spline factor w'(q)/q K is what the
+// pair term uses (the average of i's and j's), and with t = 1 - q it is
+//   t > 1/2:  K (9 q - 6)     = kD + nkB t,   kD = 3K, nkB = -9K
+//   t <= 1/2: -3 K t^2 H / r  = kA t^2 / r,   kA = -3 K H
+// (the spline is C1 at q = 1/2, so either side may take the boundary).  The
+// pair sums take A2 = 2A against the halved factor, atq = -alpha~/4 and
+// adh = alpha_d / 2 as the halves of the pair averages, and rh = rho / 2.
+// Planes: q0 = {1/H, kA, nkB, kD}, q1 = {A2, c, atq, adh}, q2 = {rh, u, H^2, 0}.
 __device__ __forceinline__ ForceDerived derive_force(const float4 &p0, const float4 &p2, const float4 &p3, float ad,
                                                      float g, float eps)
 {
@@ -224,15 +235,24 @@ __device__ __forceinline__ ForceDerived derive_force(const float4 &p0, const flo
     const float div = fabsf(D * irho);
     const float curl = sqrtf(p3.x * p3.x + p3.y * p3.y + p3.z * p3.z) * irho;
     const float at = p3.w * div / (div + curl + eps * c / h);
+    const float K = kC3 * ih * ih * ih * ih * ih;
     ForceDerived f;
-    f.q0 = make_float4(H, ih, A, c);
-    f.q1 = make_float4(kC3 * ih * ih * ih * ih * ih, at, ad, rho);
-    f.q2 = make_float2(u, H * H);
+    f.q0 = make_float4(ih, -3.0f * K * H, -9.0f * K, 3.0f * K);
+    f.q1 = make_float4(2.0f * A, c, -0.25f * at, 0.5f * ad);
+    f.q2 = make_float4(0.5f * rho, u, H * H, 0.f);
     return f;
 }
 
-// derived planes of the batched form: float4 planes at q and q + 4P, a float2
-// plane at q + 8P (force); one float4 plane (gradient)
+// half the spline factor of one side (constants of derive_force): t = 1 - r/H
+// clamped at 0, so beyond the support the factor is exactly zero
+__device__ __forceinline__ float half_factor(float r, float invr, float ih, float kA, float nkB, float kD)
+{
+    const float t = fmaxf(fmaf(-r, ih, 1.0f), 0.0f);
+    return t > 0.5f ? fmaf(nkB, t, kD) : kA * t * t * invr;
+}
+
+// derived planes of the batched form: float4 planes at q, q + 4P and q + 8P
+// (force); one float4 plane (gradient)
 template <int LOOP, bool PREP>
 __device__ __forceinline__ void load_i(const InteractArgs &a, int64_t slot, bool valid, IData &d)
 {
@@ -242,7 +262,8 @@ __device__ __forceinline__ void load_i(const InteractArgs &a, int64_t slot, bool
         d.H = 0.f;
         d.H2 = -1.f;
         d.invH = 0.f;
-        d.vx = d.vy = d.vz = d.u = d.c = d.K5 = d.A = d.at = d.ad = d.rho = 0.f;
+        d.vx = d.vy = d.vz = d.u = d.c = 0.f;
+        d.kA = d.nkB = d.kD = d.A2 = d.atq = d.adh = d.rh = 0.f;
         return;
     }
     const float4 p0 = ((const float4 *)a.pack)[slot];
@@ -255,23 +276,25 @@ __device__ __forceinline__ void load_i(const InteractArgs &a, int64_t slot, bool
         if constexpr (PREP) {
             f.q0 = ((const float4 *)a.q)[slot];
             f.q1 = ((const float4 *)(a.q + 4 * a.P))[slot];
-            f.q2 = ((const float2 *)(a.q + 8 * a.P))[slot];
+            f.q2 = ((const float4 *)(a.q + 8 * a.P))[slot];
         } else {
             const float4 p2 = ((const float4 *)(a.pack + a.P * 32))[slot];
             const float4 p3 = ((const float4 *)(a.pack + a.P * 48))[slot];
             const float ad = ((const float *)(a.pack + a.P * 64))[slot];
             f = derive_force(p0, p2, p3, ad, g, a.eps);
         }
-        d.H = f.q0.x;
-        d.invH = f.q0.y;
-        d.A = f.q0.z;
-        d.c = f.q0.w;
-        d.K5 = f.q1.x;
-        d.at = f.q1.y;
-        d.ad = f.q1.z;
-        d.rho = f.q1.w;
-        d.u = f.q2.x;
-        d.H2 = f.q2.y;
+        d.H = kGammaK * p0.w;
+        d.invH = f.q0.x;
+        d.kA = f.q0.y;
+        d.nkB = f.q0.z;
+        d.kD = f.q0.w;
+        d.A2 = f.q1.x;
+        d.c = f.q1.y;
+        d.atq = f.q1.z;
+        d.adh = f.q1.w;
+        d.rh = f.q2.x;
+        d.u = f.q2.y;
+        d.H2 = f.q2.z;
     } else {
         d.H = kGammaK * p0.w;
         d.H2 = d.H * d.H;
@@ -317,8 +340,7 @@ struct JRec<2, false> {
 };
 template <>
 struct JRec<2, true> {
-    float4 p0, p1, q0, q1;
-    float2 q2;
+    float4 p0, p1, q0, q1, q2;
 };
 
 // loads of one j record; js is always a slot inside the buffer (the caller
@@ -338,7 +360,7 @@ __device__ __forceinline__ void load_j(const InteractArgs &a, int64_t js, JRec<L
         } else if constexpr (PREP) {
             r.q0 = ((const float4 *)a.q)[js];
             r.q1 = ((const float4 *)(a.q + 4 * a.P))[js];
-            r.q2 = ((const float2 *)(a.q + 8 * a.P))[js];
+            r.q2 = ((const float4 *)(a.q + 8 * a.P))[js];
         } else {
             r.p2 = ((const float4 *)(a.pack + a.P * 32))[js];
             r.p3 = ((const float4 *)(a.pack + a.P * 48))[js];
@@ -375,9 +397,9 @@ __device__ __forceinline__ void stage_j(const InteractArgs &a, Lds<LOOP, WIN> &L
             } else {
                 f = derive_force(r.p0, r.p2, r.p3, r.ad, a.gam, a.eps);
             }
-            L.c2[k] = make_float4(f.q0.x, f.q0.y, f.q0.z, f.q0.w);
-            L.c3[k] = make_float4(f.q1.x, f.q1.y, f.q1.z, f.q1.w);
-            L.c4[k] = make_float4(f.q2.x, f.q2.y, jsb, 0.f);
+            L.c2[k] = f.q0;
+            L.c3[k] = f.q1;
+            L.c4[k] = make_float4(f.q2.x, f.q2.y, f.q2.z, jsb);
         }
     }
 }
@@ -393,7 +415,7 @@ __device__ __forceinline__ float test_sign(const Lds<LOOP, WIN> &L, int k, const
 {
     const float4 q = L.ph[k];
     float t;
-    if constexpr (PERCAND) t = (d.t0 - fmaxf(d.H2, L.c4[k].y)) - q.w;
+    if constexpr (PERCAND) t = (d.t0 - fmaxf(d.H2, L.c4[k].z)) - q.w;
     else t = d.t0 - q.w;
     return fmaf(d.nx2, q.x, fmaf(d.ny2, q.y, fmaf(d.nz2, q.z, t)));
 }
@@ -439,8 +461,7 @@ template <>
 struct Cand<2> {
     float x, y, z;
     int32_t js;
-    float4 c1, c2, c3;  // v m | H 1/H A c | K5 alpha~ alpha_d rho
-    float2 c4;          // u H^2
+    float4 c1, c2, c3, c4;  // v m | 1/H kA nkB kD | A2 c atq adh | rh u H^2 slot
 };
 
 template <int LOOP, int WIN>
@@ -460,9 +481,8 @@ __device__ __forceinline__ Cand<LOOP> cand_load(const Lds<LOOP, WIN> &L, int k)
             c.js = __float_as_int(c.c2.w);
         } else {
             c.c3 = L.c3[k];
-            const float4 c4 = L.c4[k];
-            c.c4 = make_float2(c4.x, c4.y);
-            c.js = __float_as_int(c4.z);
+            c.c4 = L.c4[k];
+            c.js = __float_as_int(c.c4.w);
         }
     }
     return c;
@@ -499,7 +519,7 @@ __device__ __forceinline__ void pair(const InteractArgs &a, const Cand<LOOP> &c,
             if constexpr (LOOP == 1) {
                 if (!(r2 < d.H2)) return;
             } else {
-                if (!(r2 < fmaxf(d.H2, c.c4.y))) return;
+                if (!(r2 < fmaxf(d.H2, c.c4.z))) return;
             }
         }
         const float4 c1 = c.c1;
@@ -526,30 +546,29 @@ __device__ __forceinline__ void pair(const InteractArgs &a, const Cand<LOOP> &c,
                 if (c.js != d.slot && r2 < d.H2) acc.s5 = fmaxf(acc.s5, vs);
             }
         } else {
-            const float4 c2 = c.c2;  // H 1/H A c
-            const float4 c3 = c.c3;  // K5 at ad rho
-            const float2 c4 = c.c4;  // u H^2
-            const float uj = c4.x;
+            const float4 c2 = c.c2;  // 1/H kA nkB kD
+            const float4 c3 = c.c3;  // A2 c atq adh
+            const float4 c4 = c.c4;  // rh u H^2 slot
+            // fi, fj: halves of w'(q)/q K of i and j, so fb is their average
             float fi, fj;
             if constexpr (CNT) {
-                fi = r2 < d.H2 ? d.K5 * spline_f(r * d.invH, d.H * invr) : 0.0f;
-                fj = r2 < c4.y ? c3.x * spline_f(r * c2.y, c2.x * invr) : 0.0f;
+                fi = r2 < d.H2 ? half_factor(r, invr, d.invH, d.kA, d.nkB, d.kD) : 0.0f;
+                fj = r2 < c4.z ? half_factor(r, invr, c2.x, c2.y, c2.z, c2.w) : 0.0f;
             } else {
-                fi = d.K5 * spline_f(r * d.invH, d.H * invr);
-                fj = c3.x * spline_f(r * c2.y, c2.x * invr);
+                fi = half_factor(r, invr, d.invH, d.kA, d.nkB, d.kD);
+                fj = half_factor(r, invr, c2.x, c2.y, c2.z, c2.w);
             }
-            const float fb = 0.5f * (fi + fj);
-            const float vsig = d.c + c2.w - a.beta * mu;
-            const float irb = fast_rcp(0.5f * (d.rho + c3.w));
-            const float Pi = -0.25f * (d.at + c3.y) * vsig * mu * irb;
-            const float mj = c1.w;
-            const float s = fmaf(d.A, fi, fmaf(c2.z, fj, Pi * fb));
-            const float ms = mj * s;
+            const float fb = fi + fj;
+            const float vsig = d.c + c3.y - a.beta * mu;
+            const float g = fast_rcp(d.rh + c4.x) * fb;                // fb / rho_ij
+            const float pf = (d.atq + c3.z) * vsig * mu * g;           // Pi_ij fb
+            const float ai = d.A2 * fi, aj = c3.x * fj;                // A_i w_i, A_j w_j
+            const float ms = c1.w * ((ai + aj) + pf);
             acc.s0 = fmaf(-ms, rx, acc.s0);
             acc.s1 = fmaf(-ms, ry, acc.s1);
             acc.s2 = fmaf(-ms, rz, acc.s2);
-            const float cond = 0.5f * (d.ad + c3.z) * fabsf(dot) * (d.u - uj) * fb * irb;
-            acc.s3 = fmaf(mj, fmaf(d.A * fi, dot, fmaf(0.5f * Pi * fb, dot, cond)), acc.s3);
+            const float cond = (d.adh + c3.w) * fabsf(dot) * (d.u - c4.y) * g;
+            acc.s3 = fmaf(c1.w, fmaf(dot, fmaf(0.5f, pf, ai), cond), acc.s3);
             if constexpr (CNT) acc.n++;
         }
     }
@@ -924,7 +943,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
         const ForceDerived f = derive_force(p0, p2, p3, ad, a.gam, a.eps);
         ((float4 *)a.q)[s] = f.q0;
         ((float4 *)(a.q + 4 * a.P))[s] = f.q1;
-        ((float2 *)(a.q + 8 * a.P))[s] = f.q2;
+        ((float4 *)(a.q + 8 * a.P))[s] = f.q2;
     }
 }
 
