@@ -122,19 +122,25 @@ __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sq
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// cubic spline pieces in q = r / H: w(q), w'(q) and w'(q)/q (clamped at q = 1)
+// cubic spline pieces in q = r / H, from t = 1 - q and s = 1/2 - q, each
+// clamped at 0: w = 2 t^3 - 8 s^3 and w' = 24 s^2 - 6 t^2.  The inner piece
+// (q < 1/2) is the outer one minus 8 s^3, a cubic that vanishes with its slope
+// at q = 1/2, so one branch-free form covers the support and gives exactly 0
+// beyond it.
 __device__ __forceinline__ void spline_w_dw(float q, float &w, float &dw)
 {
-    const float t = fmaxf(1.0f - q, 0.0f), t2 = t * t, q2 = q * q;
-    const bool in = q < 0.5f;
-    w = in ? fmaf(6.0f * q2, q - 1.0f, 1.0f) : 2.0f * t2 * t;
-    dw = in ? q * fmaf(18.0f, q, -12.0f) : -6.0f * t2;
+    const float t = fmaxf(1.0f - q, 0.0f), s = fmaxf(t - 0.5f, 0.0f);
+    const float t2 = t * t, s2 = s * s;
+    w = fmaf(2.0f * t2, t, -8.0f * s2 * s);
+    dw = fmaf(24.0f, s2, -6.0f * t2);
 }
-// w'(q)/q given r and H / r (inner branch needs no division)
-__device__ __forceinline__ float spline_f(float q, float H_over_r)
+// w'(q)/q from r, 1/r, 1/H and -6H: 18 q - 12 = 6 - 18 t for t > 1/2, else
+// -6 t^2 H / r, with t = 1 - r/H clamped at 0 (the spline is C1 at t = 1/2,
+// so either side may take the boundary; beyond the support the factor is 0)
+__device__ __forceinline__ float spline_f(float r, float invr, float ih, float m6H)
 {
-    const float t = fmaxf(1.0f - q, 0.0f);
-    return q < 0.5f ? fmaf(18.0f, q, -12.0f) : -6.0f * t * t * H_over_r;
+    const float t = fmaxf(fmaf(-r, ih, 1.0f), 0.0f);
+    return t > 0.5f ? fmaf(-18.0f, t, 6.0f) : m6H * t * t * invr;
 }
 
 // ---------------------------------------------------------------------------
@@ -175,7 +181,7 @@ struct Lds<2, WIN> {
 struct IData {
     float x, y, z, H, H2, invH;    // position relative to the i-tile centre
     float vx, vy, vz, u, c;
-    float kA, nkB, kD, A2, atq, adh, rh;  // force: see derive_force
+    float kA, nkB, kD, A2, atq, adh, rh;  // force: see derive_force; gradient: kA = -6H
     float nx2, ny2, nz2;            // -2 x, -2 y, -2 z (phase-1 test)
     float t0;                       // |x|^2 - delta - H^2 (density, gradient) or |x|^2 - delta (force)
     float ri, xi2;                  // |x| and |x|^2
@@ -299,6 +305,7 @@ __device__ __forceinline__ void load_i(const InteractArgs &a, int64_t slot, bool
         d.H = kGammaK * p0.w;
         d.H2 = d.H * d.H;
         d.invH = 1.0f / d.H;
+        d.kA = -6.0f * d.H;
     }
     if constexpr (LOOP >= 1) {
         const float4 p1 = ((const float4 *)(a.pack + a.P * 16))[slot];
@@ -468,12 +475,14 @@ template <int LOOP, int WIN>
 __device__ __forceinline__ Cand<LOOP> cand_load(const Lds<LOOP, WIN> &L, int k)
 {
     Cand<LOOP> c;
-    const float4 p = L.ph[k];
+    // byte offsets by shifts (the planes' strides are 16 and 4 bytes)
+    const uint32_t o4 = (uint32_t)k << 2;
+    const float4 p = *(const float4 *)((const char *)L.ph + (o4 << 2));
     c.x = p.x;
     c.y = p.y;
     c.z = p.z;
     if constexpr (LOOP == 0) {
-        c.m = L.m[k];
+        c.m = *(const float *)((const char *)L.m + o4);
     } else {
         c.c1 = L.c1[k];
         c.c2 = L.c2[k];
@@ -524,14 +533,15 @@ __device__ __forceinline__ void pair(const InteractArgs &a, const Cand<LOOP> &c,
         }
         const float4 c1 = c.c1;
         const float vx = d.vx - c1.x, vy = d.vy - c1.y, vz = d.vz - c1.z;
-        // r = 0 (j = i, or coincident particles) gives a finite 1/r and r = 0
-        const float invr = fast_rsq(fmaxf(r2, 0x1p-126f));
+        // r = 0 (j = i, or coincident particles) gives a finite 1/r and r = 0;
+        // the added 2^-126 is below half an ulp of any r^2 above 2^-100
+        const float invr = fast_rsq(r2 + 0x1p-126f);
         const float r = r2 * invr;
         const float dot = fmaf(vz, rz, fmaf(vy, ry, vx * rx));
         const float mu = fminf(dot * invr, 0.0f);
         if constexpr (LOOP == 1) {
             const float4 c2 = c.c2;  // u m/rho c slot
-            const float f = spline_f(r * d.invH, d.H * invr);    // w'/q
+            const float f = spline_f(r, invr, d.invH, d.kA);    // w'/q
             const float mf = c1.w * f;
             acc.s0 = fmaf(mf, dot, acc.s0);                                   // D
             acc.s1 = fmaf(mf, fmaf(vy, rz, -vz * ry), acc.s1);                // R
@@ -540,10 +550,10 @@ __device__ __forceinline__ void pair(const InteractArgs &a, const Cand<LOOP> &c,
             acc.s4 = fmaf(c2.y * (d.u - c2.x), f, acc.s4);                    // L / 2
             const float vs = d.c + c2.z - a.beta * mu;
             if constexpr (CNT) {
-                acc.s5 = fmaxf(acc.s5, vs);                                   // V
+                if (vs > acc.s5) acc.s5 = vs;                                 // V
                 acc.n++;
             } else {
-                if (c.js != d.slot && r2 < d.H2) acc.s5 = fmaxf(acc.s5, vs);
+                if (c.js != d.slot && r2 < d.H2 && vs > acc.s5) acc.s5 = vs;
             }
         } else {
             const float4 c2 = c.c2;  // 1/H kA nkB kD
