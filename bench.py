@@ -148,8 +148,8 @@ def main():
     elif a.tuning != "default":
         tune.apply(tuning, json.load(open(a.tuning)))
         tuned_from = a.tuning
-    log(f"tuning ({tuned_from}): blocks/CU {tuning.blocks_per_cu} windows {list(tuning.window)} "
-        f"queue {tuning.queue} pack waves {tuning.pack_waves}")
+    log(f"tuning ({tuned_from}): blocks/CU {tuning.blocks_per_cu} per loop {list(tuning.blocks_per_loop)} "
+        f"windows {list(tuning.window)} queue {tuning.queue} pack waves {tuning.pack_waves}")
     params = sph.default_params()
     stream = torch.cuda.current_stream()
     bufs = {L: sph.cell_buffers(plan, L) for L in range(3)}
@@ -251,6 +251,7 @@ def main():
         "config": {"workload": workload_name(a.config, ps), "layout": a.layout, "form": "batched",
                    "pairs_per_step": total_pairs, "device": tune.device_key(dev), "cu": dev.multi_processor_count,
                    "tuning": {"source": tuned_from, "blocks_per_cu": tuning.blocks_per_cu,
+                              "blocks_per_loop": list(tuning.blocks_per_loop),
                               "window": list(tuning.window), "queue": tuning.queue,
                               "pack_waves": tuning.pack_waves}},
         "pack_unpack_GBps": pack_unpack_gbs,

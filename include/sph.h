@@ -125,7 +125,9 @@ typedef struct sph_tuning {
                                 a spatially contiguous share of the tiles (equal
                                 estimated cost each), stealing from the other
                                 shares once its own is drained                     */
-    int32_t reserved[2];
+    int32_t blocks_per_loop[3]; /* per loop (density, gradient, force): 1..64 replaces
+                                blocks_per_cu for that loop's kernel, 0 keeps it    */
+    int32_t reserved;
 } sph_tuning;
 
 typedef struct sph_plan sph_plan; /* library-owned, opaque */

@@ -699,6 +699,9 @@ static sph_status check_tuning(const sph_tuning *t)
             return fail(SPH_E_ARG, "window must be 128, 256 or 512");
     if (t->pack_waves < 1 || t->pack_waves > 8) return fail(SPH_E_ARG, "pack_waves outside 1..8");
     if (t->queue < 0 || t->queue > 2) return fail(SPH_E_ARG, "queue must be 0, 1 or 2");
+    for (int k = 0; k < 3; ++k)
+        if (t->blocks_per_loop[k] < 0 || t->blocks_per_loop[k] > 64)
+            return fail(SPH_E_ARG, "blocks_per_loop outside 0..64");
     return SPH_OK;
 }
 

@@ -427,7 +427,8 @@ __device__ __forceinline__ float test_sign(const Lds<LOOP, WIN> &L, int k, const
     return fmaf(d.nx2, q.x, fmaf(d.ny2, q.y, fmaf(d.nz2, q.z, t)));
 }
 
-// phase 1 over the nw words of a window: one 32-bit mask per word and lane
+// phase 1 over the nw words of a window on the VALU: one 32-bit mask per word
+// and lane, candidate kb + b at bit b
 template <int LOOP, int WIN, bool PERCAND>
 __device__ __forceinline__ void test_words(Lds<LOOP, WIN> &L, int nc, int nw, const IData &dd, bool valid)
 {
@@ -436,16 +437,70 @@ __device__ __forceinline__ void test_words(Lds<LOOP, WIN> &L, int nc, int nw, co
         uint32_t m = 0;
         const int kb = 32 * w;
         const int kn = __builtin_amdgcn_readfirstlane(min(32, nc - kb));
-        // shift each candidate's sign bit in: candidate kb + b ends at bit 31 - b
+        // shift each candidate's sign bit in from the top candidate down
         if (kn == 32) {
 #pragma unroll 8
-            for (int b = 0; b < 32; ++b)
+            for (int b = 31; b >= 0; --b)
                 m = __builtin_amdgcn_alignbit(m, __float_as_uint(test_sign<LOOP, WIN, PERCAND>(L, kb + b, dd)), 31);
         } else {
-            for (int b = 0; b < kn; ++b)
+            for (int b = kn - 1; b >= 0; --b)
                 m = __builtin_amdgcn_alignbit(m, __float_as_uint(test_sign<LOOP, WIN, PERCAND>(L, kb + b, dd)), 31);
-            m <<= (32 - kn);
         }
+        L.mask[w][lane] = valid ? m : 0u;
+    }
+}
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// sign bits of the 16 results of one 32x32 product, result r at bit r
+__device__ __forceinline__ uint32_t sign_bits(const f32x16 &d)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int r = 15; r >= 0; --r) m = __builtin_amdgcn_alignbit(m, __float_as_uint(d[r]), 31);
+    return m;
+}
+
+// Phase 1 on the matrix cores.  The expanded test of every candidate j against
+// every lane's particle i is one entry of a 32 x 64 product with K = 6:
+//   (x_j, y_j, z_j, -|x_j|^2, 1, 0) . (-2 x_i, -2 y_i, -2 z_i, -1, t0_i, 0),
+// three v_mfma_f32_32x32x2f32 per half of the wave's particles (A row i = a
+// candidate, B column = a particle; lane l supplies A[l % 32][l / 32] and
+// B[l / 32][l % 32]; result r of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4 of
+// column l % 32).  Row i reads window slot b(i) = 16 ((i / 4) % 2) + 4 (i / 8)
+// + i % 4, so that after one permlane32 swap of the two halves' sign masks every
+// lane holds its own particle's bits with candidate kb + b at bit b, as the
+// VALU test leaves them.  The products are accumulated in FP32 with no more
+// roundings than the VALU form, which the margin delta covers.
+template <int LOOP, int WIN>
+__device__ __forceinline__ void test_words_mfma(Lds<LOOP, WIN> &L, int nc, int nw, const IData &dd, bool valid)
+{
+    const int lane = threadIdx.x & 63;
+    // B operands of the particle halves 0-31 ([0]) and 32-63 ([1])
+    const auto bxy = __builtin_amdgcn_permlane32_swap(__float_as_uint(dd.nx2), __float_as_uint(dd.ny2), false, false);
+    const auto bzw = __builtin_amdgcn_permlane32_swap(__float_as_uint(dd.nz2), __float_as_uint(-1.0f), false, false);
+    const auto bt = __builtin_amdgcn_permlane32_swap(__float_as_uint(dd.t0), 0u, false, false);
+    const float one = lane < 32 ? 1.0f : 0.0f;
+    const int i = lane & 31;
+    const int slot = 16 * ((i >> 2) & 1) + 4 * (i >> 3) + (i & 3);
+    const int comp = lane >> 5;  // x (z) in the lower half, y (w) in the upper
+    for (int w = 0; w < nw; ++w) {
+        const int kb = 32 * w;
+        const float *q = (const float *)&L.ph[kb + slot];
+        const float axy = q[comp], azw = q[2 + comp];
+        // one half at a time: 16 accumulator registers live, not 32
+        f32x16 d = __builtin_amdgcn_mfma_f32_32x32x2f32(axy, __uint_as_float(bxy[0]), f32x16{}, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_32x32x2f32(azw, __uint_as_float(bzw[0]), d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_32x32x2f32(one, __uint_as_float(bt[0]), d, 0, 0, 0);
+        const uint32_t m0 = sign_bits(d);
+        __builtin_amdgcn_sched_barrier(0);
+        d = __builtin_amdgcn_mfma_f32_32x32x2f32(axy, __uint_as_float(bxy[1]), f32x16{}, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_32x32x2f32(azw, __uint_as_float(bzw[1]), d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_32x32x2f32(one, __uint_as_float(bt[1]), d, 0, 0, 0);
+        const auto h = __builtin_amdgcn_permlane32_swap(m0, sign_bits(d), false, false);
+        uint32_t m = h[0] | (h[1] << 16);
+        const int kn = __builtin_amdgcn_readfirstlane(min(32, nc - kb));
+        if (kn < 32) m &= (1u << kn) - 1u;  // slots beyond the window's count
         L.mask[w][lane] = valid ? m : 0u;
     }
 }
@@ -630,12 +685,12 @@ __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, 
         dd.t0 = dd.xi2 - test_delta(dd.ri, dd.rj);
         if (hw <= 1.02f * dd.hmin) {
             dd.t0 -= fmaxf(dd.H2, hw * hw);
-            test_words<LOOP, WIN, false>(L, nc, nw, dd, valid);
+            test_words_mfma<LOOP, WIN>(L, nc, nw, dd, valid);
         } else {
             test_words<LOOP, WIN, true>(L, nc, nw, dd, valid);
         }
     } else {
-        test_words<LOOP, WIN, false>(L, nc, nw, dd, valid);
+        test_words_mfma<LOOP, WIN>(L, nc, nw, dd, valid);
     }
     wave_sync();
     if (nw == 0) return;
@@ -649,8 +704,8 @@ __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, 
         const bool act = cur != 0;
         if (!__any(act)) break;
         if (act) {
-            const int b = __builtin_clz(cur);
-            cur &= ~(0x80000000u >> b);
+            const int b = __builtin_ctz(cur);  // lowest slot first
+            cur &= cur - 1u;
             pair<LOOP, CNT>(a, cand_load<LOOP, WIN>(L, 32 * w + b), d, acc);
         }
     }
@@ -1025,8 +1080,9 @@ sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, 
         a.queue = (int32_t *)ws;
         a.use_queue = tn->queue;
         if (a.nitems == 0) return SPH_OK;
-        // blocks_per_cu counts groups of four waves
-        grid = (unsigned)std::min<int64_t>((int64_t)tn->blocks_per_cu * 4 * p->num_cu, a.nitems);
+        // blocks_per_cu counts groups of four waves; a loop may set its own
+        const int bpc = tn->blocks_per_loop[loop] > 0 ? tn->blocks_per_loop[loop] : tn->blocks_per_cu;
+        grid = (unsigned)std::min<int64_t>((int64_t)bpc * 4 * p->num_cu, a.nitems);
         win = tn->window[loop];
         if (a.use_queue) {
             hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, a.queue);

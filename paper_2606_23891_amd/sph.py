@@ -42,7 +42,7 @@ class sph_params(C.Structure):
 
 class sph_tuning(C.Structure):
     _fields_ = [("blocks_per_cu", C.c_int32), ("window", C.c_int32 * 3), ("pack_waves", C.c_int32),
-                ("queue", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("queue", C.c_int32), ("blocks_per_loop", C.c_int32 * 3), ("reserved", C.c_int32)]
 
 
 class sph_plan_info(C.Structure):

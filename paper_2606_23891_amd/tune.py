@@ -1,8 +1,9 @@
 """Autotuner for the batched form's launch parameters.
 
 For each loop it times the interaction kernel over candidate windows (the LDS
-candidate buffer per wave), persistent-grid sizes (blocks per CU) and work
-distribution (device queue or static stride), and times pack + unpack over
+candidate buffer per wave) and persistent-grid sizes (blocks per CU), each loop
+keeping its own, under each work distribution (static stride, one queue, per-XCD
+queues; shared by the loops), and times pack + unpack over
 waves per block; it keeps the fastest of each (median of a few HIP-event
 timed repetitions on the device) and records them in a JSON cache keyed by
 device name and workload signature.  ``bench.py --tuning auto`` reads the cache.
@@ -51,9 +52,10 @@ def load(device: str, sig: str):
 
 def apply(tuning, entry: dict):
     for k, v in entry.items():
-        if k == "window":
+        if k in ("window", "blocks_per_loop"):
+            arr = getattr(tuning, k)
             for i, w in enumerate(v):
-                tuning.window[i] = int(w)
+                arr[i] = int(w)
         elif k in ("blocks_per_cu", "pack_waves", "queue"):
             setattr(tuning, k, int(v))
     return tuning
@@ -111,29 +113,30 @@ def tune(plan, store, log=print):
         if pw_t is None or ms < pw_t:
             pw_best, pw_t = pw, ms
     best["pack_waves"] = pw_best
-    # interaction kernels; the grid size and queue mode are shared by the loops,
-    # so they are chosen on the sum of the three loops' best windows
+    # interaction kernels: each loop takes its own window and grid size; the
+    # queue mode is shared, chosen on the sum of the loops' best times
     totals = {}
-    for bpc, q in itertools.product(BLOCKS_PER_CU, QUEUE):
-        tot, wins = 0.0, []
+    for q in QUEUE:
+        tot, wins, bpcs = 0.0, [], []
         for L in range(3):
             pack, res = bufs[L]
             sph.sph_pack_cells(plan, L, store, pack)
-            bw, bt = None, None
-            for w in WINDOWS[L]:
+            bk, bt = None, None
+            for bpc, w in itertools.product(BLOCKS_PER_CU, WINDOWS[L]):
                 t = sph.default_tuning()
                 t.blocks_per_cu, t.queue = bpc, q
                 t.window[L] = w
                 ms = _timed(lambda: sph.sph_interact_cells(plan, L, pack, res, ws, params=params, tuning=t))
                 times[f"loop{L}_bpc{bpc}_q{q}_w{w}"] = ms
                 if bt is None or ms < bt:
-                    bw, bt = w, ms
+                    bk, bt = (bpc, w), ms
             tot += bt
-            wins.append(bw)
-        totals[(bpc, q)] = (tot, wins)
-        log(f"blocks/CU={bpc} queue={q}: {tot:.3f} ms (windows {wins})")
-    (bpc, q), (tot, wins) = min(totals.items(), key=lambda kv: kv[1][0])
-    best.update(blocks_per_cu=bpc, queue=q, window=wins)
+            bpcs.append(bk[0])
+            wins.append(bk[1])
+        totals[q] = (tot, wins, bpcs)
+        log(f"queue={q}: {tot:.3f} ms (windows {wins}, blocks/CU {bpcs})")
+    q, (tot, wins, bpcs) = min(totals.items(), key=lambda kv: kv[1][0])
+    best.update(blocks_per_cu=bpcs[2], blocks_per_loop=bpcs, queue=q, window=wins)
     return best, times
 
 
