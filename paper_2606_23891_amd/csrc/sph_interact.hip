@@ -215,7 +215,7 @@ __device__ __forceinline__ float4 derive_gradient(const float4 &p1, const float2
 }
 
 struct ForceDerived {
-    float4 q0, q1, q2;
+    float4 q0, q1;
 };
 
 // The force pair term needs, per particle, K = H^-5 (8/pi) (the spline's
@@ -229,7 +229,8 @@ struct ForceDerived {
 // (the spline is C1 at q = 1/2, so either side may take the boundary).  The
 // pair sums take A2 = 2A against the halved factor, atq = -alpha~/4 and
 // adh = alpha_d / 2 as the halves of the pair averages, and rh = rho / 2.
-// Planes: q0 = {1/H, kA, nkB, kD}, q1 = {A2, c, atq, adh}, q2 = {rh, u, H^2, 0}.
+// Planes: q0 = {1/H, K, A2, c}, q1 = {atq, adh, rh, u}; kA, nkB, kD and H^2
+// follow from K and h where a particle is loaded (spline_consts).
 __device__ __forceinline__ ForceDerived derive_force(const float4 &p0, const float4 &p2, const float4 &p3, float ad,
                                                      float g, float eps)
 {
@@ -243,10 +244,16 @@ __device__ __forceinline__ ForceDerived derive_force(const float4 &p0, const flo
     const float at = p3.w * div / (div + curl + eps * c / h);
     const float K = kC3 * ih * ih * ih * ih * ih;
     ForceDerived f;
-    f.q0 = make_float4(ih, -3.0f * K * H, -9.0f * K, 3.0f * K);
-    f.q1 = make_float4(2.0f * A, c, -0.25f * at, 0.5f * ad);
-    f.q2 = make_float4(0.5f * rho, u, H * H, 0.f);
+    f.q0 = make_float4(ih, K, 2.0f * A, c);
+    f.q1 = make_float4(-0.25f * at, 0.5f * ad, 0.5f * rho, u);
     return f;
+}
+
+// the spline constants of derive_force from K and h: {kA, nkB, kD, H}
+__device__ __forceinline__ float4 spline_consts(float K, float h)
+{
+    const float H = kGammaK * h;
+    return make_float4(-3.0f * K * H, -9.0f * K, 3.0f * K, H);
 }
 
 // half the spline factor of one side (constants of derive_force): t = 1 - r/H
@@ -257,8 +264,8 @@ __device__ __forceinline__ float half_factor(float r, float invr, float ih, floa
     return t > 0.5f ? fmaf(nkB, t, kD) : kA * t * t * invr;
 }
 
-// derived planes of the batched form: float4 planes at q, q + 4P and q + 8P
-// (force); one float4 plane (gradient)
+// derived planes of the batched form: float4 planes at q and q + 4P (force);
+// one float4 plane (gradient)
 template <int LOOP, bool PREP>
 __device__ __forceinline__ void load_i(const InteractArgs &a, int64_t slot, bool valid, IData &d)
 {
@@ -282,25 +289,25 @@ __device__ __forceinline__ void load_i(const InteractArgs &a, int64_t slot, bool
         if constexpr (PREP) {
             f.q0 = ((const float4 *)a.q)[slot];
             f.q1 = ((const float4 *)(a.q + 4 * a.P))[slot];
-            f.q2 = ((const float4 *)(a.q + 8 * a.P))[slot];
         } else {
             const float4 p2 = ((const float4 *)(a.pack + a.P * 32))[slot];
             const float4 p3 = ((const float4 *)(a.pack + a.P * 48))[slot];
             const float ad = ((const float *)(a.pack + a.P * 64))[slot];
             f = derive_force(p0, p2, p3, ad, g, a.eps);
         }
-        d.H = kGammaK * p0.w;
+        const float4 k = spline_consts(f.q0.y, p0.w);
+        d.H = k.w;
+        d.H2 = d.H * d.H;
         d.invH = f.q0.x;
-        d.kA = f.q0.y;
-        d.nkB = f.q0.z;
-        d.kD = f.q0.w;
-        d.A2 = f.q1.x;
-        d.c = f.q1.y;
-        d.atq = f.q1.z;
-        d.adh = f.q1.w;
-        d.rh = f.q2.x;
-        d.u = f.q2.y;
-        d.H2 = f.q2.z;
+        d.kA = k.x;
+        d.nkB = k.y;
+        d.kD = k.z;
+        d.A2 = f.q0.z;
+        d.c = f.q0.w;
+        d.atq = f.q1.x;
+        d.adh = f.q1.y;
+        d.rh = f.q1.z;
+        d.u = f.q1.w;
     } else {
         d.H = kGammaK * p0.w;
         d.H2 = d.H * d.H;
@@ -347,7 +354,7 @@ struct JRec<2, false> {
 };
 template <>
 struct JRec<2, true> {
-    float4 p0, p1, q0, q1, q2;
+    float4 p0, p1, q0, q1;
 };
 
 // loads of one j record; js is always a slot inside the buffer (the caller
@@ -367,7 +374,6 @@ __device__ __forceinline__ void load_j(const InteractArgs &a, int64_t js, JRec<L
         } else if constexpr (PREP) {
             r.q0 = ((const float4 *)a.q)[js];
             r.q1 = ((const float4 *)(a.q + 4 * a.P))[js];
-            r.q2 = ((const float4 *)(a.q + 8 * a.P))[js];
         } else {
             r.p2 = ((const float4 *)(a.pack + a.P * 32))[js];
             r.p3 = ((const float4 *)(a.pack + a.P * 48))[js];
@@ -400,13 +406,13 @@ __device__ __forceinline__ void stage_j(const InteractArgs &a, Lds<LOOP, WIN> &L
             if constexpr (PREP) {
                 f.q0 = r.q0;
                 f.q1 = r.q1;
-                f.q2 = r.q2;
             } else {
                 f = derive_force(r.p0, r.p2, r.p3, r.ad, a.gam, a.eps);
             }
-            L.c2[k] = f.q0;
-            L.c3[k] = f.q1;
-            L.c4[k] = make_float4(f.q2.x, f.q2.y, f.q2.z, jsb);
+            const float4 sc = spline_consts(f.q0.y, r.p0.w);
+            L.c2[k] = make_float4(f.q0.x, sc.x, sc.y, sc.z);
+            L.c3[k] = make_float4(f.q0.z, f.q0.w, f.q1.x, f.q1.y);
+            L.c4[k] = make_float4(f.q1.z, f.q1.w, sc.w * sc.w, jsb);
         }
     }
 }
@@ -1008,7 +1014,6 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
         const ForceDerived f = derive_force(p0, p2, p3, ad, a.gam, a.eps);
         ((float4 *)a.q)[s] = f.q0;
         ((float4 *)(a.q + 4 * a.P))[s] = f.q1;
-        ((float4 *)(a.q + 8 * a.P))[s] = f.q2;
     }
 }
 

@@ -161,7 +161,7 @@ inline size_t result_bytes_for(int loop, int64_t nslot)
 // 1 float2) loop
 constexpr size_t kQueueBytes = 256;
 static_assert(kQueues * kQueueStride * sizeof(int32_t) <= kQueueBytes, "queue counters");
-constexpr int kDerivedFloats[3] = {0, 4, 12};
+constexpr int kDerivedFloats[3] = {0, 4, 8};
 inline size_t interact_ws_bytes_for(int loop, int64_t n)
 {
     return kQueueBytes + (size_t)round_slots(n) * 4 * kDerivedFloats[loop];
