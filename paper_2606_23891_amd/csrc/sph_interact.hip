@@ -79,37 +79,6 @@ struct InteractArgs {
     float gam, beta, eps;
 };
 
-// lane-shuffled copy of v (DPP); rows outside ROW_MASK keep v
-template <int CTRL, int ROW_MASK = 0xF>
-__device__ __forceinline__ float dpp(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
-}
-
-// maximum over the 64 lanes of a converged wave, returned uniform: quad swaps,
-// half-row and row mirrors, then row broadcasts carry the result to lane 63
-__device__ __forceinline__ float wave_max_u(float v)
-{
-    v = fmaxf(v, dpp<0xB1>(v));       // quad_perm [1,0,3,2]
-    v = fmaxf(v, dpp<0x4E>(v));       // quad_perm [2,3,0,1]
-    v = fmaxf(v, dpp<0x141>(v));      // row_half_mirror
-    v = fmaxf(v, dpp<0x140>(v));      // row_mirror
-    v = fmaxf(v, dpp<0x142, 0xA>(v)); // row_bcast15
-    v = fmaxf(v, dpp<0x143, 0xC>(v)); // row_bcast31
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-}
-
-__device__ __forceinline__ float wave_min_u(float v)
-{
-    v = fminf(v, dpp<0xB1>(v));
-    v = fminf(v, dpp<0x4E>(v));
-    v = fminf(v, dpp<0x141>(v));
-    v = fminf(v, dpp<0x140>(v));
-    v = fminf(v, dpp<0x142, 0xA>(v));
-    v = fminf(v, dpp<0x143, 0xC>(v));
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-}
-
 // wave-scope ordering of LDS traffic between lanes of one wave
 __device__ __forceinline__ void wave_sync()
 {

@@ -54,19 +54,6 @@ __device__ __forceinline__ void st(const StoreArg &s, int64_t p, T v)
     *reinterpret_cast<T *>(field_ptr<L, F, C>(s, p)) = v;
 }
 
-__device__ __forceinline__ float wave_min(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ float wave_max(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
 struct PackArgs {
     StoreArg store;
     const Chunk *chunks;
@@ -131,10 +118,11 @@ __global__ __launch_bounds__(512) void k_pack(PackArgs a)
             }
         }
     }
+    // chunk bounds by DPP reductions (VALU, no LDS round trips)
     const float inf = __builtin_huge_valf();
-    const float lx = wave_min(valid ? dx : inf), ly = wave_min(valid ? dy : inf), lz = wave_min(valid ? dz : inf);
-    const float hx = wave_max(valid ? dx : -inf), hy = wave_max(valid ? dy : -inf), hz = wave_max(valid ? dz : -inf);
-    const float hm = wave_max(valid ? kGammaK * hh : 0.f);
+    const float lx = wave_min_u(valid ? dx : inf), ly = wave_min_u(valid ? dy : inf), lz = wave_min_u(valid ? dz : inf);
+    const float hx = wave_max_u(valid ? dx : -inf), hy = wave_max_u(valid ? dy : -inf), hz = wave_max_u(valid ? dz : -inf);
+    const float hm = wave_max_u(valid ? kGammaK * hh : 0.f);
     if (lane == 0) {
         a.bounds[2 * c] = make_float4(lx, ly, lz, hm);
         a.bounds[2 * c + 1] = make_float4(hx, hy, hz, 0.f);
