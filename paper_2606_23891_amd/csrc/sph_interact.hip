@@ -7,26 +7,31 @@
 //   1. tile cull -- lane k tests j-tile k of the item's j-tile list against
 //      the i-tile's box (tile boxes are written by the pack kernel), so one
 //      ballot culls 64 tiles with one round trip to memory;
-//   2. stage -- for each surviving tile lane k holds j-particle k (the next
-//      tile's records are already in flight), drops it when it is beyond
+//   2. stage -- for each surviving tile lane k holds j-particle k (the records
+//      of a batch of tiles are loaded together), drops it when it is beyond
 //      reach of the i-tile's box, and the survivors are compacted (ballot +
 //      mbcnt) into an LDS candidate window together with the per-particle
 //      quantities the pair term needs (sound speed, A = P/(Omega rho^2),
-//      Balsara-limited viscosity, ...), computed once per candidate;
-//   3. when the window is full (or the tile list ends) every lane tests every
-//      candidate (broadcast LDS reads, ~8 VALU each) and records the hits as
-//      bits; then each lane walks only its own set bits and evaluates the pair
-//      term, reading the candidate record from LDS.
+//      Balsara-limited viscosity, ...);
+//   3. when the window is full (or the tile list ends) every lane's particle is
+//      tested against every candidate -- the expanded distance test is a small
+//      dense product, done on the matrix cores (test_words_mfma) -- and the
+//      hits are recorded as bits; then each lane walks only its own set bits
+//      and evaluates the pair term on the VALU, reading the candidate record
+//      from LDS.
 // Sums stay in registers: no atomics, a fixed order per lane, so results are
-// deterministic.  FP32 VALU throughout: pairwise kernel sums are not a dense
-// contraction, so MFMA does not apply.
+// deterministic.  The pair terms themselves are FP32 VALU work: a sum of
+// per-pair nonlinear terms is not a contraction.  Each kernel comes in two
+// variants: with pair counts (exact support and j != i tests before every
+// term) and without (the timed one; see pair()).
 //
 // Two work sources share the code:
 //   per-task (MODE 0): an item is one 64-slot chunk of one side of a task; the
 //     partner is the other side (the same side for a self task); results are
 //     the task's partial sums per slot, reduced later by unpack;
-//   batched (MODE 1): an item is one tile of one cell, pulled from a device
-//     work queue in descending-cost order; the partners are all neighbour
+//   batched (MODE 1): an item is one tile of one cell, pulled from device work
+//     queues (one queue in descending-cost order, or one per XCD over a
+//     spatially contiguous share); the partners are all neighbour
 //     cells of the cell, each translated into its frame; results are final.
 #include <hip/hip_runtime.h>
 
@@ -386,12 +391,12 @@ __device__ __forceinline__ void stage_j(const InteractArgs &a, Lds<LOOP, WIN> &L
     }
 }
 
-// Phase-1 test of candidate k, as a sign: the result is negative when
-// |x_i - x_j|^2 < H^2 + delta_i, evaluated as |x_i|^2 - delta_i - H^2 + |x_j|^2 -
-// 2 x_i.x_j with delta_i covering the rounding of these four operations, so the
-// hits are a superset of the exact test that the pair term applies again.  For
-// the force loop H^2 is max(H_i^2, Hw^2) with Hw the largest support of the
-// window's tiles, which bounds max(H_i, H_j) for every staged j.
+// Phase-1 test of candidate k on the VALU, as a sign: the result is negative
+// when |x_i - x_j|^2 < H^2 + delta_i, evaluated as |x_i|^2 - delta_i - H^2 +
+// |x_j|^2 - 2 x_i.x_j with delta_i covering the rounding of these operations, so
+// the hits are a superset of the exact test.  PERCAND (force loop, mixed
+// supports): H^2 is max(H_i^2, H_j^2) with the candidate's own H_j^2; otherwise
+// t0 already holds the support term.
 template <int LOOP, int WIN, bool PERCAND = false>
 __device__ __forceinline__ float test_sign(const Lds<LOOP, WIN> &L, int k, const IData &d)
 {
