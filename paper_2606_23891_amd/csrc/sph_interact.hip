@@ -122,34 +122,44 @@ __device__ __forceinline__ float spline_f(float r, float invr, float ih, float m
 // ---------------------------------------------------------------------------
 // LDS candidate window of one wave.  ph holds, per candidate, the position
 // relative to the i-tile centre and -|x|^2 (the phase-1 test reads only ph,
-// plus H^2 for the force loop); the other planes feed the pair term.  Every
-// plane of the gradient and force windows has a 16-byte stride, so one
-// address serves all reads of a candidate; the candidate's pack slot rides in
-// a spare component.
-template <int LOOP, int WIN>
+// plus 1/H for the force loop's mixed-support test); the other planes feed the
+// pair term.  Every plane of the gradient and force windows has a 16-byte
+// stride, so one address serves all reads of a candidate.  The gradient
+// window carries the candidate's pack slot in a spare component.  The force
+// window packs its 16 floats into four planes -- 64 bytes per candidate, so a
+// 128-candidate window and its masks take 10 KB and sixteen waves fit a CU --
+// and recomputes -|x|^2 (from x y z), nkB (= -3 kD) and H^2 (from 1/H) where
+// they are needed; its counting variant adds a slot array.
+template <int LOOP, int WIN, bool CNT>
 struct Lds;
 
-template <int WIN>
-struct Lds<0, WIN> {
+template <int WIN, bool CNT>
+struct Lds<0, WIN, CNT> {
     float4 ph[WIN];  // x y z -|x|^2
     float m[WIN];
     uint32_t mask[WIN / 32][64];
 };
-template <int WIN>
-struct Lds<1, WIN> {
+template <int WIN, bool CNT>
+struct Lds<1, WIN, CNT> {
     float4 ph[WIN];  // x y z -|x|^2
     float4 c1[WIN];  // vx vy vz m
     float4 c2[WIN];  // u m/rho c slot(bits)
     uint32_t mask[WIN / 32][64];
 };
 template <int WIN>
-struct Lds<2, WIN> {
-    float4 ph[WIN];  // x y z -|x|^2
-    float4 c1[WIN];  // vx vy vz m
-    float4 c2[WIN];  // 1/H kA nkB kD
-    float4 c3[WIN];  // A2 c atq adh
-    float4 c4[WIN];  // rh u H^2 slot(bits)
+struct LdsForce {
+    float4 ph[WIN];  // x y z vx
+    float4 c1[WIN];  // vy vz m 1/H
+    float4 c2[WIN];  // kA kD A2 c
+    float4 c3[WIN];  // atq adh rh u
     uint32_t mask[WIN / 32][64];
+};
+template <int WIN>
+struct Lds<2, WIN, false> : LdsForce<WIN> {
+};
+template <int WIN>
+struct Lds<2, WIN, true> : LdsForce<WIN> {
+    int32_t jslot[WIN];
 };
 
 struct IData {
@@ -358,36 +368,36 @@ __device__ __forceinline__ void load_j(const InteractArgs &a, int64_t js, JRec<L
 
 // stage candidate j (record r, pack slot js, translated by (tx,ty,tz) and
 // shifted to the i-tile centre (cx,cy,cz)) at LDS index k
-template <int LOOP, bool PREP, int WIN>
-__device__ __forceinline__ void stage_j(const InteractArgs &a, Lds<LOOP, WIN> &L, int k, int64_t js,
+template <int LOOP, bool PREP, int WIN, bool CNT>
+__device__ __forceinline__ void stage_j(const InteractArgs &a, Lds<LOOP, WIN, CNT> &L, int k, int64_t js,
                                         const JRec<LOOP, PREP> &r, float tx, float ty, float tz, float cx,
                                         float cy, float cz)
 {
     const float x = (r.p0.x + tx) - cx, y = (r.p0.y + ty) - cy, z = (r.p0.z + tz) - cz;
-    [[maybe_unused]] const float jsb = __int_as_float((int32_t)js);  // the slot, for the j != i test
-    L.ph[k] = make_float4(x, y, z, -fmaf(z, z, fmaf(y, y, x * x)));
     if constexpr (LOOP == 0) {
+        L.ph[k] = make_float4(x, y, z, -fmaf(z, z, fmaf(y, y, x * x)));
         L.m[k] = r.m;
-    } else {
+    } else if constexpr (LOOP == 1) {
+        L.ph[k] = make_float4(x, y, z, -fmaf(z, z, fmaf(y, y, x * x)));
         L.c1[k] = make_float4(r.p1.x, r.p1.y, r.p1.z, r.p1.w);
-        if constexpr (LOOP == 1) {
-            float4 q;
-            if constexpr (PREP) q = r.q0;
-            else q = derive_gradient(r.p1, r.p2, a.gam);
-            L.c2[k] = make_float4(q.x, q.y, q.z, jsb);
+        float4 q;
+        if constexpr (PREP) q = r.q0;
+        else q = derive_gradient(r.p1, r.p2, a.gam);
+        L.c2[k] = make_float4(q.x, q.y, q.z, __int_as_float((int32_t)js));  // slot: j != i test
+    } else {
+        ForceDerived f;
+        if constexpr (PREP) {
+            f.q0 = r.q0;
+            f.q1 = r.q1;
         } else {
-            ForceDerived f;
-            if constexpr (PREP) {
-                f.q0 = r.q0;
-                f.q1 = r.q1;
-            } else {
-                f = derive_force(r.p0, r.p2, r.p3, r.ad, a.gam, a.eps);
-            }
-            const float4 sc = spline_consts(f.q0.y, r.p0.w);
-            L.c2[k] = make_float4(f.q0.x, sc.x, sc.y, sc.z);
-            L.c3[k] = make_float4(f.q0.z, f.q0.w, f.q1.x, f.q1.y);
-            L.c4[k] = make_float4(f.q1.z, f.q1.w, sc.w * sc.w, jsb);
+            f = derive_force(r.p0, r.p2, r.p3, r.ad, a.gam, a.eps);
         }
+        const float4 sc = spline_consts(f.q0.y, r.p0.w);
+        L.ph[k] = make_float4(x, y, z, r.p1.x);
+        L.c1[k] = make_float4(r.p1.y, r.p1.z, r.p1.w, f.q0.x);
+        L.c2[k] = make_float4(sc.x, sc.z, f.q0.z, f.q0.w);
+        L.c3[k] = f.q1;
+        if constexpr (CNT) L.jslot[k] = (int32_t)js;
     }
 }
 
@@ -397,20 +407,27 @@ __device__ __forceinline__ void stage_j(const InteractArgs &a, Lds<LOOP, WIN> &L
 // the hits are a superset of the exact test.  PERCAND (force loop, mixed
 // supports): H^2 is max(H_i^2, H_j^2) with the candidate's own H_j^2; otherwise
 // t0 already holds the support term.
-template <int LOOP, int WIN, bool PERCAND = false>
-__device__ __forceinline__ float test_sign(const Lds<LOOP, WIN> &L, int k, const IData &d)
+template <int LOOP, int WIN, bool CNT, bool PERCAND>
+__device__ __forceinline__ float test_sign(const Lds<LOOP, WIN, CNT> &L, int k, const IData &d)
 {
     const float4 q = L.ph[k];
+    // -|x_j|^2: stored by the density and gradient windows, rebuilt for force
+    const float nq2 = LOOP == 2 ? -fmaf(q.z, q.z, fmaf(q.y, q.y, q.x * q.x)) : q.w;
     float t;
-    if constexpr (PERCAND) t = (d.t0 - fmaxf(d.H2, L.c4[k].z)) - q.w;
-    else t = d.t0 - q.w;
+    if constexpr (PERCAND) {
+        static_assert(LOOP == 2, "per-candidate supports are the force loop's");
+        const float ih = L.c1[k].w;
+        t = (d.t0 - fmaxf(d.H2, __builtin_amdgcn_rcpf(ih * ih))) - nq2;
+    } else {
+        t = d.t0 - nq2;
+    }
     return fmaf(d.nx2, q.x, fmaf(d.ny2, q.y, fmaf(d.nz2, q.z, t)));
 }
 
 // phase 1 over the nw words of a window on the VALU: one 32-bit mask per word
 // and lane, candidate kb + b at bit b
-template <int LOOP, int WIN, bool PERCAND>
-__device__ __forceinline__ void test_words(Lds<LOOP, WIN> &L, int nc, int nw, const IData &dd, bool valid)
+template <int LOOP, int WIN, bool CNT, bool PERCAND>
+__device__ __forceinline__ void test_words(Lds<LOOP, WIN, CNT> &L, int nc, int nw, const IData &dd, bool valid)
 {
     const int lane = threadIdx.x & 63;
     for (int w = 0; w < nw; ++w) {
@@ -421,10 +438,10 @@ __device__ __forceinline__ void test_words(Lds<LOOP, WIN> &L, int nc, int nw, co
         if (kn == 32) {
 #pragma unroll 8
             for (int b = 31; b >= 0; --b)
-                m = __builtin_amdgcn_alignbit(m, __float_as_uint(test_sign<LOOP, WIN, PERCAND>(L, kb + b, dd)), 31);
+                m = __builtin_amdgcn_alignbit(m, __float_as_uint(test_sign<LOOP, WIN, CNT, PERCAND>(L, kb + b, dd)), 31);
         } else {
             for (int b = kn - 1; b >= 0; --b)
-                m = __builtin_amdgcn_alignbit(m, __float_as_uint(test_sign<LOOP, WIN, PERCAND>(L, kb + b, dd)), 31);
+                m = __builtin_amdgcn_alignbit(m, __float_as_uint(test_sign<LOOP, WIN, CNT, PERCAND>(L, kb + b, dd)), 31);
         }
         L.mask[w][lane] = valid ? m : 0u;
     }
@@ -452,8 +469,8 @@ __device__ __forceinline__ uint32_t sign_bits(const f32x16 &d)
 // lane holds its own particle's bits with candidate kb + b at bit b, as the
 // VALU test leaves them.  The products are accumulated in FP32 with no more
 // roundings than the VALU form, which the margin delta covers.
-template <int LOOP, int WIN>
-__device__ __forceinline__ void test_words_mfma(Lds<LOOP, WIN> &L, int nc, int nw, const IData &dd, bool valid)
+template <int LOOP, int WIN, bool CNT>
+__device__ __forceinline__ void test_words_mfma(Lds<LOOP, WIN, CNT> &L, int nc, int nw, const IData &dd, bool valid)
 {
     const int lane = threadIdx.x & 63;
     // B operands of the particle halves 0-31 ([0]) and 32-63 ([1])
@@ -466,8 +483,16 @@ __device__ __forceinline__ void test_words_mfma(Lds<LOOP, WIN> &L, int nc, int n
     const int comp = lane >> 5;  // x (z) in the lower half, y (w) in the upper
     for (int w = 0; w < nw; ++w) {
         const int kb = 32 * w;
-        const float *q = (const float *)&L.ph[kb + slot];
-        const float axy = q[comp], azw = q[2 + comp];
+        float axy, azw;
+        if constexpr (LOOP == 2) {
+            const float4 v = L.ph[kb + slot];  // x y z vx: -|x|^2 rebuilt
+            axy = comp ? v.y : v.x;
+            azw = comp ? -fmaf(v.z, v.z, fmaf(v.y, v.y, v.x * v.x)) : v.z;
+        } else {
+            const float *q = (const float *)&L.ph[kb + slot];
+            axy = q[comp];
+            azw = q[2 + comp];
+        }
         // one half at a time: 16 accumulator registers live, not 32
         f32x16 d = __builtin_amdgcn_mfma_f32_32x32x2f32(axy, __uint_as_float(bxy[0]), f32x16{}, 0, 0, 0);
         d = __builtin_amdgcn_mfma_f32_32x32x2f32(azw, __uint_as_float(bzw[0]), d, 0, 0, 0);
@@ -501,13 +526,13 @@ struct Cand<1> {
 };
 template <>
 struct Cand<2> {
-    float x, y, z;
+    float x, y, z, vx;
     int32_t js;
-    float4 c1, c2, c3, c4;  // v m | 1/H kA nkB kD | A2 c atq adh | rh u H^2 slot
+    float4 c1, c2, c3;  // vy vz m 1/H | kA kD A2 c | atq adh rh u
 };
 
-template <int LOOP, int WIN>
-__device__ __forceinline__ Cand<LOOP> cand_load(const Lds<LOOP, WIN> &L, int k)
+template <int LOOP, int WIN, bool CNT>
+__device__ __forceinline__ Cand<LOOP> cand_load(const Lds<LOOP, WIN, CNT> &L, int k)
 {
     Cand<LOOP> c;
     // byte offsets by shifts (the planes' strides are 16 and 4 bytes)
@@ -524,9 +549,9 @@ __device__ __forceinline__ Cand<LOOP> cand_load(const Lds<LOOP, WIN> &L, int k)
         if constexpr (LOOP == 1) {
             c.js = __float_as_int(c.c2.w);
         } else {
+            c.vx = p.w;
             c.c3 = L.c3[k];
-            c.c4 = L.c4[k];
-            c.js = __float_as_int(c.c4.w);
+            if constexpr (CNT) c.js = L.jslot[k];
         }
     }
     return c;
@@ -563,11 +588,20 @@ __device__ __forceinline__ void pair(const InteractArgs &a, const Cand<LOOP> &c,
             if constexpr (LOOP == 1) {
                 if (!(r2 < d.H2)) return;
             } else {
-                if (!(r2 < fmaxf(d.H2, c.c4.z))) return;
+                if (!(r2 < fmaxf(d.H2, __builtin_amdgcn_rcpf(c.c1.w * c.c1.w)))) return;
             }
         }
         const float4 c1 = c.c1;
-        const float vx = d.vx - c1.x, vy = d.vy - c1.y, vz = d.vz - c1.z;
+        float vx, vy, vz;
+        if constexpr (LOOP == 1) {
+            vx = d.vx - c1.x;
+            vy = d.vy - c1.y;
+            vz = d.vz - c1.z;
+        } else {
+            vx = d.vx - c.vx;
+            vy = d.vy - c1.x;
+            vz = d.vz - c1.y;
+        }
         // r = 0 (j = i, or coincident particles) gives a finite 1/r and r = 0;
         // the added 2^-126 is below half an ulp of any r^2 above 2^-100
         const float invr = fast_rsq(r2 + 0x1p-126f);
@@ -591,29 +625,30 @@ __device__ __forceinline__ void pair(const InteractArgs &a, const Cand<LOOP> &c,
                 if (c.js != d.slot && r2 < d.H2 && vs > acc.s5) acc.s5 = vs;
             }
         } else {
-            const float4 c2 = c.c2;  // 1/H kA nkB kD
-            const float4 c3 = c.c3;  // A2 c atq adh
-            const float4 c4 = c.c4;  // rh u H^2 slot
+            const float mj = c1.z, ihj = c1.w;
+            const float4 c2 = c.c2;  // kA kD A2 c
+            const float4 c3 = c.c3;  // atq adh rh u
             // fi, fj: halves of w'(q)/q K of i and j, so fb is their average
             float fi, fj;
             if constexpr (CNT) {
                 fi = r2 < d.H2 ? half_factor(r, invr, d.invH, d.kA, d.nkB, d.kD) : 0.0f;
-                fj = r2 < c4.z ? half_factor(r, invr, c2.x, c2.y, c2.z, c2.w) : 0.0f;
+                fj = r2 < __builtin_amdgcn_rcpf(ihj * ihj) ? half_factor(r, invr, ihj, c2.x, -3.0f * c2.y, c2.y)
+                                                           : 0.0f;
             } else {
                 fi = half_factor(r, invr, d.invH, d.kA, d.nkB, d.kD);
-                fj = half_factor(r, invr, c2.x, c2.y, c2.z, c2.w);
+                fj = half_factor(r, invr, ihj, c2.x, -3.0f * c2.y, c2.y);
             }
             const float fb = fi + fj;
-            const float vsig = d.c + c3.y - a.beta * mu;
-            const float g = fast_rcp(d.rh + c4.x) * fb;                // fb / rho_ij
-            const float pf = (d.atq + c3.z) * vsig * mu * g;           // Pi_ij fb
-            const float ai = d.A2 * fi, aj = c3.x * fj;                // A_i w_i, A_j w_j
-            const float ms = c1.w * ((ai + aj) + pf);
+            const float vsig = d.c + c2.w - a.beta * mu;
+            const float g = fast_rcp(d.rh + c3.z) * fb;                // fb / rho_ij
+            const float pf = (d.atq + c3.x) * vsig * mu * g;           // Pi_ij fb
+            const float ai = d.A2 * fi, aj = c2.z * fj;                // A_i w_i, A_j w_j
+            const float ms = mj * ((ai + aj) + pf);
             acc.s0 = fmaf(-ms, rx, acc.s0);
             acc.s1 = fmaf(-ms, ry, acc.s1);
             acc.s2 = fmaf(-ms, rz, acc.s2);
-            const float cond = (d.adh + c3.w) * fabsf(dot) * (d.u - c4.y) * g;
-            acc.s3 = fmaf(c1.w, fmaf(dot, fmaf(0.5f, pf, ai), cond), acc.s3);
+            const float cond = (d.adh + c3.y) * fabsf(dot) * (d.u - c3.w) * g;
+            acc.s3 = fmaf(mj, fmaf(dot, fmaf(0.5f, pf, ai), cond), acc.s3);
             if constexpr (CNT) acc.n++;
         }
     }
@@ -649,7 +684,7 @@ __device__ __forceinline__ void write_out(const InteractArgs &a, const IData &d,
 // test every staged candidate against every lane (phase 1: one bit per lane
 // and candidate, in LDS), then let each lane walk its own hits (phase 2)
 template <int LOOP, int WIN, bool CNT>
-__device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, int nc, float hw, const IData &d,
+__device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN, CNT> &L, int nc, float hw, const IData &d,
                                       bool valid, Acc &acc)
 {
     const int lane = threadIdx.x & 63;
@@ -665,12 +700,12 @@ __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, 
         dd.t0 = dd.xi2 - test_delta(dd.ri, dd.rj);
         if (hw <= 1.02f * dd.hmin) {
             dd.t0 -= fmaxf(dd.H2, hw * hw);
-            test_words_mfma<LOOP, WIN>(L, nc, nw, dd, valid);
+            test_words_mfma<LOOP, WIN, CNT>(L, nc, nw, dd, valid);
         } else {
-            test_words<LOOP, WIN, true>(L, nc, nw, dd, valid);
+            test_words<LOOP, WIN, CNT, true>(L, nc, nw, dd, valid);
         }
     } else {
-        test_words_mfma<LOOP, WIN>(L, nc, nw, dd, valid);
+        test_words_mfma<LOOP, WIN, CNT>(L, nc, nw, dd, valid);
     }
     wave_sync();
     if (nw == 0) return;
@@ -686,7 +721,7 @@ __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN> &L, 
         if (act) {
             const int b = __builtin_ctz(cur);  // lowest slot first
             cur &= cur - 1u;
-            pair<LOOP, CNT>(a, cand_load<LOOP, WIN>(L, 32 * w + b), d, acc);
+            pair<LOOP, CNT>(a, cand_load<LOOP, WIN, CNT>(L, 32 * w + b), d, acc);
         }
     }
     wave_sync();
@@ -733,7 +768,7 @@ __device__ __forceinline__ bool tile_keep(const TileInfo &t, const R &r, const f
 // flushing the window whenever the next tile's survivors do not fit (one
 // flush call site, so the batch stays in registers)
 template <int LOOP, bool PREP, int WIN, int B, bool CNT>
-__device__ __forceinline__ void stage_batch(const InteractArgs &a, Lds<LOOP, WIN> &L, int &nc, float &hw,
+__device__ __forceinline__ void stage_batch(const InteractArgs &a, Lds<LOOP, WIN, CNT> &L, int &nc, float &hw,
                                             const TileInfo (&tb)[B], const JRec<LOOP, PREP> (&rb)[B], const IData &d,
                                             bool valid, const float4 &lo, const float4 &hi, const float4 &cen,
                                             Acc &acc)
@@ -765,7 +800,7 @@ __device__ __forceinline__ void stage_batch(const InteractArgs &a, Lds<LOOP, WIN
                     if (keep[b]) {
                         const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[b] >> 32),
                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal[b], 0u));
-                        stage_j<LOOP, PREP, WIN>(a, L, s.nc + rank, tb[b].js0 + lane, rb[b], tb[b].tx, tb[b].ty,
+                        stage_j<LOOP, PREP, WIN, CNT>(a, L, s.nc + rank, tb[b].js0 + lane, rb[b], tb[b].tx, tb[b].ty,
                                                  tb[b].tz, cen.x, cen.y, cen.z);
                     }
                     s.nc = __builtin_amdgcn_readfirstlane(s.nc + cnt);
@@ -791,7 +826,7 @@ constexpr int kJBatch = LOOP == 0 ? 4 : 2;
 
 // gather the candidates of one item's j-tile list (nj tiles) into the window
 template <int LOOP, int MODE, int WIN, bool CNT>
-__device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN> &L, int &nc, float &hw,
+__device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN, CNT> &L, int &nc, float &hw,
                                           const Chunk &ch,
                                           IData &d, bool valid, const float4 &lo, const float4 &hi,
                                           const float4 &cen, float halfdiag, Acc &acc)
@@ -878,7 +913,7 @@ template <int LOOP, int MODE, int WIN, bool CNT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<LOOP>))) void k_interact(
     InteractArgs a)
 {
-    __shared__ Lds<LOOP, WIN> L;
+    __shared__ Lds<LOOP, WIN, CNT> L;
     const int lane = threadIdx.x & 63;
     const int64_t wave_id = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
     const int64_t nwaves = (int64_t)gridDim.x;
