@@ -107,6 +107,12 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_23891_amd.build`")
+    # torch carries its own HIP runtime under the same soname as the one the
+    # library links (libamdhip64.so.7); whichever is loaded first serves the
+    # whole process, and torch does not run on another runtime.  Load torch's
+    # first, so that the library and torch share it.
+    import torch  # noqa: F401
+
     L = C.CDLL(LIB_PATH)
     for name, (args, res) in _SIGS.items():
         fn = getattr(L, name)

@@ -89,3 +89,23 @@ def test_validation_errors_before_any_launch():
     st.sub[0] = 0x1001  # misaligned
     assert L.sph_store_put(C.byref(st), 0, C.c_void_p(256), None) == -1
     assert b"aligned" in L.sph_last_error()
+
+
+def test_library_shares_torchs_hip_runtime():
+    """Loading the library first must still leave torch's HIP runtime as the
+    process's one (both carry the soname libamdhip64.so.7; torch does not run
+    on another): a fresh process that loads the library before anything else
+    maps only torch's copy."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2606_23891_amd import sph\n"
+            "sph.lib()\n"
+            "maps = open('/proc/self/maps').read().split()\n"
+            "print('\\n'.join(sorted({m for m in maps if 'libamdhip64' in m})))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    mapped = [l for l in out.stdout.split() if l]
+    import torch
+    torch_lib = os.path.realpath(os.path.join(os.path.dirname(torch.__file__), "lib"))
+    assert mapped and all(os.path.realpath(p).startswith(torch_lib) for p in mapped), mapped

@@ -195,6 +195,26 @@ def test_loops_octree_uneven(mode):
     _check_loops(ps, 4, mode, bundle=16)
 
 
+def _coincident_set(seed=5):
+    """a 16^3 jittered lattice in which 48 particles are moved onto 48 others:
+    distinct particles at r = 0, the method's degenerate pair (each keeps its
+    own velocity, energy and smoothing length)"""
+    rng = np.random.default_rng(seed)
+    f = inputs.lattice_set(16, seed=seed, jitter=0.1, velocity="gresho", switches=True)
+    src = rng.choice(f["x"].shape[0], 96, replace=False)
+    f["x"][src[48:]] = f["x"][src[:48]]
+    f, cells, tasks = inputs.uniform_grid(f, 4)
+    return inputs.ParticleSet(f, cells, tasks, {"config": -1, "n_side": 16, "grid": 4})
+
+
+@pytest.mark.parametrize("mode", ["per_task", "batched"])
+def test_loops_coincident_particles(mode):
+    ps = _coincident_set()
+    x = ps.fields["x"]
+    assert len(np.unique(x, axis=0)) == x.shape[0] - 48
+    _check_loops(ps, 8, mode, bundle=8)
+
+
 def test_density_closed_form_lattice():
     ps = inputs.make_config(0, jitter=0.0)
     plan = sph.Plan(ps.cells, ps.tasks, ps.n)
