@@ -221,7 +221,10 @@ sph_status sph_pack(const sph_plan *plan, sph_loop loop, const sph_store *store,
  *   gradient: j != i with r < H_i
  *   force   : j != i with r < max(H_i, H_j)
  * H = sqrt(10/3) h.  counts (optional, int32 per slot) receives the number of
- * interacting j.  pack_bytes / res_bytes are the caller's buffer sizes. */
+ * interacting j; a non-null counts selects kernels that apply the exact
+ * support and j != i tests before every pair term, while without counts the
+ * kernels skip tests whose pairs contribute exact zeros anyway (the sums agree
+ * to rounding).  pack_bytes / res_bytes are the caller's buffer sizes. */
 sph_status sph_density(const sph_plan *plan, const void *pack_buf, size_t pack_bytes, int32_t t0,
                        int32_t t1, const sph_params *params, void *res_buf, size_t res_bytes,
                        int32_t *counts, void *stream);
@@ -264,10 +267,12 @@ sph_status sph_batched_ws_bytes(const sph_plan *plan, size_t *bytes);
 sph_status sph_pack_cells(const sph_plan *plan, sph_loop loop, const sph_store *store, void *pack_buf,
                           size_t pack_bytes, const sph_tuning *tuning, void *stream);
 /* Workspace of sph_interact_cells for a loop: 256 bytes for the work-queue
- * counter, then (gradient, force) per-particle planes of the quantities the
- * pair terms derive from the packed fields (sound speed, m/rho; support and
- * its inverse, A = P/(Omega rho^2), the Balsara-limited viscosity switch),
- * computed once per particle by the same launch. */
+ * counters (one per XCD), then (gradient, force) per-particle planes of the
+ * quantities the pair terms derive from the packed fields, computed once per
+ * particle by the same launch: gradient u, m/rho and the sound speed; force
+ * 1/H, the spline normalisation H^-5 8/pi, A = P/(Omega rho^2), the sound
+ * speed, the Balsara-limited viscosity switch, alpha_d, rho and u (with the
+ * pair term's constant factors folded in). */
 sph_status sph_interact_ws_bytes(const sph_plan *plan, sph_loop loop, size_t *bytes);
 /* ws: device memory of ws_bytes >= sph_interact_ws_bytes(loop), 256-byte
  * aligned, owned by the caller; overwritten. */
