@@ -308,6 +308,22 @@ sph_status sph_offload_bytes(sph_layout layout, sph_loop loop, int64_t n, size_t
 sph_status sph_offload_step(const sph_plan *plan, const sph_store *host, const sph_store *dev,
                             const sph_params *params, const sph_tuning *tuning, void *ws, size_t ws_bytes,
                             void *stream);
+/* The same step pipelined (Sec. 2.3's cycle with its transfers overlapped):
+ * the particles are cut into nbundle (1..64) ranges of whole cells; on a copy
+ * stream each substruct a step needs goes to the device once, bundle by bundle,
+ * before the first loop that reads (or partly writes) it; each bundle is packed
+ * as soon as its bytes are there; the interaction waits for every pack; each
+ * bundle is then unpacked and its output substructs copied back on a second
+ * copy stream while the rest of the work proceeds.  The copy streams belong to
+ * the plan (created on the first call, default priority, destroyed with the
+ * plan); the call is ordered after earlier work on `stream`, and later work on
+ * `stream` is ordered after all of it.  The host store must not change during
+ * the call; on completion host and device stores hold what sph_offload_step
+ * leaves (every kernel runs over the same tiles).  Calls sharing a plan must not
+ * overlap.  ws as for sph_step_batched. */
+sph_status sph_offload_step_async(const sph_plan *plan, const sph_store *host, const sph_store *dev,
+                                  const sph_params *params, const sph_tuning *tuning, int32_t nbundle,
+                                  void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Adjoint of L = sum_i |a_i|^2 through density and force (hand-written).   */

@@ -401,6 +401,9 @@ sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task 
                 tiles.push_back(t);
             }
         }
+        p->tile_off.resize(ncell + 1);
+        for (int32_t c = 0; c < ncell; ++c) p->tile_off[c] = cr[c].tile0;
+        p->tile_off[ncell] = (int32_t)tiles.size();
         std::vector<int32_t> deg(ncell, 0);
         for (const sph_task &k : p->tasks) {
             deg[k.ci]++;
@@ -516,6 +519,8 @@ void sph_plan_destroy(sph_plan *p)
                     p->d_nbr_off, p->d_items, p->d_items_x, p->d_jt_off, p->d_jt, p->d_csr_off, p->d_csr};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    if (p->off_h2d) (void)hipStreamDestroy(p->off_h2d);
+    if (p->off_d2h) (void)hipStreamDestroy(p->off_d2h);
     delete p;
 }
 
@@ -939,6 +944,155 @@ sph_status sph_offload_step(const sph_plan *p, const sph_store *host, const sph_
             if (fl[k] & 2)
                 SPH_HIP(hipMemcpyAsync(host->sub[k], dev->sub[k], (size_t)p->n * d.sub_bytes[k], hipMemcpyDeviceToHost, st));
     }
+    return SPH_OK;
+}
+
+// Pipelined offload step.  Three streams: copies to the device, compute, copies
+// back.  The particles are cut into nbundle ranges of whole cells; a bundle's
+// substructs go to the device on the copy stream, its cells are packed as soon
+// as they are there, the interaction waits for every pack, and each bundle is
+// unpacked and sent back while the next bundle unpacks and the next loop runs.
+// A substruct is sent to the device once per step, before the first loop that
+// reads it (or writes part of it); a loop's outputs come back after the loop.
+// Every stage runs the same kernels over the same tiles as sph_offload_step.
+namespace {
+// the events of one call; released when the call returns (an event still
+// pending is released by the runtime once it completes)
+struct OffloadSync {
+    hipStream_t cp = nullptr, dn = nullptr;
+    std::vector<hipEvent_t> ev;
+    hipEvent_t make()
+    {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        ev.push_back(e);
+        return e;
+    }
+    ~OffloadSync()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+}  // namespace
+
+sph_status sph_offload_step_async(const sph_plan *p, const sph_store *host, const sph_store *dev,
+                                  const sph_params *prm, const sph_tuning *tn, int32_t nbundle, void *ws,
+                                  size_t ws_bytes, void *stream)
+{
+    sph_status s;
+    if ((s = batched_checks(p, 0)) || (s = check_store(host)) || (s = check_store(dev)) || (s = check_tuning(tn)))
+        return s;
+    if (!prm) return fail(SPH_E_ARG, "params is null");
+    if (host->layout != dev->layout || host->n != p->n || dev->n != p->n)
+        return fail(SPH_E_ARG, "host and device stores must share the plan's size and one layout");
+    if (nbundle < 1 || nbundle > 64) return fail(SPH_E_ARG, "nbundle outside 1..64");
+    size_t need = 0;
+    sph_batched_ws_bytes(p, &need);
+    if (!ws || !aligned256(ws)) return fail(SPH_E_ARG, "workspace null or misaligned");
+    if (ws_bytes < need) return fail(SPH_E_CAPACITY, "workspace needs " + std::to_string(need) + " bytes");
+    if (p->n == 0) return SPH_OK;
+    sph_tuning def;
+    sph_tuning_default(&def);
+    if (!tn) tn = &def;
+    hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)ws;
+    void *q = base;
+    void *pack = base + interact_ws_bytes_for(2, p->n);
+    void *res = (char *)pack + pack_bytes_for(2, p->n, p->ntile);
+    const LayoutDesc &d = kLayouts[host->layout];
+
+    // bundles: whole cells, about n / nbundle particles each
+    std::vector<int32_t> cb{0};
+    for (int b = 1; b < nbundle; ++b) {
+        const int64_t target = p->n * b / nbundle;
+        int32_t c = cb.back();
+        while (c < p->ncell && p->cells[c].first < target) ++c;
+        if (c > cb.back() && c < p->ncell) cb.push_back(c);
+    }
+    cb.push_back(p->ncell);
+    const int nb = (int)cb.size() - 1;
+    auto part0 = [&](int b) { return b == nb ? p->n : (int64_t)p->cells[cb[b]].first; };
+
+    OffloadSync sy;
+    {
+        // default-priority streams owned by the plan
+        std::lock_guard<std::mutex> lk(const_cast<sph_plan *>(p)->off_mu);
+        sph_plan *pm = const_cast<sph_plan *>(p);
+        if (!pm->off_h2d) SPH_HIP(hipStreamCreateWithFlags(&pm->off_h2d, hipStreamNonBlocking));
+        if (!pm->off_d2h) SPH_HIP(hipStreamCreateWithFlags(&pm->off_d2h, hipStreamNonBlocking));
+        sy.cp = pm->off_h2d;
+        sy.dn = pm->off_d2h;
+    }
+    hipEvent_t start = sy.make();
+    if (!start) return fail(SPH_E_HIP, "event creation failed");
+    SPH_HIP(hipEventRecord(start, st));
+    SPH_HIP(hipStreamWaitEvent(sy.cp, start, 0));
+    SPH_HIP(hipStreamWaitEvent(sy.dn, start, 0));
+
+    bool on_dev[kMaxSub] = {};
+    std::vector<hipEvent_t> back(nb, nullptr);  // last copy-back of each bundle
+    for (int loop = 0; loop < 3; ++loop) {
+        int fl[kMaxSub];
+        offload_plan(host->layout, loop, fl);
+        bool send[kMaxSub] = {};
+        for (int k = 0; k < d.nsub; ++k) {
+            send[k] = (fl[k] & 1) && !on_dev[k];
+            if (fl[k] & 1) on_dev[k] = true;
+            if (fl[k] & 2) on_dev[k] = true;  // fully written by the unpack
+        }
+        // 1. bundle copies to the device, each packed once it has arrived
+        for (int b = 0; b < nb; ++b) {
+            const int64_t p0 = part0(b), p1 = part0(b + 1);
+            bool any = false;
+            for (int k = 0; k < d.nsub; ++k)
+                if (send[k]) {
+                    const size_t sb = d.sub_bytes[k];
+                    SPH_HIP(hipMemcpyAsync((char *)dev->sub[k] + p0 * sb, (const char *)host->sub[k] + p0 * sb,
+                                           (size_t)(p1 - p0) * sb, hipMemcpyHostToDevice, sy.cp));
+                    any = true;
+                }
+            if (any) {
+                hipEvent_t e = sy.make();
+                if (!e) return fail(SPH_E_HIP, "event creation failed");
+                SPH_HIP(hipEventRecord(e, sy.cp));
+                SPH_HIP(hipStreamWaitEvent(st, e, 0));
+            }
+            if ((s = launch_pack_tiles(p, loop, dev, p->tile_off[cb[b]], p->tile_off[cb[b + 1]], pack, tn->pack_waves,
+                                       st)))
+                return s;
+        }
+        // 2. the interaction over every tile
+        if ((s = launch_interact(p, loop, true, 0, p->ntask, pack, prm, tn, res, nullptr, q, st))) return s;
+        // 3. bundle unpacks, each copied back once unpacked; a bundle is not
+        //    unpacked again before its previous copy-back has read it
+        for (int b = 0; b < nb; ++b) {
+            if (back[b]) SPH_HIP(hipStreamWaitEvent(st, back[b], 0));
+            if ((s = launch_unpack_tiles(p, loop, res, p->tile_off[cb[b]], p->tile_off[cb[b + 1]], dev, tn->pack_waves,
+                                         st)))
+                return s;
+            hipEvent_t u = sy.make();
+            hipEvent_t c = sy.make();
+            if (!u || !c) return fail(SPH_E_HIP, "event creation failed");
+            SPH_HIP(hipEventRecord(u, st));
+            SPH_HIP(hipStreamWaitEvent(sy.dn, u, 0));
+            const int64_t p0 = part0(b), p1 = part0(b + 1);
+            for (int k = 0; k < d.nsub; ++k)
+                if (fl[k] & 2) {
+                    const size_t sb = d.sub_bytes[k];
+                    SPH_HIP(hipMemcpyAsync((char *)host->sub[k] + p0 * sb, (const char *)dev->sub[k] + p0 * sb,
+                                           (size_t)(p1 - p0) * sb, hipMemcpyDeviceToHost, sy.dn));
+                }
+            SPH_HIP(hipEventRecord(c, sy.dn));
+            back[b] = c;
+        }
+    }
+    // the caller's stream resumes once both copy streams are done
+    hipEvent_t e1 = sy.make(), e2 = sy.make();
+    if (!e1 || !e2) return fail(SPH_E_HIP, "event creation failed");
+    SPH_HIP(hipEventRecord(e1, sy.cp));
+    SPH_HIP(hipEventRecord(e2, sy.dn));
+    SPH_HIP(hipStreamWaitEvent(st, e1, 0));
+    SPH_HIP(hipStreamWaitEvent(st, e2, 0));
     return SPH_OK;
 }
 

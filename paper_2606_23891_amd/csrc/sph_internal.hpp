@@ -134,6 +134,10 @@ struct sph_plan {
     int32_t *d_jt_off = nullptr;     // per cell: first entry of its j-tile list
     sph::JTile *d_jt = nullptr;      // flattened j-tiles of every cell's neighbours
     int32_t max_jt = 0;
+    std::vector<int32_t> tile_off;   // per cell: its first tile (ncell + 1 entries)
+    // copy streams of the pipelined offload step, created on its first call
+    std::mutex off_mu;
+    hipStream_t off_h2d = nullptr, off_d2h = nullptr;
     // per-particle slot lists, built on the first multi-task unpack
     std::mutex csr_mu;
     bool csr_built = false;
@@ -206,6 +210,12 @@ sph_status launch_pack(const sph_plan *p, int loop, const sph_store *s, bool cel
 sph_status launch_unpack(sph_plan *p, int loop, const void *res, bool cells, int32_t t0, int32_t t1,
                          const sph_store *s, int waves, hipStream_t st);
 sph_status launch_zero(const sph_plan *p, int loop, const sph_store *s, hipStream_t st);
+// batched form over the tiles [tile0, tile1) only (the buffers keep their
+// full-size layout)
+sph_status launch_pack_tiles(const sph_plan *p, int loop, const sph_store *s, int32_t tile0, int32_t tile1,
+                             void *buf, int waves, hipStream_t st);
+sph_status launch_unpack_tiles(const sph_plan *p, int loop, const void *res, int32_t tile0, int32_t tile1,
+                               const sph_store *s, int waves, hipStream_t st);
 sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, int32_t t1,
                            const void *pack, const sph_params *prm, const sph_tuning *tn, void *res,
                            int32_t *counts, void *ws, hipStream_t st);

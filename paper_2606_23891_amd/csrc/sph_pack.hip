@@ -271,6 +271,40 @@ sph_status launch_pack(const sph_plan *p, int loop, const sph_store *s, bool cel
     SPH_BY_LAYOUT(s->layout, pack_l, p, loop, a, waves, st);
 }
 
+sph_status launch_pack_tiles(const sph_plan *p, int loop, const sph_store *s, int32_t tile0, int32_t tile1,
+                             void *buf, int waves, hipStream_t st)
+{
+    PackArgs a{};
+    a.store = store_arg(s);
+    a.cells = p->d_cells;
+    a.tasks = p->d_tasks;
+    a.buf = (char *)buf;
+    a.chunks = p->d_tiles;
+    a.chunk_base = tile0;
+    a.nchunk = tile1 - tile0;
+    a.slot_base = 0;
+    a.P = round_slots(p->n);
+    // chunk c of the launch is tile tile0 + c: its bounds sit at that tile's place
+    a.bounds = (float4 *)(a.buf + a.P * 4 * kPackFloats[loop]) + 2 * (int64_t)tile0;
+    if (a.nchunk <= 0) return SPH_OK;
+    SPH_BY_LAYOUT(s->layout, pack_l, p, loop, a, waves, st);
+}
+
+sph_status launch_unpack_tiles(const sph_plan *p, int loop, const void *res, int32_t tile0, int32_t tile1,
+                               const sph_store *s, int waves, hipStream_t st)
+{
+    UnpackArgs a{};
+    a.store = store_arg(s);
+    a.res = (const float *)res;
+    a.n = p->n;
+    a.chunks = p->d_tiles;
+    a.chunk_base = tile0;
+    a.nchunk = tile1 - tile0;
+    a.P = round_slots(p->n);
+    if (a.nchunk <= 0) return SPH_OK;
+    SPH_BY_LAYOUT(s->layout, unpack_l, loop, a, true, false, waves, st);
+}
+
 sph_status launch_unpack(sph_plan *p, int loop, const void *res, bool cells, int32_t t0, int32_t t1,
                          const sph_store *s, int waves, hipStream_t st)
 {

@@ -92,6 +92,7 @@ _SIGS = {
     "sph_graph_destroy": ([vp], None),
     "sph_offload_bytes": ([i32, i32, i64, C.POINTER(sz), C.POINTER(sz)], i32),
     "sph_offload_step": ([vp, vp, vp, vp, vp, vp, sz, vp], i32),
+    "sph_offload_step_async": ([vp, vp, vp, vp, vp, i32, vp, sz, vp], i32),
     "sph_adjoint_ws_bytes": ([vp, C.POINTER(sz)], i32),
     "sph_adjoint_forward": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp], i32),
     "sph_force_adjoint": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz,
@@ -412,6 +413,14 @@ def sph_offload_step(plan, host_store, dev_store, ws, params=None, tuning=None, 
     _check(lib().sph_offload_step(_h(plan), _s(host_store), _s(dev_store), C.byref(p),
                                   C.byref(tuning) if tuning else None, _ptr(ws), _nbytes(ws), _stream(stream)),
            "sph_offload_step")
+
+
+def sph_offload_step_async(plan, host_store, dev_store, ws, nbundle=8, params=None, tuning=None, stream=None):
+    p = params if params is not None else default_params()
+    _check(lib().sph_offload_step_async(_h(plan), _s(host_store), _s(dev_store), C.byref(p),
+                                        C.byref(tuning) if tuning else None, int(nbundle), _ptr(ws), _nbytes(ws),
+                                        _stream(stream)),
+           "sph_offload_step_async")
 
 
 class Graph:

@@ -142,3 +142,51 @@ def test_offload_step_matches_resident_step(layout):
     torch.cuda.synchronize()
     assert back.raw() == resident.raw()
     plan.close()
+
+
+def _filled_host_store(lay, f, n):
+    """a pinned host store holding the fields f (written through a device store)"""
+    import torch
+    host = sph.Store(lay, n, device="pinned")
+    tmp = sph.Store(lay, n)
+    tmp.put_all(f)
+    torch.cuda.synchronize()
+    for h, d in zip(host.subs, tmp.subs):
+        h.copy_(d.cpu())
+    return host
+
+
+@pytest.mark.parametrize("layout", ["AOS", "SAOS_SHARED", "SOA"])
+def test_offload_async_matches_offload_step(layout):
+    """the pipelined offload step (bundles of cells, two copy streams, each
+    substruct sent once per step) leaves the host and device stores byte for
+    byte as the stream-ordered offload step does, for 1, 3 and 8 bundles, also
+    when run twice in a row on one plan"""
+    import torch
+    ps = inputs.make_config(1, n_side=32)
+    lay = sph.LAYOUTS.index(layout)
+    f = dict(ps.fields)
+    extra = inputs.random_fields(ps.n, 23, x=f["x"])
+    for k in ("time_bin", "id", "cold", "a", "u_dt", "lap_u", "v_sig", "wcount"):
+        f[k] = extra[k]
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    ws = torch.zeros(sph.sph_batched_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    host_ref = _filled_host_store(lay, f, ps.n)
+    dev_ref = sph.Store(lay, ps.n)
+    sph.sph_offload_step(plan, host_ref, dev_ref, ws)
+    torch.cuda.synchronize()
+    ref_h, ref_d = host_ref.raw(), dev_ref.raw()
+    for nb in (1, 3, 8):
+        log(f"offload async {layout} bundles={nb}")
+        host = _filled_host_store(lay, f, ps.n)
+        dev = sph.Store(lay, ps.n)
+        sph.sph_offload_step_async(plan, host, dev, ws, nbundle=nb)
+        torch.cuda.synchronize()
+        assert host.raw() == ref_h, nb
+        assert dev.raw() == ref_d, nb
+    # a second step on the stores the first left behind, both ways
+    sph.sph_offload_step(plan, host_ref, dev_ref, ws)
+    sph.sph_offload_step_async(plan, host, dev, ws, nbundle=8)
+    torch.cuda.synchronize()
+    assert host.raw() == host_ref.raw()
+    plan.close()
