@@ -396,7 +396,8 @@ def layout_sweep(ps, plan, names, tuning, steps):
 
 def offload_sweep(ps, plan, names, tuning, reps=2):
     """the offload form per layout: host store in pinned memory, per-loop copies
-    of the substructs each loop needs, batched compute on the device"""
+    of the substructs each loop needs, batched compute on the device; also the
+    pipelined step (4 and 16 bundles of cells, copies on two streams)"""
     import torch
 
     from paper_2606_23891_amd import sph
@@ -427,6 +428,16 @@ def offload_sweep(ps, plan, names, tuning, reps=2):
         ms = e0.elapsed_time(e1) / reps
         res[name] = {"ms_per_step": round(ms, 3), "h2d_GB": round(h2d / 1e9, 3), "d2h_GB": round(d2h / 1e9, 3),
                      "link_GB/s": round((h2d + d2h) / (ms * 1e-3) / 1e9, 1)}
+        # the pipelined step: bundles of cells on two copy streams
+        for nbundle in (4, 16):
+            sph.sph_offload_step_async(plan, host, dev, ws, nbundle=nbundle, tuning=tuning)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(reps):
+                sph.sph_offload_step_async(plan, host, dev, ws, nbundle=nbundle, tuning=tuning)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res[name][f"async{nbundle}_ms_per_step"] = round(e0.elapsed_time(e1) / reps, 3)
         log(f"offload {name}: {ms:.1f} ms/step, {res[name]}")
         del dev, host
         torch.cuda.empty_cache()
