@@ -67,6 +67,108 @@ struct PackArgs {
     float4 *bounds; // 2 per chunk
 };
 
+// fields each loop's pack reads (paper Table 1)
+constexpr bool kPackReads[3][NFIELD] = {
+    // X  V  A  M  H  U  UDT RHO RDH WC DIV ROT LAP VSIG AV AD TB ID COLD
+    {1, 0, 0, 1, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {1, 1, 0, 1, 1, 1, 0, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {1, 1, 0, 1, 1, 1, 0, 1, 1, 0, 1, 1, 0, 0, 1, 1, 0, 0, 0}};
+
+// byte span [lo, hi) of substruct S's record that loop LOOP's pack reads
+// (lo > hi when it reads nothing there), and the widest load that the record
+// stride and the span's start allow (records are 256-byte aligned arrays)
+constexpr int span_lo(int L, int LOOP, int S)
+{
+    int lo = 1 << 30;
+    for (int f = 0; f < NFIELD; ++f)
+        if (kPackReads[LOOP][f])
+            for (int c = 0; c < kNComp[f]; ++c)
+                if (kLayouts[L].sub[f][c] == S && kLayouts[L].off[f][c] < lo) lo = kLayouts[L].off[f][c];
+    return lo;
+}
+constexpr int span_hi(int L, int LOOP, int S)
+{
+    int hi = -1;
+    for (int f = 0; f < NFIELD; ++f)
+        if (kPackReads[LOOP][f])
+            for (int c = 0; c < kNComp[f]; ++c)
+                if (kLayouts[L].sub[f][c] == S && kLayouts[L].off[f][c] + kCompBytes[f] > hi)
+                    hi = kLayouts[L].off[f][c] + kCompBytes[f];
+    return hi;
+}
+constexpr int load_width(int record, int lo)
+{
+    return (record % 16 == 0 && lo % 16 == 0) ? 16 : (record % 8 == 0 && lo % 8 == 0) ? 8 : 4;
+}
+
+// the values a pack reads, by field
+struct PackVals {
+    double x[3];
+    float m, h, v[3], u, rho, rdh, div, rot[3], av, ad;
+    template <int F, int C>
+    __device__ __forceinline__ void set(const uint32_t *w)
+    {
+        if constexpr (F == FX) {
+            const uint64_t b = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+            x[C] = __longlong_as_double((long long)b);
+        } else {
+            const float f = __uint_as_float(w[0]);
+            if constexpr (F == FMASS) m = f;
+            else if constexpr (F == FH) h = f;
+            else if constexpr (F == FV) v[C] = f;
+            else if constexpr (F == FU) u = f;
+            else if constexpr (F == FRHO) rho = f;
+            else if constexpr (F == FRHODH) rdh = f;
+            else if constexpr (F == FDIV) div = f;
+            else if constexpr (F == FROT) rot[C] = f;
+            else if constexpr (F == FAV) av = f;
+            else if constexpr (F == FAD) ad = f;
+        }
+    }
+};
+
+// Read the span of substruct S with the widest aligned loads, then take every
+// field the loop reads out of the loaded words: one pass over each record
+// instead of one narrow load per field (the bytes are the same, the requests
+// a fraction)
+template <int L, int LOOP, int S>
+__device__ __forceinline__ void load_sub(const StoreArg &st, int64_t p, PackVals &v)
+{
+    constexpr int lo = span_lo(L, LOOP, S), hi = span_hi(L, LOOP, S);
+    if constexpr (lo < hi) {
+        constexpr int R = kLayouts[L].sub_bytes[S];
+        constexpr int G = load_width(R, lo);
+        constexpr int NB = (hi - lo + G - 1) / G * G;  // lo + NB <= R: R and lo are multiples of G
+        uint32_t w[NB / 4];
+        const char *base = (const char *)__builtin_assume_aligned(st.sub[S], 256) + p * R + lo;
+        static_for<0, NB / G>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            if constexpr (G == 16) {
+                const uint4 q = *(const uint4 *)(base + 16 * k);
+                w[4 * k] = q.x;
+                w[4 * k + 1] = q.y;
+                w[4 * k + 2] = q.z;
+                w[4 * k + 3] = q.w;
+            } else if constexpr (G == 8) {
+                const uint2 q = *(const uint2 *)(base + 8 * k);
+                w[2 * k] = q.x;
+                w[2 * k + 1] = q.y;
+            } else {
+                w[k] = *(const uint32_t *)(base + 4 * k);
+            }
+        });
+        static_for<0, NFIELD>([&](auto fc) {
+            constexpr int F = decltype(fc)::value;
+            if constexpr (kPackReads[LOOP][F]) {
+                static_for<0, kNComp[F]>([&](auto cc) {
+                    constexpr int C = decltype(cc)::value;
+                    if constexpr (kLayouts[L].sub[F][C] == S) v.template set<F, C>(w + (kLayouts[L].off[F][C] - lo) / 4);
+                });
+            }
+        });
+    }
+}
+
 template <int L, int LOOP>
 __global__ __launch_bounds__(512) void k_pack(PackArgs a)
 {
@@ -86,35 +188,33 @@ __global__ __launch_bounds__(512) void k_pack(PackArgs a)
     const bool valid = lane < ch.n;
     const int64_t p = ch.part0 + lane;
     const int64_t slot = ch.slot0 - a.slot_base + lane;
-    const StoreArg &s = a.store;
     const int64_t P = a.P;
     float dx = 0.f, dy = 0.f, dz = 0.f, hh = 0.f;
     if (valid) {
-        dx = (float)(ld<L, FX, 0, double>(s, p) - o0);
-        dy = (float)(ld<L, FX, 1, double>(s, p) - o1);
-        dz = (float)(ld<L, FX, 2, double>(s, p) - o2);
-        hh = ld<L, FH, 0, float>(s, p);
+        PackVals v;
+        static_for<0, kLayouts[L].nsub>([&](auto sc) { load_sub<L, LOOP, decltype(sc)::value>(a.store, p, v); });
+        dx = (float)(v.x[0] - o0);
+        dy = (float)(v.x[1] - o1);
+        dz = (float)(v.x[2] - o2);
+        hh = v.h;
         float4 *pl0 = (float4 *)a.buf;
         pl0[slot] = make_float4(dx, dy, dz, hh);
         if constexpr (LOOP == 0) {
             float *pl1 = (float *)(a.buf + P * 16);
-            pl1[slot] = ld<L, FMASS, 0, float>(s, p);
+            pl1[slot] = v.m;
         } else {
             float4 *pl1 = (float4 *)(a.buf + P * 16);
-            pl1[slot] = make_float4(ld<L, FV, 0, float>(s, p), ld<L, FV, 1, float>(s, p),
-                                    ld<L, FV, 2, float>(s, p), ld<L, FMASS, 0, float>(s, p));
+            pl1[slot] = make_float4(v.v[0], v.v[1], v.v[2], v.m);
             if constexpr (LOOP == 1) {
                 float2 *pl2 = (float2 *)(a.buf + P * 32);
-                pl2[slot] = make_float2(ld<L, FU, 0, float>(s, p), ld<L, FRHO, 0, float>(s, p));
+                pl2[slot] = make_float2(v.u, v.rho);
             } else {
                 float4 *pl2 = (float4 *)(a.buf + P * 32);
-                pl2[slot] = make_float4(ld<L, FU, 0, float>(s, p), ld<L, FRHO, 0, float>(s, p),
-                                        ld<L, FRHODH, 0, float>(s, p), ld<L, FDIV, 0, float>(s, p));
+                pl2[slot] = make_float4(v.u, v.rho, v.rdh, v.div);
                 float4 *pl3 = (float4 *)(a.buf + P * 48);
-                pl3[slot] = make_float4(ld<L, FROT, 0, float>(s, p), ld<L, FROT, 1, float>(s, p),
-                                        ld<L, FROT, 2, float>(s, p), ld<L, FAV, 0, float>(s, p));
+                pl3[slot] = make_float4(v.rot[0], v.rot[1], v.rot[2], v.av);
                 float *pl4 = (float *)(a.buf + P * 64);
-                pl4[slot] = ld<L, FAD, 0, float>(s, p);
+                pl4[slot] = v.ad;
             }
         }
     }
