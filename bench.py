@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--layouts", default=None,
                     help="'all' or comma list: also time pack + unpack of every loop per store layout")
+    ap.add_argument("--fission", default=None,
+                    help="'all' or comma list of layouts: also time pack + unpack under every "
+                         "loop-fission schedule")
     ap.add_argument("--offload", default=None,
                     help="'all' or comma list of layouts: also time the offload form (pinned host store)")
     ap.add_argument("--copy-mib", type=int, default=1024,
@@ -336,6 +339,10 @@ def main():
         names = sph.LAYOUTS if a.layouts == "all" else a.layouts.split(",")
         out["layouts"] = layout_sweep(ps, plan, names, tuning, a.steps)
 
+    if a.fission:
+        names = sph.LAYOUTS if a.fission == "all" else a.fission.split(",")
+        out["fission"] = fission_sweep(ps, plan, names, tuning, a.steps)
+
     if a.offload:
         names = sph.LAYOUTS if a.offload == "all" else a.offload.split(",")
         out["offload"] = offload_sweep(ps, plan, names, tuning)
@@ -347,6 +354,39 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def _pack_unpack_row(ps, plan, st, bufs, tuning, steps):
+    """pack + unpack time of each loop of the batched form on one store"""
+    import torch
+
+    from paper_2606_23891_amd import sph
+
+    stream = torch.cuda.current_stream()
+    row = {}
+    for L in range(3):
+        pack, r = bufs[L]
+        for s_ in range(2):
+            sph.sph_pack_cells(plan, L, st, pack, tuning)
+            sph.sph_unpack_cells(plan, L, r, st, tuning)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        tp = tu = 0.0
+        for _ in range(steps):
+            e[0].record(stream)
+            sph.sph_pack_cells(plan, L, st, pack, tuning)
+            e[1].record(stream)
+            sph.sph_unpack_cells(plan, L, r, st, tuning)
+            e[2].record(stream)
+            torch.cuda.synchronize()
+            tp += e[0].elapsed_time(e[1])
+            tu += e[1].elapsed_time(e[2])
+        tp /= steps
+        tu /= steps
+        row[LOOP_NAME[L]] = {"pack_ms": round(tp, 4), "unpack_ms": round(tu, 4),
+                             "pack_GB/s": round(PACK_BYTES[L] * ps.n / (tp * 1e-3) / 1e9, 1),
+                             "unpack_GB/s": round(UNPACK_BYTES[L] * ps.n / (tu * 1e-3) / 1e9, 1)}
+    row["total_ms"] = round(sum(v["pack_ms"] + v["unpack_ms"] for k, v in row.items() if k in LOOP_NAME.values()), 4)
+    return row
+
+
 def layout_sweep(ps, plan, names, tuning, steps):
     """pack + unpack time of each loop for every store layout (fresh store each)"""
     import torch
@@ -354,35 +394,12 @@ def layout_sweep(ps, plan, names, tuning, steps):
     from paper_2606_23891_amd import sph
 
     bufs = {L: sph.cell_buffers(plan, L) for L in range(3)}
-    stream = torch.cuda.current_stream()
     res = {}
     for name in names:
         st = sph.Store(sph.LAYOUTS.index(name), ps.n)
         st.put_all(ps.fields)
         torch.cuda.synchronize()
-        row = {}
-        for L in range(3):
-            pack, r = bufs[L]
-            for s_ in range(2):
-                sph.sph_pack_cells(plan, L, st, pack, tuning)
-                sph.sph_unpack_cells(plan, L, r, st, tuning)
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-            tp = tu = 0.0
-            for _ in range(steps):
-                e[0].record(stream)
-                sph.sph_pack_cells(plan, L, st, pack, tuning)
-                e[1].record(stream)
-                sph.sph_unpack_cells(plan, L, r, st, tuning)
-                e[2].record(stream)
-                torch.cuda.synchronize()
-                tp += e[0].elapsed_time(e[1])
-                tu += e[1].elapsed_time(e[2])
-            tp /= steps
-            tu /= steps
-            row[LOOP_NAME[L]] = {"pack_ms": round(tp, 4), "unpack_ms": round(tu, 4),
-                                 "pack_GB/s": round(PACK_BYTES[L] * ps.n / (tp * 1e-3) / 1e9, 1),
-                                 "unpack_GB/s": round(UNPACK_BYTES[L] * ps.n / (tu * 1e-3) / 1e9, 1)}
-        row["total_ms"] = round(sum(v["pack_ms"] + v["unpack_ms"] for k, v in row.items() if k in LOOP_NAME.values()), 4)
+        row = _pack_unpack_row(ps, plan, st, bufs, tuning, steps)
         res[name] = row
         log(f"layout {name}: pack+unpack {row['total_ms']:.3f} ms per step")
         del st
@@ -391,6 +408,40 @@ def layout_sweep(ps, plan, names, tuning, steps):
     if base:
         for name in res:
             res[name]["vs_AOS"] = round(res[name]["total_ms"] / base, 4)
+    return res
+
+
+def fission_sweep(ps, plan, names, tuning, steps):
+    """pack + unpack time per loop-fission schedule of the batched form, for
+    each named store layout (Sec. 3.3's split conversion loops, one kernel per
+    group of members)"""
+    import copy
+
+    import torch
+
+    from paper_2606_23891_amd import sph
+
+    bufs = {L: sph.cell_buffers(plan, L) for L in range(3)}
+    res = {}
+    for name in names:
+        lay = sph.LAYOUTS.index(name)
+        st = sph.Store(lay, ps.n)
+        st.put_all(ps.fields)
+        torch.cuda.synchronize()
+        res[name] = {}
+        for sname, sched in sph.SCHEDULES.items():
+            tn = copy.copy(tuning) if tuning is not None else sph.default_tuning()
+            tn.pack_schedule = sched
+            row = _pack_unpack_row(ps, plan, st, bufs, tn, steps)
+            row["kernels"] = {LOOP_NAME[L]: [len(m) for m in sph.sph_fission_passes(lay, L, sched)]
+                              for L in range(3)}
+            res[name][sname] = row
+            log(f"fission {name} {sname}: pack+unpack {row['total_ms']:.3f} ms per step")
+        base = res[name]["by_particle"]["total_ms"]
+        for sname in res[name]:
+            res[name][sname]["vs_by_particle"] = round(res[name][sname]["total_ms"] / base, 4)
+        del st
+        torch.cuda.empty_cache()
     return res
 
 

@@ -127,7 +127,12 @@ typedef struct sph_tuning {
                                 shares once its own is drained                     */
     int32_t blocks_per_loop[3]; /* per loop (density, gradient, force): 1..64 replaces
                                 blocks_per_cu for that loop's kernel, 0 keeps it    */
-    int32_t reserved;
+    int32_t pack_schedule;   /* loop fission of the batched pack and unpack (Sec.
+                                3.3): 0 by particle (one kernel converts every
+                                field), 1 by struct (one kernel per substruct), 2
+                                by element (one per field), 3 by type (one per
+                                component type), 4 by struct and type; the groups
+                                of a layout and loop are sph_fission_passes()'s   */
 } sph_tuning;
 
 typedef struct sph_plan sph_plan; /* library-owned, opaque */
@@ -177,6 +182,20 @@ sph_status sph_field_info(sph_field field, int32_t *ncomp, int32_t *comp_bytes);
  * pre-processing of Sec. 2.3).  Results are float planes per slot:
  *   density [rho rho_dh wcount]; gradient [D R0 R1 R2 L V]; force [a0 a1 a2 u_dt]. */
 sph_status sph_pack_layout(sph_loop loop, int32_t *nplane, int32_t *plane_floats, int32_t *result_planes);
+
+/* Loop fission (Sec. 3.3): the kernels one pack and one unpack of the
+ * batched form run under sph_tuning.pack_schedule (0..4, as listed there),
+ * each given by the members it converts.  A pack mask has bit k set for the
+ * k-th float of the force record (dx dy dz h vx vy vz m u rho rho_dh D R0 R1
+ * R2 alpha_v alpha_d); density and gradient pack subsets of it.  An unpack
+ * mask has bit k set for result plane k of the loop.  Each loop's members are
+ * split into groups that share what the schedule keys on (nothing, the
+ * substruct, the field, the component's type, substruct and type), the groups
+ * in the order of their first member; the masks partition the loop's members.
+ * pack_masks and unpack_masks hold SPH_MAX_PASSES entries.  Host only. */
+#define SPH_MAX_PASSES 32
+sph_status sph_fission_passes(sph_layout layout, sph_loop loop, int32_t schedule, int32_t *npack,
+                              uint32_t *pack_masks, int32_t *nunpack, uint32_t *unpack_masks);
 
 /* ---------------------------------------------------------------------- */
 /* Store access: the getter / setter analogue (Sec. 3.2, Algorithm 1).      */

@@ -258,6 +258,21 @@ sph_status sph_pack_layout(sph_loop loop, int32_t *nplane, int32_t *plane_floats
     return SPH_OK;
 }
 
+sph_status sph_fission_passes(sph_layout layout, sph_loop loop, int32_t schedule, int32_t *npack,
+                              uint32_t *pack_masks, int32_t *nunpack, uint32_t *unpack_masks)
+{
+    sph_status s = check_loop(loop);
+    if (s) return s;
+    if ((int)layout < 0 || (int)layout >= kNLayouts) return fail(SPH_E_LAYOUT, "unknown layout");
+    if (schedule < 0 || schedule > 4) return fail(SPH_E_ARG, "schedule outside 0..4");
+    if (!npack || !pack_masks || !nunpack || !unpack_masks) return fail(SPH_E_ARG, "null output");
+    static_assert(SPH_MAX_PASSES >= 17, "a pass per member fits");
+    for (int k = 0; k < SPH_MAX_PASSES; ++k) pack_masks[k] = unpack_masks[k] = 0;
+    *npack = fission_passes(layout, loop, schedule, false, pack_masks);
+    *nunpack = fission_passes(layout, loop, schedule, true, unpack_masks);
+    return SPH_OK;
+}
+
 static sph_status store_copy(const sph_store *store, sph_field field, const void *src, void *dst,
                              void *stream)
 {
@@ -704,6 +719,7 @@ static sph_status check_tuning(const sph_tuning *t)
             return fail(SPH_E_ARG, "window must be 128, 256 or 512");
     if (t->pack_waves < 1 || t->pack_waves > 8) return fail(SPH_E_ARG, "pack_waves outside 1..8");
     if (t->queue < 0 || t->queue > 2) return fail(SPH_E_ARG, "queue must be 0, 1 or 2");
+    if (t->pack_schedule < 0 || t->pack_schedule > 4) return fail(SPH_E_ARG, "pack_schedule outside 0..4");
     for (int k = 0; k < 3; ++k)
         if (t->blocks_per_loop[k] < 0 || t->blocks_per_loop[k] > 64)
             return fail(SPH_E_ARG, "blocks_per_loop outside 0..64");
@@ -746,7 +762,8 @@ sph_status sph_pack_cells(const sph_plan *p, sph_loop loop, const sph_store *sto
     if (p->n == 0) return SPH_OK;
     if (!pack_buf || !aligned256(pack_buf)) return fail(SPH_E_ARG, "pack buffer null or misaligned");
     if (pack_bytes < pack_bytes_for(loop, p->n, p->ntile)) return fail(SPH_E_CAPACITY, "pack buffer too small");
-    return launch_pack(p, loop, store, true, 0, 0, pack_buf, tn ? tn->pack_waves : 4, (hipStream_t)stream);
+    return launch_pack(p, loop, store, true, 0, 0, pack_buf, tn ? tn->pack_waves : 4, (hipStream_t)stream,
+                       tn ? tn->pack_schedule : 0);
 }
 
 sph_status sph_interact_cells(const sph_plan *p, sph_loop loop, const void *pack_buf, size_t pack_bytes,
@@ -780,7 +797,7 @@ sph_status sph_unpack_cells(const sph_plan *p, sph_loop loop, const void *res_bu
     if (!res_buf || !aligned256(res_buf)) return fail(SPH_E_ARG, "result buffer null or misaligned");
     if (res_bytes < result_bytes_for(loop, p->n)) return fail(SPH_E_CAPACITY, "result buffer too small");
     return launch_unpack(const_cast<sph_plan *>(p), loop, res_buf, true, 0, 0, store, tn ? tn->pack_waves : 4,
-                         (hipStream_t)stream);
+                         (hipStream_t)stream, tn ? tn->pack_schedule : 0);
 }
 
 static sph_status step_batched(const sph_plan *p, const sph_store *store, const sph_params *prm,
@@ -803,9 +820,10 @@ static sph_status step_batched(const sph_plan *p, const sph_store *store, const 
     void *pack = base + interact_ws_bytes_for(2, p->n);
     void *res = (char *)pack + pack_bytes_for(2, p->n, p->ntile);
     for (int loop = 0; loop < 3; ++loop) {
-        if ((s = launch_pack(p, loop, store, true, 0, 0, pack, tn->pack_waves, st))) return s;
+        if ((s = launch_pack(p, loop, store, true, 0, 0, pack, tn->pack_waves, st, tn->pack_schedule))) return s;
         if ((s = launch_interact(p, loop, true, 0, p->ntask, pack, prm, tn, res, nullptr, q, st))) return s;
-        if ((s = launch_unpack(const_cast<sph_plan *>(p), loop, res, true, 0, 0, store, tn->pack_waves, st)))
+        if ((s = launch_unpack(const_cast<sph_plan *>(p), loop, res, true, 0, 0, store, tn->pack_waves, st,
+                               tn->pack_schedule)))
             return s;
     }
     return SPH_OK;
@@ -937,9 +955,11 @@ sph_status sph_offload_step(const sph_plan *p, const sph_store *host, const sph_
         for (int k = 0; k < d.nsub; ++k)
             if (fl[k] & 1)
                 SPH_HIP(hipMemcpyAsync(dev->sub[k], host->sub[k], (size_t)p->n * d.sub_bytes[k], hipMemcpyHostToDevice, st));
-        if ((s = launch_pack(p, loop, dev, true, 0, 0, pack, tn->pack_waves, st))) return s;
+        if ((s = launch_pack(p, loop, dev, true, 0, 0, pack, tn->pack_waves, st, tn->pack_schedule))) return s;
         if ((s = launch_interact(p, loop, true, 0, p->ntask, pack, prm, tn, res, nullptr, q, st))) return s;
-        if ((s = launch_unpack(const_cast<sph_plan *>(p), loop, res, true, 0, 0, dev, tn->pack_waves, st))) return s;
+        if ((s = launch_unpack(const_cast<sph_plan *>(p), loop, res, true, 0, 0, dev, tn->pack_waves, st,
+                               tn->pack_schedule)))
+            return s;
         for (int k = 0; k < d.nsub; ++k)
             if (fl[k] & 2)
                 SPH_HIP(hipMemcpyAsync(host->sub[k], dev->sub[k], (size_t)p->n * d.sub_bytes[k], hipMemcpyDeviceToHost, st));
@@ -1058,7 +1078,7 @@ sph_status sph_offload_step_async(const sph_plan *p, const sph_store *host, cons
                 SPH_HIP(hipStreamWaitEvent(st, e, 0));
             }
             if ((s = launch_pack_tiles(p, loop, dev, p->tile_off[cb[b]], p->tile_off[cb[b + 1]], pack, tn->pack_waves,
-                                       st)))
+                                       st, tn->pack_schedule)))
                 return s;
         }
         // 2. the interaction over every tile
@@ -1068,7 +1088,7 @@ sph_status sph_offload_step_async(const sph_plan *p, const sph_store *host, cons
         for (int b = 0; b < nb; ++b) {
             if (back[b]) SPH_HIP(hipStreamWaitEvent(st, back[b], 0));
             if ((s = launch_unpack_tiles(p, loop, res, p->tile_off[cb[b]], p->tile_off[cb[b + 1]], dev, tn->pack_waves,
-                                         st)))
+                                         st, tn->pack_schedule)))
                 return s;
             hipEvent_t u = sy.make();
             hipEvent_t c = sy.make();

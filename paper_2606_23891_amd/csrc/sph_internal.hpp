@@ -205,17 +205,22 @@ inline size_t interact_ws_bytes_for(int loop, int64_t n)
 // ---------------------------------------------------------------------------
 // launchers implemented in the .hip files
 // ---------------------------------------------------------------------------
+// schedule: the loop fission of sph_tuning.pack_schedule (batched form only;
+// per-task ranges always use the fused kernels)
 sph_status launch_pack(const sph_plan *p, int loop, const sph_store *s, bool cells, int32_t t0, int32_t t1,
-                       void *buf, int waves, hipStream_t st);
+                       void *buf, int waves, hipStream_t st, int schedule = 0);
 sph_status launch_unpack(sph_plan *p, int loop, const void *res, bool cells, int32_t t0, int32_t t1,
-                         const sph_store *s, int waves, hipStream_t st);
+                         const sph_store *s, int waves, hipStream_t st, int schedule = 0);
+// the fission groups of a layout's pack (unpack) members: bit masks as in
+// sph_fission_passes, returned count (0 for an unknown layout)
+int fission_passes(int layout, int loop, int schedule, bool unpack, uint32_t *masks);
 sph_status launch_zero(const sph_plan *p, int loop, const sph_store *s, hipStream_t st);
 // batched form over the tiles [tile0, tile1) only (the buffers keep their
 // full-size layout)
 sph_status launch_pack_tiles(const sph_plan *p, int loop, const sph_store *s, int32_t tile0, int32_t tile1,
-                             void *buf, int waves, hipStream_t st);
+                             void *buf, int waves, hipStream_t st, int schedule = 0);
 sph_status launch_unpack_tiles(const sph_plan *p, int loop, const void *res, int32_t tile0, int32_t tile1,
-                               const sph_store *s, int waves, hipStream_t st);
+                               const sph_store *s, int waves, hipStream_t st, int schedule = 0);
 sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, int32_t t1,
                            const void *pack, const sph_params *prm, const sph_tuning *tn, void *res,
                            int32_t *counts, void *ws, hipStream_t st);

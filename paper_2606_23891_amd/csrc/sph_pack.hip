@@ -229,6 +229,109 @@ __global__ __launch_bounds__(512) void k_pack(PackArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// loop fission (Sec. 3.3): a pack split into passes, each its own launch over
+// the same chunks, converting only the members of its mask
+// ---------------------------------------------------------------------------
+// members of the force record in plane order; density and gradient pack the
+// subsets kItemsOf[loop]
+constexpr int kNItem = 17;
+constexpr int kItemF[kNItem] = {FX, FX, FX, FH, FV, FV, FV, FMASS, FU, FRHO, FRHODH, FDIV, FROT, FROT, FROT, FAV, FAD};
+constexpr int kItemC[kNItem] = {0, 1, 2, 0, 0, 1, 2, 0, 0, 0, 0, 0, 0, 1, 2, 0, 0};
+constexpr uint32_t kItemsOf[3] = {0x8Fu, 0x3FFu, 0x1FFFFu};
+// the member stored in word w of plane q of a loop's record (-1: none)
+constexpr int kPlaneItem[3][5][4] = {{{0, 1, 2, 3}, {7, -1, -1, -1}},
+                                     {{0, 1, 2, 3}, {4, 5, 6, 7}, {8, 9, -1, -1}},
+                                     {{0, 1, 2, 3}, {4, 5, 6, 7}, {8, 9, 10, 11}, {12, 13, 14, 15}, {16, -1, -1, -1}}};
+
+constexpr uint32_t plane_mask(int loop, int q)
+{
+    uint32_t m = 0;
+    for (int w = 0; w < 4; ++w)
+        if (kPlaneItem[loop][q][w] >= 0) m |= 1u << kPlaneItem[loop][q][w];
+    return m;
+}
+
+// One pass of a fissioned pack: as k_pack, restricted to the members in
+// `mask` (uniform, so every test below is a scalar branch).  A plane whose
+// members all belong to the pass is stored whole, otherwise member by member;
+// the pass holding a position component writes that component's chunk bounds,
+// the pass holding h the largest support radius.
+template <int L, int LOOP>
+__global__ __launch_bounds__(512) void k_pack_pass(PackArgs a, uint32_t mask)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t c = __builtin_amdgcn_readfirstlane((int)((int64_t)blockIdx.x * (blockDim.x >> 6) +
+                                                           (threadIdx.x >> 6)));
+    if (c >= a.nchunk) return;
+    const Chunk ch = a.chunks[a.chunk_base + c];
+    const sph_cell &oc = a.cells[ch.cell];
+    double o[3] = {oc.loc[0], oc.loc[1], oc.loc[2]};
+    if (ch.side) {
+        const sph_task &t = a.tasks[ch.task];
+        o[0] = o[0] - t.shift[0];
+        o[1] = o[1] - t.shift[1];
+        o[2] = o[2] - t.shift[2];
+    }
+    const bool valid = lane < ch.n;
+    const int64_t p = ch.part0 + lane;
+    const int64_t slot = ch.slot0 - a.slot_base + lane;
+    float val[kNItem] = {};
+    if (valid) {
+        static_for<0, kNItem>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            constexpr int F = kItemF[k], C = kItemC[k];
+            if constexpr ((kItemsOf[LOOP] >> k) & 1u) {
+                if ((mask >> k) & 1u) {
+                    if constexpr (F == FX) val[k] = (float)(ld<L, FX, C, double>(a.store, p) - o[C]);
+                    else val[k] = ld<L, F, C, float>(a.store, p);
+                }
+            }
+        });
+        int64_t plane_off = 0;
+        static_for<0, kPackPlanes[LOOP]>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr int nf = kPlaneFloats[LOOP][q];
+            constexpr uint32_t pm = plane_mask(LOOP, q);
+            float *pl = (float *)(a.buf + plane_off) + slot * nf;
+            if ((mask & pm) == pm) {
+                if constexpr (nf == 4)
+                    *(float4 *)pl = make_float4(val[kPlaneItem[LOOP][q][0]], val[kPlaneItem[LOOP][q][1]],
+                                                val[kPlaneItem[LOOP][q][2]], val[kPlaneItem[LOOP][q][3]]);
+                else if constexpr (nf == 2)
+                    *(float2 *)pl = make_float2(val[kPlaneItem[LOOP][q][0]], val[kPlaneItem[LOOP][q][1]]);
+                else
+                    *pl = val[kPlaneItem[LOOP][q][0]];
+            } else if (mask & pm) {
+                static_for<0, nf>([&](auto wc) {
+                    constexpr int w = decltype(wc)::value;
+                    if ((mask >> kPlaneItem[LOOP][q][w]) & 1u) pl[w] = val[kPlaneItem[LOOP][q][w]];
+                });
+            }
+            plane_off += a.P * 4 * nf;
+        });
+    }
+    float *lo = (float *)&a.bounds[2 * c], *hi = (float *)&a.bounds[2 * c + 1];
+    const float inf = __builtin_huge_valf();
+    static_for<0, 3>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        if ((mask >> k) & 1u) {
+            const float l = wave_min_u(valid ? val[k] : inf), h = wave_max_u(valid ? val[k] : -inf);
+            if (lane == 0) {
+                lo[k] = l;
+                hi[k] = h;
+            }
+        }
+    });
+    if ((mask >> 3) & 1u) {
+        const float hm = wave_max_u(valid ? kGammaK * val[3] : 0.f);
+        if (lane == 0) {
+            lo[3] = hm;
+            hi[3] = 0.f;
+        }
+    }
+}
+
 // loop outputs: (field, component) per result plane
 constexpr int kOutF[3][6] = {{FRHO, FRHODH, FWCOUNT}, {FDIV, FROT, FROT, FROT, FLAP, FVSIG}, {FA, FA, FA, FUDT}};
 constexpr int kOutC[3][6] = {{0, 0, 0}, {0, 0, 1, 2, 0, 0}, {0, 1, 2, 0}};
@@ -253,12 +356,14 @@ struct UnpackArgs {
     const int64_t *csr;
     int64_t slot_lo, slot_hi;  // absolute slots of the range (CSR path)
     int64_t n;
+    uint32_t mask;             // result planes of a fissioned pass (MASKED kernels)
 };
 
 // One chunk per wave.  CELLS: per-particle results, out = +0 (+) r; else one
 // task's partials added into the current value (slots of one task touch
-// distinct particles, so lanes never collide).
-template <int L, int LOOP, bool CELLS>
+// distinct particles, so lanes never collide).  MASKED: one pass of a
+// fissioned unpack, writing only the result planes in a.mask.
+template <int L, int LOOP, bool CELLS, bool MASKED>
 __global__ __launch_bounds__(512) void k_unpack_chunks(UnpackArgs a)
 {
     const int lane = threadIdx.x & 63;
@@ -272,6 +377,8 @@ __global__ __launch_bounds__(512) void k_unpack_chunks(UnpackArgs a)
     static_for<0, kResPlanes[LOOP]>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         constexpr int F = kOutF[LOOP][k], C = kOutC[LOOP][k];
+        if constexpr (MASKED)
+            if (!((a.mask >> k) & 1u)) return;
         const float r = a.res[k * a.P + slot];
         const float cur = CELLS ? 0.0f : ld<L, F, C, float>(a.store, p);
         st<L, F, C, float>(a.store, p, reduce_one<LOOP, k>(cur, r));
@@ -298,37 +405,99 @@ __global__ __launch_bounds__(256) void k_unpack_csr(UnpackArgs a)
     });
 }
 
+// the fission groups of a layout's pack (unpack) members under a schedule
 template <int L>
-static sph_status pack_l(const sph_plan *p, int loop, const PackArgs &a, int waves, hipStream_t st)
+static int passes_l(int loop, int schedule, bool unpack, uint32_t *masks)
+{
+    const int nmem = unpack ? kResPlanes[loop] : kNItem;
+    int key[kNItem];
+    int ng = 0;
+    for (int k = 0; k < nmem; ++k) {
+        if (!unpack && !((kItemsOf[loop] >> k) & 1u)) continue;
+        const int F = unpack ? kOutF[loop][k] : kItemF[k];
+        const int C = unpack ? kOutC[loop][k] : kItemC[k];
+        const int sub = kLayouts[L].sub[F][C], bytes = kCompBytes[F];
+        const int kk = schedule == 1 ? sub : schedule == 2 ? F : schedule == 3 ? bytes : schedule == 4 ? sub * 16 + bytes : 0;
+        int g = 0;
+        while (g < ng && key[g] != kk) ++g;
+        if (g == ng) {
+            key[ng] = kk;
+            masks[ng++] = 0;
+        }
+        masks[g] |= 1u << k;
+    }
+    return ng;
+}
+
+int fission_passes(int layout, int loop, int schedule, bool unpack, uint32_t *masks)
+{
+    switch (layout) {
+    case 0: return passes_l<0>(loop, schedule, unpack, masks);
+    case 1: return passes_l<1>(loop, schedule, unpack, masks);
+    case 2: return passes_l<2>(loop, schedule, unpack, masks);
+    case 3: return passes_l<3>(loop, schedule, unpack, masks);
+    case 4: return passes_l<4>(loop, schedule, unpack, masks);
+    case 5: return passes_l<5>(loop, schedule, unpack, masks);
+    case 6: return passes_l<6>(loop, schedule, unpack, masks);
+    case 7: return passes_l<7>(loop, schedule, unpack, masks);
+    case 8: return passes_l<8>(loop, schedule, unpack, masks);
+    default: return 0;
+    }
+}
+
+template <int L>
+static sph_status pack_l(const sph_plan *p, int loop, const PackArgs &a, int waves, int schedule, hipStream_t st)
 {
     const unsigned grid = (unsigned)((a.nchunk + waves - 1) / waves);
     const dim3 blk(64 * waves);
-    if (loop == 0) hipLaunchKernelGGL((k_pack<L, 0>), dim3(grid), blk, 0, st, a);
-    else if (loop == 1) hipLaunchKernelGGL((k_pack<L, 1>), dim3(grid), blk, 0, st, a);
-    else hipLaunchKernelGGL((k_pack<L, 2>), dim3(grid), blk, 0, st, a);
+    if (schedule == 0) {
+        if (loop == 0) hipLaunchKernelGGL((k_pack<L, 0>), dim3(grid), blk, 0, st, a);
+        else if (loop == 1) hipLaunchKernelGGL((k_pack<L, 1>), dim3(grid), blk, 0, st, a);
+        else hipLaunchKernelGGL((k_pack<L, 2>), dim3(grid), blk, 0, st, a);
+    } else {
+        uint32_t masks[kNItem];
+        const int np = passes_l<L>(loop, schedule, false, masks);
+        for (int q = 0; q < np; ++q) {
+            if (loop == 0) hipLaunchKernelGGL((k_pack_pass<L, 0>), dim3(grid), blk, 0, st, a, masks[q]);
+            else if (loop == 1) hipLaunchKernelGGL((k_pack_pass<L, 1>), dim3(grid), blk, 0, st, a, masks[q]);
+            else hipLaunchKernelGGL((k_pack_pass<L, 2>), dim3(grid), blk, 0, st, a, masks[q]);
+        }
+    }
     (void)p;
     SPH_CHECK_LAUNCH("pack launch");
     return SPH_OK;
 }
 
 template <int L, int LOOP>
-static void unpack_ll(const UnpackArgs &a, bool cells, bool csr, int waves, hipStream_t st)
+static void unpack_ll(const UnpackArgs &a, bool cells, bool csr, int waves, int schedule, hipStream_t st)
 {
     if (csr) {
         hipLaunchKernelGGL((k_unpack_csr<L, LOOP>), dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
         return;
     }
     const unsigned grid = (unsigned)((a.nchunk + waves - 1) / waves);
-    if (cells) hipLaunchKernelGGL((k_unpack_chunks<L, LOOP, true>), dim3(grid), dim3(64 * waves), 0, st, a);
-    else hipLaunchKernelGGL((k_unpack_chunks<L, LOOP, false>), dim3(grid), dim3(64 * waves), 0, st, a);
+    if (!cells) {
+        hipLaunchKernelGGL((k_unpack_chunks<L, LOOP, false, false>), dim3(grid), dim3(64 * waves), 0, st, a);
+    } else if (schedule == 0) {
+        hipLaunchKernelGGL((k_unpack_chunks<L, LOOP, true, false>), dim3(grid), dim3(64 * waves), 0, st, a);
+    } else {
+        uint32_t masks[kNItem];
+        const int np = passes_l<L>(LOOP, schedule, true, masks);
+        UnpackArgs b = a;
+        for (int q = 0; q < np; ++q) {
+            b.mask = masks[q];
+            hipLaunchKernelGGL((k_unpack_chunks<L, LOOP, true, true>), dim3(grid), dim3(64 * waves), 0, st, b);
+        }
+    }
 }
 
 template <int L>
-static sph_status unpack_l(int loop, const UnpackArgs &a, bool cells, bool csr, int waves, hipStream_t st)
+static sph_status unpack_l(int loop, const UnpackArgs &a, bool cells, bool csr, int waves, int schedule,
+                           hipStream_t st)
 {
-    if (loop == 0) unpack_ll<L, 0>(a, cells, csr, waves, st);
-    else if (loop == 1) unpack_ll<L, 1>(a, cells, csr, waves, st);
-    else unpack_ll<L, 2>(a, cells, csr, waves, st);
+    if (loop == 0) unpack_ll<L, 0>(a, cells, csr, waves, schedule, st);
+    else if (loop == 1) unpack_ll<L, 1>(a, cells, csr, waves, schedule, st);
+    else unpack_ll<L, 2>(a, cells, csr, waves, schedule, st);
     SPH_CHECK_LAUNCH("unpack launch");
     return SPH_OK;
 }
@@ -344,7 +513,7 @@ static sph_status unpack_l(int loop, const UnpackArgs &a, bool cells, bool csr, 
     }
 
 sph_status launch_pack(const sph_plan *p, int loop, const sph_store *s, bool cells, int32_t t0, int32_t t1,
-                       void *buf, int waves, hipStream_t st)
+                       void *buf, int waves, hipStream_t st, int schedule)
 {
     PackArgs a{};
     a.store = store_arg(s);
@@ -368,11 +537,11 @@ sph_status launch_pack(const sph_plan *p, int loop, const sph_store *s, bool cel
     a.P = round_slots(nslot);
     a.bounds = (float4 *)(a.buf + a.P * 4 * kPackFloats[loop]);
     if (a.nchunk == 0) return SPH_OK;
-    SPH_BY_LAYOUT(s->layout, pack_l, p, loop, a, waves, st);
+    SPH_BY_LAYOUT(s->layout, pack_l, p, loop, a, waves, schedule, st);
 }
 
 sph_status launch_pack_tiles(const sph_plan *p, int loop, const sph_store *s, int32_t tile0, int32_t tile1,
-                             void *buf, int waves, hipStream_t st)
+                             void *buf, int waves, hipStream_t st, int schedule)
 {
     PackArgs a{};
     a.store = store_arg(s);
@@ -387,11 +556,11 @@ sph_status launch_pack_tiles(const sph_plan *p, int loop, const sph_store *s, in
     // chunk c of the launch is tile tile0 + c: its bounds sit at that tile's place
     a.bounds = (float4 *)(a.buf + a.P * 4 * kPackFloats[loop]) + 2 * (int64_t)tile0;
     if (a.nchunk <= 0) return SPH_OK;
-    SPH_BY_LAYOUT(s->layout, pack_l, p, loop, a, waves, st);
+    SPH_BY_LAYOUT(s->layout, pack_l, p, loop, a, waves, schedule, st);
 }
 
 sph_status launch_unpack_tiles(const sph_plan *p, int loop, const void *res, int32_t tile0, int32_t tile1,
-                               const sph_store *s, int waves, hipStream_t st)
+                               const sph_store *s, int waves, hipStream_t st, int schedule)
 {
     UnpackArgs a{};
     a.store = store_arg(s);
@@ -402,11 +571,11 @@ sph_status launch_unpack_tiles(const sph_plan *p, int loop, const void *res, int
     a.nchunk = tile1 - tile0;
     a.P = round_slots(p->n);
     if (a.nchunk <= 0) return SPH_OK;
-    SPH_BY_LAYOUT(s->layout, unpack_l, loop, a, true, false, waves, st);
+    SPH_BY_LAYOUT(s->layout, unpack_l, loop, a, true, false, waves, schedule, st);
 }
 
 sph_status launch_unpack(sph_plan *p, int loop, const void *res, bool cells, int32_t t0, int32_t t1,
-                         const sph_store *s, int waves, hipStream_t st)
+                         const sph_store *s, int waves, hipStream_t st, int schedule)
 {
     UnpackArgs a{};
     a.store = store_arg(s);
@@ -432,7 +601,7 @@ sph_status launch_unpack(sph_plan *p, int loop, const void *res, bool cells, int
         }
     }
     if (a.nchunk == 0) return SPH_OK;
-    SPH_BY_LAYOUT(s->layout, unpack_l, loop, a, cells, csr, waves, st);
+    SPH_BY_LAYOUT(s->layout, unpack_l, loop, a, cells, csr, waves, schedule, st);
 }
 
 }  // namespace sph

@@ -42,7 +42,7 @@ class sph_params(C.Structure):
 
 class sph_tuning(C.Structure):
     _fields_ = [("blocks_per_cu", C.c_int32), ("window", C.c_int32 * 3), ("pack_waves", C.c_int32),
-                ("queue", C.c_int32), ("blocks_per_loop", C.c_int32 * 3), ("reserved", C.c_int32)]
+                ("queue", C.c_int32), ("blocks_per_loop", C.c_int32 * 3), ("pack_schedule", C.c_int32)]
 
 
 class sph_plan_info(C.Structure):
@@ -66,6 +66,8 @@ _SIGS = {
     "sph_field_location": ([i32, i32, i32, C.POINTER(i32), C.POINTER(sz), C.POINTER(sz)], i32),
     "sph_field_info": ([i32, C.POINTER(i32), C.POINTER(i32)], i32),
     "sph_pack_layout": ([i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)], i32),
+    "sph_fission_passes": ([i32, i32, i32, C.POINTER(i32), C.POINTER(C.c_uint32), C.POINTER(i32),
+                            C.POINTER(C.c_uint32)], i32),
     "sph_store_put": ([vp, i32, vp, vp], i32),
     "sph_store_get": ([vp, i32, vp, vp], i32),
     "sph_plan_create": ([vp, i32, vp, i32, i64, C.POINTER(vp)], i32),
@@ -181,6 +183,19 @@ def sph_pack_layout(loop: int):
     pf = (i32 * 5)()
     _check(lib().sph_pack_layout(loop, C.byref(n), pf, C.byref(rp)), "sph_pack_layout")
     return [pf[i] for i in range(n.value)], rp.value
+
+
+MAX_PASSES = 32
+SCHEDULES = {"by_particle": 0, "by_struct": 1, "by_element": 2, "by_type": 3, "by_struct_and_type": 4}
+
+
+def sph_fission_passes(layout: int, loop: int, schedule: int):
+    """(pack masks, unpack masks) of the kernels a fissioned pack / unpack runs."""
+    npk, nun = i32(), i32()
+    pm, um = (C.c_uint32 * MAX_PASSES)(), (C.c_uint32 * MAX_PASSES)()
+    _check(lib().sph_fission_passes(layout, loop, schedule, C.byref(npk), pm, C.byref(nun), um),
+           "sph_fission_passes")
+    return [int(pm[i]) for i in range(npk.value)], [int(um[i]) for i in range(nun.value)]
 
 
 # ---------------------------------------------------------------------------

@@ -56,7 +56,7 @@ def apply(tuning, entry: dict):
             arr = getattr(tuning, k)
             for i, w in enumerate(v):
                 arr[i] = int(w)
-        elif k in ("blocks_per_cu", "pack_waves", "queue"):
+        elif k in ("blocks_per_cu", "pack_waves", "queue", "pack_schedule"):
             setattr(tuning, k, int(v))
     return tuning
 
@@ -113,6 +113,24 @@ def tune(plan, store, log=print):
         if pw_t is None or ms < pw_t:
             pw_best, pw_t = pw, ms
     best["pack_waves"] = pw_best
+    # loop fission of the conversions: the fused kernels or one of the split
+    # schedules, whichever moves the layout's fields fastest
+    ps_best, ps_t = 0, None
+    for sname, sched in sph.SCHEDULES.items():
+        t = sph.default_tuning()
+        t.pack_waves, t.pack_schedule = pw_best, sched
+
+        def run():
+            for L in range(3):
+                pack, res = bufs[L]
+                sph.sph_pack_cells(plan, L, store, pack, t)
+                sph.sph_unpack_cells(plan, L, res, store, t)
+        ms = _timed(run)
+        times[f"pack_unpack_{sname}"] = ms
+        log(f"pack+unpack {sname}: {ms:.3f} ms")
+        if ps_t is None or ms < ps_t:
+            ps_best, ps_t = sched, ms
+    best["pack_schedule"] = ps_best
     # interaction kernels: each loop takes its own window and grid size; the
     # queue mode is shared, chosen on the sum of the loops' best times
     totals = {}

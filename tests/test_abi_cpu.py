@@ -46,6 +46,68 @@ def test_pack_record_matches_oracle():
         assert rp == oracle.RESULT_PLANES[loop]
 
 
+# members of the force record in plane order, the subsets density and
+# gradient pack, and each loop's result planes (field, component)
+_MEMBERS = [("x", 0), ("x", 1), ("x", 2), ("h", 0), ("v", 0), ("v", 1), ("v", 2), ("mass", 0), ("u", 0),
+            ("rho", 0), ("rho_dh", 0), ("div_v", 0), ("rot_v", 0), ("rot_v", 1), ("rot_v", 2), ("alpha_v", 0),
+            ("alpha_d", 0)]
+_LOOP_MEMBERS = [[0, 1, 2, 3, 7], list(range(10)), list(range(17))]
+_RESULTS = [[("rho", 0), ("rho_dh", 0), ("wcount", 0)],
+            [("div_v", 0), ("rot_v", 0), ("rot_v", 1), ("rot_v", 2), ("lap_u", 0), ("v_sig", 0)],
+            [("a", 0), ("a", 1), ("a", 2), ("u_dt", 0)]]
+
+
+@pytest.mark.parametrize("layout", range(9))
+def test_fission_passes_partition_by_schedule_key(layout):
+    """every schedule's pass masks partition the loop's members, members of a
+    pass share the schedule's key (none / substruct / field / component type /
+    both) read from the layout tables, passes differ in it and come in the
+    order of their first member"""
+    for loop in range(3):
+        packs = [(_MEMBERS[k], k) for k in _LOOP_MEMBERS[loop]]
+        unpacks = [(fc, k) for k, fc in enumerate(_RESULTS[loop])]
+        for sched in range(5):
+            pm, um = sph.sph_fission_passes(layout, loop, sched)
+            for masks, mem in ((pm, packs), (um, unpacks)):
+                def key(fc):
+                    fid = sph.FIELD_ID[fc[0]]
+                    sub = sph.sph_field_location(layout, fid, fc[1])[0]
+                    nbytes = sph.sph_field_info(fid)[1]
+                    return [0, sub, fid, nbytes, (sub, nbytes)][sched]
+                want_order, groups = [], {}
+                for fc, bit in mem:
+                    kk = key(fc)
+                    if kk not in groups:
+                        want_order.append(kk)
+                        groups[kk] = 0
+                    groups[kk] |= 1 << bit
+                assert masks == [groups[kk] for kk in want_order], (layout, loop, sched)
+                union = 0
+                for m in masks:
+                    assert m and not (union & m)
+                    union |= m
+                assert union == sum(1 << bit for _, bit in mem)
+            if sched == 0:
+                assert len(pm) == 1 and len(um) == 1
+    with pytest.raises(sph.SphError):
+        sph.sph_fission_passes(layout, 0, 5)
+    with pytest.raises(sph.SphError):
+        sph.sph_fission_passes(layout, 3, 1)
+
+
+def test_fission_passes_known_counts():
+    """SoA splits every component; AoS has one substruct; the type split
+    separates positions (float64) from the float32 members"""
+    soa, aos, shared = sph.LAYOUTS.index("SOA"), sph.LAYOUTS.index("AOS"), sph.LAYOUTS.index("SAOS_SHARED")
+    assert len(sph.sph_fission_passes(soa, 2, 1)[0]) == 17
+    assert len(sph.sph_fission_passes(aos, 2, 1)[0]) == 1
+    assert len(sph.sph_fission_passes(aos, 2, 2)[0]) == 11
+    assert sph.sph_fission_passes(aos, 0, 3)[0] == [0x7, 0x88]
+    assert len(sph.sph_fission_passes(shared, 2, 1)[0]) == 3
+    assert len(sph.sph_fission_passes(shared, 2, 4)[0]) == 4
+    assert sph.sph_fission_passes(shared, 0, 1)[1] == [1, 2, 4]
+
+
 def _status(name, *args):
     return getattr(sph.lib(), name)(*args)
 

@@ -132,6 +132,76 @@ def test_cells_pack_unpack_bitexact(sets, layout):
         plan.close()
 
 
+@pytest.mark.parametrize("layout", [0, 1, 4, 7, 8])
+def test_fission_schedules_bitexact(sets, layout):
+    """every loop-fission schedule of the batched pack and unpack writes the
+    same bytes as the fused kernels (pack buffers pre-filled with a pattern,
+    so a missed or stray write shows) and as the oracle"""
+    import torch
+    rng = np.random.default_rng(9)
+    for name in ("grid512", "octree"):
+        ps = sets[name]
+        f = inputs.random_fields(ps.n, 19, x=ps.fields["x"])
+        plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+        for loop in range(3):
+            host = oracle.HostStore(layout, ps.n)
+            host.put_all(f)
+            ref = oracle.pack_cells(host, loop, ps.cells)
+            P = oracle.round_slots(ps.n)
+            r = rng.uniform(-1, 1, (oracle.RESULT_PLANES[loop], P)).astype(np.float32)
+            r[:, :5] = [-0.0, 0.0, 1e-40, -1e-40, 3.0]
+            oracle.unpack_cells(host, loop, r)
+            fused = None
+            for sched in range(5):
+                log(f"fission {name} layout={layout} loop={loop} schedule={sched} "
+                    f"passes={sph.sph_fission_passes(layout, loop, sched)}")
+                tn = sph.default_tuning()
+                tn.pack_schedule = sched
+                st = sph.Store(layout, ps.n)
+                st.put_all(f)
+                pack, res = sph.cell_buffers(plan, loop)
+                pack.fill_(0x5A)
+                sph.sph_pack_cells(plan, loop, st, pack, tn)
+                torch.cuda.synchronize()
+                got = pack.cpu().numpy()
+                if fused is None:
+                    fused = got
+                assert np.array_equal(got, fused), sched
+                pack.zero_()
+                sph.sph_pack_cells(plan, loop, st, pack, tn)
+                torch.cuda.synchronize()
+                assert np.array_equal(pack.cpu().numpy()[: ref.size], ref), sched
+                res[: r.nbytes].copy_(torch.from_numpy(r.view(np.uint8).reshape(-1)))
+                sph.sph_unpack_cells(plan, loop, res, st, tn)
+                torch.cuda.synchronize()
+                assert st.raw() == host.raw(), sched
+        plan.close()
+
+
+def test_fission_step_matches_fused_step():
+    """a whole batched step under each schedule leaves the store byte for byte
+    as the fused step does; an unknown schedule is refused"""
+    import torch
+    ps = inputs.make_config(1, n_side=32)
+    lay = sph.LAYOUTS.index("SAOS_SHARED")
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    ws = torch.zeros(sph.sph_batched_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    ref = None
+    for sched in range(5):
+        log(f"fission step schedule={sched}")
+        tn = sph.default_tuning()
+        tn.pack_schedule = sched
+        st = device_store(ps, lay)
+        sph.sph_step_batched(plan, st, ws, tuning=tn)
+        torch.cuda.synchronize()
+        ref = st.raw() if ref is None else ref
+        assert st.raw() == ref, sched
+    tn.pack_schedule = 5
+    with pytest.raises(sph.SphError):
+        sph.sph_step_batched(plan, st, ws, tuning=tn)
+    plan.close()
+
+
 def _check_loops(ps, layout, mode, rows=None, bundle=1):
     """density -> gradient -> force on the GPU; each loop compared with the oracle
     fed the GPU's own previous-loop outputs (loop isolation)."""

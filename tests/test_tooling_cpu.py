@@ -63,7 +63,8 @@ def test_tuning_cache_keys_and_apply(tmp_path, monkeypatch):
     cache = tmp_path / "cache.json"
     cache.write_text(json.dumps({"gfx950-256cu": {sig: {"window": [512, 256, 128], "blocks_per_cu": 2,
                                                          "blocks_per_loop": [8, 4, 2],
-                                                         "queue": 2, "pack_waves": 8}}}))
+                                                         "queue": 2, "pack_waves": 8,
+                                                         "pack_schedule": 3}}}))
     monkeypatch.setattr(tune, "CACHE", str(cache))
     entry = tune.load("gfx950-256cu", sig)
     assert tune.load("gfx942-304cu", sig) is None
@@ -71,7 +72,8 @@ def test_tuning_cache_keys_and_apply(tmp_path, monkeypatch):
     class T:
         window = [0, 0, 0]
         blocks_per_loop = [0, 0, 0]
-        blocks_per_cu = pack_waves = queue = 0
+        blocks_per_cu = pack_waves = queue = pack_schedule = 0
     t = tune.apply(T(), entry)
+    assert t.pack_schedule == 3
     assert list(t.window) == [512, 256, 128] and (t.blocks_per_cu, t.queue, t.pack_waves) == (2, 2, 8)
     assert list(t.blocks_per_loop) == [8, 4, 2]
