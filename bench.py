@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--fission", default=None,
                     help="'all' or comma list of layouts: also time pack + unpack under every "
                          "loop-fission schedule")
+    ap.add_argument("--convert", default=None,
+                    help="'default' or comma list of SRC:DST layouts: also time whole-store layout "
+                         "conversions")
     ap.add_argument("--offload", default=None,
                     help="'all' or comma list of layouts: also time the offload form (pinned host store)")
     ap.add_argument("--copy-mib", type=int, default=1024,
@@ -343,6 +346,10 @@ def main():
         names = sph.LAYOUTS if a.fission == "all" else a.fission.split(",")
         out["fission"] = fission_sweep(ps, plan, names, tuning, a.steps)
 
+    if a.convert:
+        pairs = CONVERT_PAIRS if a.convert == "default" else [tuple(x.split(":")) for x in a.convert.split(",")]
+        out["convert"] = convert_sweep(ps, pairs, a.steps)
+
     if a.offload:
         names = sph.LAYOUTS if a.offload == "all" else a.offload.split(",")
         out["offload"] = offload_sweep(ps, plan, names, tuning)
@@ -442,6 +449,45 @@ def fission_sweep(ps, plan, names, tuning, steps):
             res[name][sname]["vs_by_particle"] = round(res[name][sname]["total_ms"] / base, 4)
         del st
         torch.cuda.empty_cache()
+    return res
+
+
+CONVERT_PAIRS = [("AOS", "SOA"), ("SOA", "AOS"), ("AOS", "SAOS_SHARED"), ("SAOS_SHARED", "AOS"),
+                 ("SAOS_SHARED", "SOA"), ("SOA", "SAOS_SHARED"), ("SAOS_SHARED", "SAOS_SHARED")]
+
+
+def convert_sweep(ps, pairs, steps):
+    """whole-store layout conversion: time and rate (every record of both
+    stores moved once)"""
+    import torch
+
+    from paper_2606_23891_amd import sph
+
+    stream = torch.cuda.current_stream()
+    res = {}
+    stores = {}
+    for src_name, dst_name in pairs:
+        for nm in (src_name, dst_name):
+            if nm not in stores:
+                stores[nm] = sph.Store(sph.LAYOUTS.index(nm), ps.n)
+                stores[nm].put_all(ps.fields)
+        src = stores[src_name]
+        dst = stores[dst_name] if dst_name != src_name else sph.Store(sph.LAYOUTS.index(dst_name), ps.n)
+        sph.sph_store_convert(src, dst)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            sph.sph_store_convert(src, dst)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        nbytes = ps.n * (sum(sph.sph_layout_info(src.layout)) + sum(sph.sph_layout_info(dst.layout)))
+        res[f"{src_name}->{dst_name}"] = {"ms": round(ms, 4), "bytes": nbytes,
+                                          "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+        log(f"convert {src_name} -> {dst_name}: {ms:.3f} ms, {nbytes / (ms * 1e-3) / 1e9:.0f} GB/s")
+    del stores
+    torch.cuda.empty_cache()
     return res
 
 

@@ -204,6 +204,14 @@ sph_status sph_fission_passes(sph_layout layout, sph_loop loop, int32_t schedule
 sph_status sph_store_put(const sph_store *store, sph_field field, const void *src, void *stream);
 /* Copy a field out of the store into a dense device array dst[n][ncomp]. */
 sph_status sph_store_get(const sph_store *store, sph_field field, void *dst, void *stream);
+/* Rewrite a store into another layout (a decomposition that changes with the
+ * algorithmic phase, Sec. 4's Recommendation 3): every component of every
+ * field of every particle is copied bit for bit from src into dst, the
+ * padding bytes of dst's records are set to zero.  Both are device stores of
+ * the same n, in any two layouts (the same one included); no substruct of dst
+ * may overlap one of src (SPH_E_ARG).  One kernel, one thread per particle:
+ * each source record read once, each destination record written once. */
+sph_status sph_store_convert(const sph_store *src, const sph_store *dst, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Plan: cells and tasks of one step (Sec. 2.2).                            */

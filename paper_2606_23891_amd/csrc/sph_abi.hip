@@ -301,6 +301,24 @@ sph_status sph_store_get(const sph_store *store, sph_field field, void *dst, voi
     return store_copy(store, field, nullptr, dst, stream);
 }
 
+sph_status sph_store_convert(const sph_store *src, const sph_store *dst, void *stream)
+{
+    sph_status s;
+    if ((s = check_store(src)) || (s = check_store(dst))) return s;
+    if (src->n != dst->n) return fail(SPH_E_ARG, "stores hold different particle counts");
+    if (src->n == 0) return SPH_OK;
+    // no destination substruct may share bytes with a source substruct
+    for (int i = 0; i < src->nsub; ++i)
+        for (int j = 0; j < dst->nsub; ++j) {
+            const uintptr_t a0 = (uintptr_t)src->sub[i], a1 = a0 + (uintptr_t)src->n * kLayouts[src->layout].sub_bytes[i];
+            const uintptr_t b0 = (uintptr_t)dst->sub[j], b1 = b0 + (uintptr_t)dst->n * kLayouts[dst->layout].sub_bytes[j];
+            if (a0 < b1 && b0 < a1)
+                return fail(SPH_E_ARG, "destination substruct " + std::to_string(j) + " overlaps source substruct " +
+                                           std::to_string(i));
+        }
+    return launch_convert(src, dst, (hipStream_t)stream);
+}
+
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------

@@ -211,6 +211,8 @@ sph_status launch_pack(const sph_plan *p, int loop, const sph_store *s, bool cel
                        void *buf, int waves, hipStream_t st, int schedule = 0);
 sph_status launch_unpack(sph_plan *p, int loop, const void *res, bool cells, int32_t t0, int32_t t1,
                          const sph_store *s, int waves, hipStream_t st, int schedule = 0);
+// every member of every particle of src into dst (checked stores, same n)
+sph_status launch_convert(const sph_store *src, const sph_store *dst, hipStream_t st);
 // the fission groups of a layout's pack (unpack) members: bit masks as in
 // sph_fission_passes, returned count (0 for an unknown layout)
 int fission_passes(int layout, int loop, int schedule, bool unpack, uint32_t *masks);

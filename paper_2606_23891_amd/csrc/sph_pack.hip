@@ -502,6 +502,162 @@ static sph_status unpack_l(int loop, const UnpackArgs &a, bool cells, bool csr, 
     return SPH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// layout conversion: every member of every particle from one layout's store
+// into another's (a store that changes its decomposition between phases)
+// ---------------------------------------------------------------------------
+// a particle's members as 32-bit words: 8-byte components take two, the
+// 1-byte time bin one (low byte)
+constexpr int comp_words(int f) { return kCompBytes[f] == 8 ? 2 : 1; }
+constexpr int word_of(int f, int c)
+{
+    int w = 0;
+    for (int g = 0; g < f; ++g) w += kNComp[g] * comp_words(g);
+    return w + c * comp_words(f);
+}
+constexpr int kParticleWords = word_of(NFIELD - 1, 0) + kNComp[NFIELD - 1] * comp_words(NFIELD - 1);
+static_assert(kParticleWords == 40, "member words");
+
+// Read substruct S of layout L whole (records of 1 byte: one byte load) and
+// take out its members.
+template <int L, int S>
+__device__ __forceinline__ void read_record(const StoreArg &st, int64_t p, uint32_t *v)
+{
+    constexpr int R = kLayouts[L].sub_bytes[S];
+    const char *base = (const char *)__builtin_assume_aligned(st.sub[S], 256) + p * R;
+    if constexpr (R == 1) {
+        // the only 1-byte record is a lone 1-byte member
+        static_for<0, NFIELD>([&](auto fc) {
+            constexpr int F = decltype(fc)::value;
+            static_for<0, kNComp[F]>([&](auto cc) {
+                constexpr int C = decltype(cc)::value;
+                if constexpr (kLayouts[L].sub[F][C] == S) v[word_of(F, C)] = *(const uint8_t *)base;
+            });
+        });
+    } else {
+        constexpr int G = load_width(R, 0);
+        uint32_t w[R / 4];
+        static_for<0, R / G>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            if constexpr (G == 16) {
+                const uint4 q = *(const uint4 *)(base + 16 * k);
+                w[4 * k] = q.x;
+                w[4 * k + 1] = q.y;
+                w[4 * k + 2] = q.z;
+                w[4 * k + 3] = q.w;
+            } else if constexpr (G == 8) {
+                const uint2 q = *(const uint2 *)(base + 8 * k);
+                w[2 * k] = q.x;
+                w[2 * k + 1] = q.y;
+            } else {
+                w[k] = *(const uint32_t *)(base + 4 * k);
+            }
+        });
+        static_for<0, NFIELD>([&](auto fc) {
+            constexpr int F = decltype(fc)::value;
+            static_for<0, kNComp[F]>([&](auto cc) {
+                constexpr int C = decltype(cc)::value;
+                if constexpr (kLayouts[L].sub[F][C] == S) {
+                    constexpr int off = kLayouts[L].off[F][C], k = word_of(F, C);
+                    if constexpr (kCompBytes[F] == 8) {
+                        v[k] = w[off / 4];
+                        v[k + 1] = w[off / 4 + 1];
+                    } else if constexpr (kCompBytes[F] == 4) {
+                        v[k] = w[off / 4];
+                    } else {
+                        v[k] = (w[off / 4] >> (8 * (off % 4))) & 0xFFu;
+                    }
+                }
+            });
+        });
+    }
+}
+
+// Assemble substruct S of layout L from the member words (padding bytes
+// zero) and write the record whole.
+template <int L, int S>
+__device__ __forceinline__ void write_record(const StoreArg &st, int64_t p, const uint32_t *v)
+{
+    constexpr int R = kLayouts[L].sub_bytes[S];
+    char *base = (char *)__builtin_assume_aligned(st.sub[S], 256) + p * R;
+    if constexpr (R == 1) {
+        static_for<0, NFIELD>([&](auto fc) {
+            constexpr int F = decltype(fc)::value;
+            static_for<0, kNComp[F]>([&](auto cc) {
+                constexpr int C = decltype(cc)::value;
+                if constexpr (kLayouts[L].sub[F][C] == S) *(uint8_t *)base = (uint8_t)v[word_of(F, C)];
+            });
+        });
+    } else {
+        constexpr int G = load_width(R, 0);
+        uint32_t w[R / 4];
+        static_for<0, R / 4>([&](auto kc) { w[decltype(kc)::value] = 0u; });
+        static_for<0, NFIELD>([&](auto fc) {
+            constexpr int F = decltype(fc)::value;
+            static_for<0, kNComp[F]>([&](auto cc) {
+                constexpr int C = decltype(cc)::value;
+                if constexpr (kLayouts[L].sub[F][C] == S) {
+                    constexpr int off = kLayouts[L].off[F][C], k = word_of(F, C);
+                    if constexpr (kCompBytes[F] == 8) {
+                        w[off / 4] = v[k];
+                        w[off / 4 + 1] = v[k + 1];
+                    } else if constexpr (kCompBytes[F] == 4) {
+                        w[off / 4] = v[k];
+                    } else {
+                        w[off / 4] |= (v[k] & 0xFFu) << (8 * (off % 4));
+                    }
+                }
+            });
+        });
+        static_for<0, R / G>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            if constexpr (G == 16)
+                *(uint4 *)(base + 16 * k) = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+            else if constexpr (G == 8)
+                *(uint2 *)(base + 8 * k) = make_uint2(w[2 * k], w[2 * k + 1]);
+            else
+                *(uint32_t *)(base + 4 * k) = w[k];
+        });
+    }
+}
+
+// one thread per particle: every source record read once, every destination
+// record written once
+template <int LS, int LD>
+__global__ __launch_bounds__(256) void k_convert(StoreArg src, StoreArg dst, int64_t n)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint32_t v[kParticleWords];
+    static_for<0, kLayouts[LS].nsub>([&](auto sc) { read_record<LS, decltype(sc)::value>(src, p, v); });
+    static_for<0, kLayouts[LD].nsub>([&](auto sc) { write_record<LD, decltype(sc)::value>(dst, p, v); });
+}
+
+template <int LS, int LD>
+static sph_status convert_ll(const StoreArg &src, const StoreArg &dst, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_convert<LS, LD>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
+    SPH_CHECK_LAUNCH("convert launch");
+    return SPH_OK;
+}
+
+template <int LS>
+static sph_status convert_l(int ld, const StoreArg &src, const StoreArg &dst, int64_t n, hipStream_t st)
+{
+    switch (ld) {
+    case 0: return convert_ll<LS, 0>(src, dst, n, st);
+    case 1: return convert_ll<LS, 1>(src, dst, n, st);
+    case 2: return convert_ll<LS, 2>(src, dst, n, st);
+    case 3: return convert_ll<LS, 3>(src, dst, n, st);
+    case 4: return convert_ll<LS, 4>(src, dst, n, st);
+    case 5: return convert_ll<LS, 5>(src, dst, n, st);
+    case 6: return convert_ll<LS, 6>(src, dst, n, st);
+    case 7: return convert_ll<LS, 7>(src, dst, n, st);
+    case 8: return convert_ll<LS, 8>(src, dst, n, st);
+    default: return fail(SPH_E_LAYOUT, "unknown layout");
+    }
+}
+
 #define SPH_BY_LAYOUT(layout, fn, ...)                                              \
     switch (layout) {                                                               \
     case 0: return fn<0>(__VA_ARGS__); case 1: return fn<1>(__VA_ARGS__);            \
@@ -602,6 +758,13 @@ sph_status launch_unpack(sph_plan *p, int loop, const void *res, bool cells, int
     }
     if (a.nchunk == 0) return SPH_OK;
     SPH_BY_LAYOUT(s->layout, unpack_l, loop, a, cells, csr, waves, schedule, st);
+}
+
+sph_status launch_convert(const sph_store *src, const sph_store *dst, hipStream_t st)
+{
+    if (src->n == 0) return SPH_OK;
+    const StoreArg a = store_arg(src), b = store_arg(dst);
+    SPH_BY_LAYOUT(src->layout, convert_l, dst->layout, a, b, src->n, st);
 }
 
 }  // namespace sph

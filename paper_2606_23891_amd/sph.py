@@ -70,6 +70,7 @@ _SIGS = {
                             C.POINTER(C.c_uint32)], i32),
     "sph_store_put": ([vp, i32, vp, vp], i32),
     "sph_store_get": ([vp, i32, vp, vp], i32),
+    "sph_store_convert": ([vp, vp, vp], i32),
     "sph_plan_create": ([vp, i32, vp, i32, i64, C.POINTER(vp)], i32),
     "sph_plan_destroy": ([vp], None),
     "sph_plan_get_info": ([vp, vp], i32),
@@ -303,6 +304,11 @@ def sph_store_put(store, field: int, src, stream=None):
 
 def sph_store_get(store, field: int, dst, stream=None):
     _check(lib().sph_store_get(_s(store), field, _ptr(dst), _stream(stream)), "sph_store_get")
+
+
+def sph_store_convert(src, dst, stream=None):
+    """every member of every particle of src into dst (another layout's store)"""
+    _check(lib().sph_store_convert(_s(src), _s(dst), _stream(stream)), "sph_store_convert")
 
 
 def sph_plan_create(cells: np.ndarray, tasks: np.ndarray, n: int):

@@ -151,6 +151,16 @@ def test_validation_errors_before_any_launch():
     st.sub[0] = 0x1001  # misaligned
     assert L.sph_store_put(C.byref(st), 0, C.c_void_p(256), None) == -1
     assert b"aligned" in L.sph_last_error()
+    # conversion: counts must agree and the stores must not overlap
+    st.sub[0] = 0x10000
+    other = sph.sph_store()
+    other.layout, other.nsub, other.n = 0, 1, 11
+    other.sub[0] = 0x20000
+    assert L.sph_store_convert(C.byref(st), C.byref(other), None) == -1
+    assert b"different particle counts" in L.sph_last_error()
+    other.n, other.sub[0] = 10, 0x10000 + 0x500   # inside st's 1600 bytes
+    assert L.sph_store_convert(C.byref(st), C.byref(other), None) == -1
+    assert b"overlaps" in L.sph_last_error()
 
 
 def test_library_shares_torchs_hip_runtime():

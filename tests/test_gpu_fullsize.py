@@ -14,7 +14,7 @@ from gpuhelp import LOOP_OUT, compare_loop, device_store, log, oracle_loop, outp
 pytestmark = pytest.mark.gpu
 
 
-def _run(k, nrows, layout):
+def _run(k, nrows, layout, convert_to=None):
     log(f"building workload {k}")
     ps = inputs.make_config(k)
     log(f"n={ps.n} cells={len(ps.cells)} tasks={len(ps.tasks)} {inputs.cell_stats(ps.cells)}")
@@ -44,11 +44,18 @@ def _run(k, nrows, layout):
         assert np.all(dc <= ref["band"]), (loop, int(dc.max()))
         for kk in LOOP_OUT[loop]:
             prev[kk] = g[kk].astype(np.float64)
+    if convert_to is not None:
+        # the whole store, outputs included, rewritten into another layout
+        log(f"convert {sph.LAYOUTS[layout]} -> {sph.LAYOUTS[convert_to]} n={ps.n}")
+        dst = sph.Store(convert_to, ps.n)
+        sph.sph_store_convert(st, dst)
+        for name in sph.FIELDS:
+            assert st.get(name).tobytes() == dst.get(name).tobytes(), name
     plan.close()
 
 
 def test_gresho256_sampled():
-    _run(2, 96, sph.LAYOUTS.index("SAOS_SHARED"))
+    _run(2, 96, sph.LAYOUTS.index("SAOS_SHARED"), convert_to=sph.LAYOUTS.index("SOA"))
 
 
 def test_clustered188_sampled():

@@ -202,6 +202,40 @@ def test_fission_step_matches_fused_step():
     plan.close()
 
 
+def test_store_convert_bitexact():
+    """converting a store between any two layouts (the same one included)
+    leaves the destination byte for byte as the oracle's store of the same
+    fields: every member copied, padding zero whatever was there before"""
+    import torch
+    n = 1000  # ragged: neither a multiple of the 256-thread block nor of 64
+    x = inputs.random_fields(n, 29)["x"]
+    f = inputs.random_fields(n, 31, x=x)
+    refs = {}
+    for ld in range(9):
+        host = oracle.HostStore(ld, n, fill=0)
+        host.put_all(f)
+        refs[ld] = host.raw()
+    for ls in range(9):
+        src = sph.Store(ls, n)
+        for t in src.subs:
+            t.fill_(0x5A)
+        src.put_all(f)
+        for ld in range(9):
+            log(f"convert {sph.LAYOUTS[ls]} -> {sph.LAYOUTS[ld]} n={n}")
+            dst = sph.Store(ld, n)
+            for t in dst.subs:
+                t.fill_(0xA5)
+            sph.sph_store_convert(src, dst)
+            torch.cuda.synchronize()
+            assert dst.raw() == refs[ld], (ls, ld)
+    # refused: different counts, overlapping stores
+    small = sph.Store(0, n - 1)
+    with pytest.raises(sph.SphError):
+        sph.sph_store_convert(src, small)
+    with pytest.raises(sph.SphError):
+        sph.sph_store_convert(src, src)
+
+
 def _check_loops(ps, layout, mode, rows=None, bundle=1):
     """density -> gradient -> force on the GPU; each loop compared with the oracle
     fed the GPU's own previous-loop outputs (loop isolation)."""
