@@ -86,10 +86,13 @@ def stage_kernels(stage, layout, tuning):
     """the kernels a batched stage launches (demangled names; the queue reset
     of the interaction stages, a one-thread kernel, is left out)"""
     for L, nm in LOOP_NAME.items():
+        split = getattr(tuning, "pack_schedule", 0) != 0
         if stage == f"pack_{nm}":
+            if split:
+                return [f"void sph::k_pack_pass<{layout}, {L}>(sph::PackArgs, unsigned int)"]
             return [f"void sph::k_pack<{layout}, {L}>(sph::PackArgs)"]
         if stage == f"unpack_{nm}":
-            return [f"void sph::k_unpack_chunks<{layout}, {L}, true>(sph::UnpackArgs)"]
+            return [f"void sph::k_unpack_chunks<{layout}, {L}, true, {'true' if split else 'false'}>(sph::UnpackArgs)"]
         if stage == nm:
             k = [f"void sph::k_interact<{L}, 1, {tuning.window[L]}, false>(sph::InteractArgs)"]
             return ([f"void sph::k_prep<{L}>(sph::PrepArgs)"] if L >= 1 else []) + k
