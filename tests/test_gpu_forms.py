@@ -189,4 +189,15 @@ def test_offload_async_matches_offload_step(layout):
     sph.sph_offload_step_async(plan, host, dev, ws, nbundle=8)
     torch.cuda.synchronize()
     assert host.raw() == host_ref.raw()
+    # bundle packs and unpacks split by a loop-fission schedule
+    for sched in (2, 4):
+        log(f"offload async {layout} bundles=3 schedule={sched}")
+        tn = sph.default_tuning()
+        tn.pack_schedule = sched
+        host_s = _filled_host_store(lay, f, ps.n)
+        dev_s = sph.Store(lay, ps.n)
+        sph.sph_offload_step_async(plan, host_s, dev_s, ws, nbundle=3, tuning=tn)
+        torch.cuda.synchronize()
+        assert host_s.raw() == ref_h, sched
+        assert dev_s.raw() == ref_d, sched
     plan.close()
