@@ -163,6 +163,59 @@ def balsara(h, u, rho, D, R, alpha_v, gamma=GAMMA_AD, eps=BALSARA_EPS) -> np.nda
     return out
 
 
+GAMMA_K = np.sqrt(10.0 / 3.0)   # support H over smoothing length h (cubic spline)
+
+
+def h_newton_step(h, m, rho, rho_dh, cell_width, eta, tol):
+    """One smoothing-length update per particle, in FP64 (h itself is a float32
+    field).  Root sought: f(h) = rho(h) h^3 - m eta^3 = 0, i.e. h = eta (m /
+    rho)^(1/3).  Newton: dh = -f / f' with f' = h^3 rho' + 3 h^2 rho, which is
+    dh = -h (rho - n) / (3 rho + h rho') for n = m eta^3 / h^3; where that
+    denominator is not positive, the fixed-point step to eta (m / rho)^(1/3).
+    |dh| <= tol h: converged, h kept.  Otherwise h + dh clipped to [h/2, 2h] and
+    to gamma_K h <= the cell width.  Returns (new h as float32, moved mask)."""
+    h64 = np.asarray(h, np.float64)
+    rho = np.asarray(rho, np.float64)
+    n = np.asarray(m, np.float64) * eta ** 3 / h64 ** 3
+    den = 3.0 * rho + h64 * np.asarray(rho_dh, np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        newton = -h64 * (rho - n) / den
+    fixed = h64 * (np.cbrt(n / rho) - 1.0)
+    dh = np.where(den > 0.0, newton, fixed)
+    conv = np.abs(dh) <= tol * h64
+    hn = np.minimum(np.clip(h64 + dh, 0.5 * h64, 2.0 * h64), np.asarray(cell_width, np.float64) / GAMMA_K)
+    hn32 = hn.astype(np.float32)
+    moved = ~conv & (hn32 != np.asarray(h, np.float32))
+    out = np.asarray(h, np.float32).copy()
+    out[moved] = hn32[moved]
+    return out, moved
+
+
+def h_iterate(x, m, h, cell_width, eta=1.2348, tol=1e-4, max_iter=30) -> Dict[str, np.ndarray]:
+    """The smoothing-length iteration: the FP64 brute-force density of the
+    particles whose h moved (all on the first pass), then one h_newton_step
+    for them, until none moves or max_iter passes.  Returns the final h, the
+    density outputs belonging to it, the passes run and the particles that
+    still moved in the last pass."""
+    h = np.asarray(h, np.float32).copy()
+    n = h.size
+    width = np.asarray(cell_width, np.float64)
+    rho, rdh, wc = np.zeros(n), np.zeros(n), np.zeros(n)
+    rows = np.arange(n)
+    passes, still = 0, 0
+    for _ in range(max_iter):
+        d = density(x, m, h, rows=rows)
+        rho[rows], rdh[rows], wc[rows] = d["rho"], d["rho_dh"], d["wcount"]
+        hn, moved = h_newton_step(h[rows], np.asarray(m)[rows], rho[rows], rdh[rows], width[rows], eta, tol)
+        h[rows] = hn
+        passes += 1
+        still = int(moved.sum())
+        rows = rows[moved]
+        if still == 0:
+            break
+    return {"h": h, "rho": rho, "rho_dh": rdh, "wcount": wc, "passes": passes, "unconverged": still}
+
+
 def pack_resolution(cells) -> np.ndarray:
     """Per-particle position resolution of the packed FP32 offsets: 2^-22 times
     the width of the particle's cell (offsets span at most a few cell widths and

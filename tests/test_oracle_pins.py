@@ -403,3 +403,67 @@ def test_unpack_reduces_in_task_order():
     res[5, :5] = [3.0, -1.0, -2.0, 5.0, 0.5]
     oracle.unpack(st, 1, cells, tasks, 0, 3, res)
     assert list(st.get("v_sig")) == [3.0, 5.0, 0.5]
+
+
+# --------------------------------------------------------------------------
+# smoothing-length iteration
+# --------------------------------------------------------------------------
+def test_h_newton_step_branches():
+    """Newton on f(h) = rho h^3 - m eta^3: with a density independent of h the
+    root is eta (m / rho)^(1/3) exactly and Newton reaches it from either side;
+    a non-positive denominator takes the fixed-point step to that root in one
+    move; steps within tol h keep h; the cell caps gamma_K h"""
+    m, eta, rho = 1.0, 1.0, 1.728                     # root h* = 1 / 1.2
+    root = eta * (m / rho) ** (1.0 / 3.0)
+    for h0 in (0.6, 1.5):
+        h = np.array([h0], np.float32)
+        for _ in range(20):
+            h, moved = oracle.h_newton_step(h, [m], [rho], [0.0], [100.0], eta, 1e-6)
+            if not moved.any():
+                break
+        assert not moved.any()
+        assert abs(float(h[0]) - root) <= 2e-6 * root
+    # the denominator 3 rho + h rho' <= 0: fixed point, one step
+    h, moved = oracle.h_newton_step(np.array([1.0], np.float32), [m], [rho], [-10.0 * rho], [100.0], eta, 1e-6)
+    assert moved[0] and float(h[0]) == pytest.approx(root, rel=1e-7)
+    # converged: the step is within tol h
+    h1 = np.array([root], np.float32)
+    h, moved = oracle.h_newton_step(h1, [m], [rho], [0.0], [100.0], eta, 1e-5)
+    assert not moved[0] and h[0] == h1[0]
+    # limits: at most 2h per step, and gamma_K h at most the cell width
+    h, _ = oracle.h_newton_step(np.array([0.1], np.float32), [m], [rho], [0.0], [100.0], eta, 1e-6)
+    assert float(h[0]) == pytest.approx(0.2, rel=1e-7)
+    h, _ = oracle.h_newton_step(np.array([0.6], np.float32), [m], [rho], [0.0], [1.0], eta, 1e-6)
+    assert float(h[0]) == pytest.approx(1.0 / oracle.GAMMA_K, rel=1e-7)
+
+
+@pytest.mark.parametrize("start", [0.8, 1.3])
+def test_h_iteration_fixed_point_perfect_lattice(start):
+    """On a perfect lattice every particle's density is the same shell sum, so
+    the iteration must land every h on the root of s(h) h^3 = eta^3 (masses
+    cancel), found here by bisection on the shell sum alone"""
+    ns = 8
+    f = inputs.lattice_set(ns, seed=1, jitter=0.0)
+    delta = 1.0 / ns
+    gk = oracle.lib().or_gamma_k()
+    eta = inputs.ETA
+
+    def g(hh):
+        s, _ = _shell_sum(delta, hh, lambda t: gk * t)
+        return s * hh ** 3 - eta ** 3   # rho = m s(h): rho h^3 = m eta^3
+
+    lo, hi = 0.9 * eta * delta, 1.1 * eta * delta
+    assert g(lo) < 0.0 < g(hi)
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if g(mid) < 0.0 else (lo, mid)
+    h_star = 0.5 * (lo + hi)
+    assert abs(h_star / (eta * delta) - 1.0) < 0.01     # the lattice density is within 1 % of m / delta^3
+    h0 = np.full(ns ** 3, np.float32(start * eta * delta))
+    out = oracle.h_iterate(f["x"], f["mass"], h0, np.full(ns ** 3, 0.5), eta=eta, tol=1e-6)
+    assert out["unconverged"] == 0 and 2 <= out["passes"] <= 10
+    assert np.all(out["h"] == out["h"][0])
+    assert abs(float(out["h"][0]) - h_star) <= 2e-6 * h_star
+    # the densities returned belong to the final h
+    d = oracle.density(f["x"], f["mass"], out["h"])
+    np.testing.assert_array_equal(d["rho"], out["rho"])
