@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--fission", default=None,
                     help="'all' or comma list of layouts: also time pack + unpack under every "
                          "loop-fission schedule")
+    ap.add_argument("--hiter", action="store_true",
+                    help="also time the smoothing-length iteration from h perturbed by up to 10 %%")
     ap.add_argument("--convert", default=None,
                     help="'default' or comma list of SRC:DST layouts: also time whole-store layout "
                          "conversions")
@@ -349,6 +351,9 @@ def main():
         names = sph.LAYOUTS if a.fission == "all" else a.fission.split(",")
         out["fission"] = fission_sweep(ps, plan, names, tuning, a.steps)
 
+    if a.hiter:
+        out["h_iteration"] = hiter_bench(ps, plan, tuning, a.layout)
+
     if a.convert:
         pairs = CONVERT_PAIRS if a.convert == "default" else [tuple(x.split(":")) for x in a.convert.split(",")]
         out["convert"] = convert_sweep(ps, pairs, a.steps)
@@ -452,6 +457,36 @@ def fission_sweep(ps, plan, names, tuning, steps):
             res[name][sname]["vs_by_particle"] = round(res[name][sname]["total_ms"] / base, 4)
         del st
         torch.cuda.empty_cache()
+    return res
+
+
+def hiter_bench(ps, plan, tuning, layout_name, eta=1.2348, tol=1e-4):
+    """the smoothing-length iteration on the workload, every h first scaled by a
+    seeded factor in [0.9, 1.1]: passes, particles left moving, wall time"""
+    import time
+
+    import numpy as np
+    import torch
+
+    from paper_2606_23891_amd import sph
+
+    st = sph.Store(sph.LAYOUTS.index(layout_name), ps.n)
+    st.put_all(ps.fields)
+    h0 = (ps.fields["h"] * np.random.default_rng(17).uniform(0.9, 1.1, ps.n)).astype(np.float32)
+    ws = torch.empty(sph.sph_h_iterate_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    res = {}
+    for rep in range(2):   # the first call warms up
+        st.put("h", h0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        passes, still = sph.sph_h_iterate(plan, st, ws, eta=eta, tol=tol, max_iter=30, tuning=tuning)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        res = {"passes": passes, "unconverged": still, "ms": round(ms, 3), "ms_per_pass": round(ms / passes, 3),
+               "eta": eta, "tol": tol, "start": "h x U(0.9, 1.1), seed 17"}
+    log(f"h iteration: {res['passes']} passes, {res['unconverged']} unconverged, {res['ms']:.2f} ms")
+    del st, ws
+    torch.cuda.empty_cache()
     return res
 
 

@@ -313,6 +313,26 @@ sph_status sph_unpack_cells(const sph_plan *plan, sph_loop loop, const void *res
 /* density -> gradient -> force, each pack -> interact -> unpack. */
 sph_status sph_step_batched(const sph_plan *plan, const sph_store *store, const sph_params *params,
                             const sph_tuning *tuning, void *ws, size_t ws_bytes, void *stream);
+/* Smoothing-length iteration: the per-particle update between the density
+ * and gradient loops (Sec. 2.1's linear kernels) that makes every h
+ * consistent with its density, rho(h) h^3 = m eta^3 (h = eta (m/rho)^(1/3);
+ * eta = 1.2348 gives about 48 neighbours for the cubic spline).  Each pass
+ * runs the density loop (batched form; after the first pass only over the
+ * tiles holding a particle that moved), then one Newton step per particle on
+ * f(h) = rho h^3 - m eta^3 using the density and its h-derivative rho_dh: a
+ * particle whose step is at most tol h keeps its h and the density computed
+ * with it; any other moves to h + dh, limited to [h/2, 2h] and to a support
+ * gamma_K h no wider than its own cell.  Stops when no particle moved or after
+ * max_iter passes; *iterations receives the passes run and *unconverged the
+ * particles that still moved in the last one (their density belongs to their
+ * previous h).  The store's h, rho, rho_dh and wcount are updated in place.
+ * Synchronises `stream` once per pass (the host reads the count); not
+ * capturable.  ws: device memory of sph_h_iterate_ws_bytes bytes, 256-byte
+ * aligned, owned by the caller.  iterations / unconverged may be null. */
+sph_status sph_h_iterate_ws_bytes(const sph_plan *plan, size_t *bytes);
+sph_status sph_h_iterate(const sph_plan *plan, const sph_store *store, const sph_params *params,
+                         const sph_tuning *tuning, float eta, float tol, int32_t max_iter, void *ws,
+                         size_t ws_bytes, int32_t *iterations, int64_t *unconverged, void *stream);
 /* Capture sph_step_batched into an executable HIP graph (*graph_exec). */
 sph_status sph_graph_capture(const sph_plan *plan, const sph_store *store, const sph_params *params,
                              const sph_tuning *tuning, void *ws, size_t ws_bytes, void **graph_exec);

@@ -847,6 +847,77 @@ static sph_status step_batched(const sph_plan *p, const sph_store *store, const 
     return SPH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// smoothing-length iteration
+// ---------------------------------------------------------------------------
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// workspace: interaction workspace, pack and result buffers of the density
+// loop, tile flags, tile work list, per-256-tile counts, two counters
+static size_t h_iter_ws_bytes_for(const sph_plan *p)
+{
+    return interact_ws_bytes_for(0, p->n) + align256(pack_bytes_for(0, p->n, p->ntile)) +
+           align256(result_bytes_for(0, p->n)) + 2 * align256((size_t)p->ntile * 4) +
+           align256(((size_t)p->ntile + 255) / 256 * 8) + 256;
+}
+
+sph_status sph_h_iterate_ws_bytes(const sph_plan *p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(SPH_E_ARG, "null argument");
+    *bytes = h_iter_ws_bytes_for(p);
+    return SPH_OK;
+}
+
+sph_status sph_h_iterate(const sph_plan *p, const sph_store *store, const sph_params *prm, const sph_tuning *tn,
+                         float eta, float tol, int32_t max_iter, void *ws, size_t ws_bytes, int32_t *iterations,
+                         int64_t *unconverged, void *stream)
+{
+    sph_status s;
+    if ((s = batched_checks(p, 0)) || (s = check_store(store)) || (s = check_tuning(tn))) return s;
+    if (!prm) return fail(SPH_E_ARG, "params is null");
+    if (store->n != p->n) return fail(SPH_E_ARG, "store size differs from the plan's");
+    if (!(eta > 0.0f) || !(tol > 0.0f) || max_iter < 1)
+        return fail(SPH_E_ARG, "eta and tol must be positive and max_iter at least 1");
+    if (!ws || !aligned256(ws)) return fail(SPH_E_ARG, "workspace null or misaligned");
+    if (ws_bytes < h_iter_ws_bytes_for(p))
+        return fail(SPH_E_CAPACITY, "workspace needs " + std::to_string(h_iter_ws_bytes_for(p)) + " bytes");
+    if (iterations) *iterations = 0;
+    if (unconverged) *unconverged = 0;
+    if (p->n == 0) return SPH_OK;
+    sph_tuning def;
+    sph_tuning_default(&def);
+    if (!tn) tn = &def;
+    const hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)ws;
+    void *q = base;
+    char *pack = base + interact_ws_bytes_for(0, p->n);
+    char *res = pack + align256(pack_bytes_for(0, p->n, p->ntile));
+    int32_t *flags = (int32_t *)(res + align256(result_bytes_for(0, p->n)));
+    int32_t *items = (int32_t *)((char *)flags + align256((size_t)p->ntile * 4));
+    int32_t *blk = (int32_t *)((char *)items + align256((size_t)p->ntile * 4));
+    int32_t *cnt = (int32_t *)((char *)blk + align256(((size_t)p->ntile + 255) / 256 * 8));  // [0] moved, [1] tiles
+    int64_t nitems = -1;  // the first pass runs every tile
+    int32_t host_cnt[2] = {0, 0};
+    for (int it = 0; it < max_iter; ++it) {
+        if ((s = launch_pack(p, 0, store, true, 0, 0, pack, tn->pack_waves, st, tn->pack_schedule))) return s;
+        if ((s = launch_interact(p, 0, true, 0, p->ntask, pack, prm, tn, res, nullptr, q, st,
+                                 nitems < 0 ? nullptr : items, nitems)))
+            return s;
+        if ((s = launch_unpack(const_cast<sph_plan *>(p), 0, res, true, 0, 0, store, tn->pack_waves, st,
+                               tn->pack_schedule)))
+            return s;
+        if ((s = launch_h_newton(p, store, eta, tol, flags, st))) return s;
+        if ((s = launch_flagged_tiles(p, flags, items, blk, cnt, st))) return s;
+        SPH_HIP(hipMemcpyAsync(host_cnt, cnt, sizeof(host_cnt), hipMemcpyDeviceToHost, st));
+        SPH_HIP(hipStreamSynchronize(st));
+        if (iterations) *iterations = it + 1;
+        if (unconverged) *unconverged = host_cnt[0];
+        if (host_cnt[0] == 0) break;
+        nitems = host_cnt[1];
+    }
+    return SPH_OK;
+}
+
 sph_status sph_step_batched(const sph_plan *p, const sph_store *store, const sph_params *prm,
                             const sph_tuning *tn, void *ws, size_t ws_bytes, void *stream)
 {

@@ -1052,7 +1052,7 @@ static sph_status launch_win(const InteractArgs &a, int win, unsigned grid, hipS
 
 sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, int32_t t1, const void *pack,
                            const sph_params *prm, const sph_tuning *tn, void *res, int32_t *counts, void *ws,
-                           hipStream_t st)
+                           hipStream_t st, const int32_t *items, int64_t nitems)
 {
     InteractArgs a{};
     a.pack = (const char *)pack;
@@ -1093,6 +1093,18 @@ sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, 
         a.bounds = (const float4 *)(a.pack + a.P * 4 * kPackFloats[loop]);
         a.queue = (int32_t *)ws;
         a.use_queue = tn->queue;
+        if (items) {
+            // a subset of the tiles in plan order: eight contiguous shares of
+            // equal length, one per XCD queue, as for the full list
+            a.items = items;
+            a.items_x = items;
+            a.nitems = nitems;
+            for (int q = 0; q < kQueues; ++q) {
+                a.xoff[q] = (int32_t)(nitems * q / kQueues);
+                a.xlen[q] = (int32_t)(nitems * (q + 1) / kQueues) - a.xoff[q];
+            }
+            a.use_queue = 2;
+        }
         if (a.nitems == 0) return SPH_OK;
         // blocks_per_cu counts groups of four waves; a loop may set its own
         const int bpc = tn->blocks_per_loop[loop] > 0 ? tn->blocks_per_loop[loop] : tn->blocks_per_cu;

@@ -213,6 +213,14 @@ sph_status launch_unpack(sph_plan *p, int loop, const void *res, bool cells, int
                          const sph_store *s, int waves, hipStream_t st, int schedule = 0);
 // every member of every particle of src into dst (checked stores, same n)
 sph_status launch_convert(const sph_store *src, const sph_store *dst, hipStream_t st);
+// one Newton step of the smoothing-length iteration over every tile (flags[t]
+// = the tile's moved particles), and the flagged tiles as a work list
+sph_status launch_h_newton(const sph_plan *p, const sph_store *s, float eta, float tol, int32_t *flags,
+                           hipStream_t st);
+// blk: scratch of two int32 per 256 tiles; count[0] = moved particles,
+// count[1] = flagged tiles
+sph_status launch_flagged_tiles(const sph_plan *p, const int32_t *flags, int32_t *items, int32_t *blk,
+                                int32_t *count, hipStream_t st);
 // the fission groups of a layout's pack (unpack) members: bit masks as in
 // sph_fission_passes, returned count (0 for an unknown layout)
 int fission_passes(int layout, int loop, int schedule, bool unpack, uint32_t *masks);
@@ -223,8 +231,11 @@ sph_status launch_pack_tiles(const sph_plan *p, int loop, const sph_store *s, in
                              void *buf, int waves, hipStream_t st, int schedule = 0);
 sph_status launch_unpack_tiles(const sph_plan *p, int loop, const void *res, int32_t tile0, int32_t tile1,
                                const sph_store *s, int waves, hipStream_t st, int schedule = 0);
+// items / nitems (batched form only): run these tiles (ascending tile order)
+// instead of the plan's full list, split into per-XCD shares
 sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, int32_t t1,
                            const void *pack, const sph_params *prm, const sph_tuning *tn, void *res,
-                           int32_t *counts, void *ws, hipStream_t st);
+                           int32_t *counts, void *ws, hipStream_t st, const int32_t *items = nullptr,
+                           int64_t nitems = -1);
 
 }  // namespace sph

@@ -658,6 +658,148 @@ static sph_status convert_l(int ld, const StoreArg &src, const StoreArg &dst, in
     }
 }
 
+// ---------------------------------------------------------------------------
+// smoothing-length iteration: Newton steps on rho(h) h^3 = m eta^3 between
+// density passes (the per-particle update between the density and gradient
+// loops)
+// ---------------------------------------------------------------------------
+struct HIterArgs {
+    StoreArg store;
+    const Chunk *tiles;
+    const sph_cell *cells;
+    int64_t ntile;
+    float eta3;        // eta^3
+    float tol;         // converged when |dh| <= tol h
+    int32_t *flags;    // per tile: the tile's particles moved by this step
+};
+
+// One wave per tile.  With f(h) = rho h^3 - m eta^3 and f' = h^3 rho' + 3 h^2
+// rho, the Newton step is dh = -h (rho - n) / (3 rho + h rho'), n = m eta^3 /
+// h^3 the density at which h would be consistent; where the denominator is
+// not positive the step is the fixed-point one, h eta-scaled to the current
+// density.  A particle whose step is within tol h keeps its h (and with it the
+// density just computed); any other takes h + dh limited to [h/2, 2h] and to
+// a support no wider than its cell.
+template <int L>
+__global__ __launch_bounds__(256) void k_h_newton(HIterArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t c = __builtin_amdgcn_readfirstlane((int)((int64_t)blockIdx.x * (blockDim.x >> 6) +
+                                                           (threadIdx.x >> 6)));
+    if (c >= a.ntile) return;
+    const Chunk ch = a.tiles[c];
+    bool moved = false;
+    if (lane < ch.n) {
+        const int64_t p = ch.part0 + lane;
+        const float h = ld<L, FH, 0, float>(a.store, p);
+        const float m = ld<L, FMASS, 0, float>(a.store, p);
+        const float rho = ld<L, FRHO, 0, float>(a.store, p);
+        const float drho = ld<L, FRHODH, 0, float>(a.store, p);
+        const float n = m * a.eta3 / (h * h * h);
+        const float den = 3.0f * rho + h * drho;
+        const float dh = den > 0.0f ? -h * (rho - n) / den : h * (cbrtf(n / rho) - 1.0f);
+        if (!(fabsf(dh) <= a.tol * h)) {
+            const float hcap = (float)(a.cells[ch.cell].width / (double)kGammaK);
+            float hn = fminf(fmaxf(h + dh, 0.5f * h), 2.0f * h);
+            hn = fminf(hn, hcap);
+            if (hn != h) {
+                st<L, FH, 0, float>(a.store, p, hn);
+                moved = true;
+            }
+        }
+    }
+    const uint64_t bal = __ballot(moved);
+    if (lane == 0) a.flags[c] = (int32_t)__popcll(bal);
+}
+
+// the tiles flagged by the last step as a work list in ascending tile order
+// (the plan's spatial order), by an ordered compaction: per-block counts of
+// flagged tiles and of moved particles, one block's scan of them, then every
+// block writes its flagged tiles at its offset (no atomics: a same-address
+// atomic per tile serialises in L2)
+__device__ __forceinline__ int32_t wave_sum_i(int32_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_flag_counts(const int32_t *flags, int64_t ntile, int32_t *blk,
+                                                     int32_t *blk_moved)
+{
+    __shared__ int32_t ws[4], wm[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t mv = t < ntile ? flags[t] : 0;
+    const uint64_t bal = __ballot(mv != 0);
+    const int32_t sm = wave_sum_i(mv);
+    if (lane == 0) {
+        ws[wv] = (int32_t)__popcll(bal);
+        wm[wv] = sm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        blk[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+        blk_moved[blockIdx.x] = wm[0] + wm[1] + wm[2] + wm[3];
+    }
+}
+
+// exclusive scan of nblk tile counts in place by one block of 256 threads,
+// 256 counts per round with the running total carried; count[0] = moved
+// particles (sum of blk_moved), count[1] = flagged tiles
+__global__ __launch_bounds__(256) void k_scan_counts(int32_t *blk, const int32_t *blk_moved, int64_t nblk,
+                                                     int32_t *count)
+{
+    __shared__ int32_t sh[256];
+    __shared__ int32_t wm[4];
+    int32_t carry = 0, moved = 0;
+    for (int64_t b0 = 0; b0 < nblk; b0 += 256) {
+        const int64_t i = b0 + threadIdx.x;
+        const int32_t v = i < nblk ? blk[i] : 0;
+        const int32_t mvs = wave_sum_i(i < nblk ? blk_moved[i] : 0);
+        if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = mvs;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        moved += wm[0] + wm[1] + wm[2] + wm[3];
+        for (int off = 1; off < 256; off <<= 1) {
+            const int32_t add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < nblk) blk[i] = carry + sh[threadIdx.x] - v;
+        carry += sh[255];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        count[0] = moved;
+        count[1] = carry;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_flag_scatter(const int32_t *flags, int64_t ntile, const int32_t *blk,
+                                                      int32_t *items)
+{
+    __shared__ int32_t ws[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool f = t < ntile && flags[t] != 0;
+    const uint64_t bal = __ballot(f);
+    if (lane == 0) ws[wv] = (int32_t)__popcll(bal);
+    __syncthreads();
+    int32_t off = blk[blockIdx.x];
+    for (int k = 0; k < wv; ++k) off += ws[k];
+    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    if (f) items[off + rank] = (int32_t)t;
+}
+
+template <int L>
+static sph_status h_newton_l(const HIterArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_h_newton<L>), dim3((unsigned)((a.ntile + 3) / 4)), dim3(256), 0, st, a);
+    SPH_CHECK_LAUNCH("smoothing-length step launch");
+    return SPH_OK;
+}
+
 #define SPH_BY_LAYOUT(layout, fn, ...)                                              \
     switch (layout) {                                                               \
     case 0: return fn<0>(__VA_ARGS__); case 1: return fn<1>(__VA_ARGS__);            \
@@ -765,6 +907,35 @@ sph_status launch_convert(const sph_store *src, const sph_store *dst, hipStream_
     if (src->n == 0) return SPH_OK;
     const StoreArg a = store_arg(src), b = store_arg(dst);
     SPH_BY_LAYOUT(src->layout, convert_l, dst->layout, a, b, src->n, st);
+}
+
+sph_status launch_h_newton(const sph_plan *p, const sph_store *s, float eta, float tol, int32_t *flags,
+                           hipStream_t st)
+{
+    HIterArgs a{};
+    a.store = store_arg(s);
+    a.tiles = p->d_tiles;
+    a.cells = p->d_cells;
+    a.ntile = p->ntile;
+    a.eta3 = eta * eta * eta;
+    a.tol = tol;
+    a.flags = flags;
+    if (a.ntile == 0) return SPH_OK;
+    SPH_BY_LAYOUT(s->layout, h_newton_l, a, st);
+}
+
+sph_status launch_flagged_tiles(const sph_plan *p, const int32_t *flags, int32_t *items, int32_t *blk,
+                                int32_t *count, hipStream_t st)
+{
+    if (p->ntile == 0) return SPH_OK;
+    const int64_t nblk = ((int64_t)p->ntile + 255) / 256;
+    int32_t *blk_moved = blk + nblk;
+    hipLaunchKernelGGL(k_flag_counts, dim3((unsigned)nblk), dim3(256), 0, st, flags, (int64_t)p->ntile, blk,
+                       blk_moved);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, st, blk, (const int32_t *)blk_moved, nblk, count);
+    hipLaunchKernelGGL(k_flag_scatter, dim3((unsigned)nblk), dim3(256), 0, st, flags, (int64_t)p->ntile, blk, items);
+    SPH_CHECK_LAUNCH("tile list launch");
+    return SPH_OK;
 }
 
 }  // namespace sph

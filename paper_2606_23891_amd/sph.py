@@ -90,6 +90,9 @@ _SIGS = {
     "sph_interact_cells": ([vp, i32, vp, sz, vp, vp, vp, sz, vp, vp, sz, vp], i32),
     "sph_unpack_cells": ([vp, i32, vp, sz, vp, vp, vp], i32),
     "sph_step_batched": ([vp, vp, vp, vp, vp, sz, vp], i32),
+    "sph_h_iterate_ws_bytes": ([vp, C.POINTER(sz)], i32),
+    "sph_h_iterate": ([vp, vp, vp, vp, C.c_float, C.c_float, i32, vp, sz, C.POINTER(i32), C.POINTER(i64), vp],
+                      i32),
     "sph_graph_capture": ([vp, vp, vp, vp, vp, sz, C.POINTER(vp)], i32),
     "sph_graph_launch": ([vp, vp], i32),
     "sph_graph_destroy": ([vp], None),
@@ -415,6 +418,22 @@ def sph_interact_cells(plan, loop: int, buf, res, ws, params=None, tuning=None, 
 def sph_unpack_cells(plan, loop: int, res, store, tuning=None, stream=None):
     _check(lib().sph_unpack_cells(_h(plan), loop, _ptr(res), _nbytes(res), _s(store),
                                   C.byref(tuning) if tuning else None, _stream(stream)), "sph_unpack_cells")
+
+
+def sph_h_iterate_ws_bytes(plan) -> int:
+    b = sz()
+    _check(lib().sph_h_iterate_ws_bytes(_h(plan), C.byref(b)), "sph_h_iterate_ws_bytes")
+    return b.value
+
+
+def sph_h_iterate(plan, store, ws, eta=1.2348, tol=1e-4, max_iter=30, params=None, tuning=None, stream=None):
+    """Smoothing-length iteration; returns (passes run, particles still moving)."""
+    p = params if params is not None else default_params()
+    it, un = i32(), i64()
+    _check(lib().sph_h_iterate(_h(plan), _s(store), C.byref(p), C.byref(tuning) if tuning else None,
+                               float(eta), float(tol), int(max_iter), _ptr(ws), _nbytes(ws), C.byref(it),
+                               C.byref(un), _stream(stream)), "sph_h_iterate")
+    return it.value, un.value
 
 
 def sph_step_batched(plan, store, ws, params=None, tuning=None, stream=None):
