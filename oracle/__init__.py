@@ -216,6 +216,55 @@ def h_iterate(x, m, h, cell_width, eta=1.2348, tol=1e-4, max_iter=30) -> Dict[st
     return {"h": h, "rho": rho, "rho_dh": rdh, "wcount": wc, "passes": passes, "unconverged": still}
 
 
+# --------------------------------------------------------------------------
+# time integration around the loops (kick-drift-kick leapfrog, one global dt)
+# --------------------------------------------------------------------------
+def kick(v, a, u, u_dt, dt):
+    """v + a dt and u + u_dt dt in float32, the product rounded, then the sum"""
+    f32 = np.float32
+    dt = f32(dt)
+    v = np.asarray(v, f32); a = np.asarray(a, f32); u = np.asarray(u, f32); u_dt = np.asarray(u_dt, f32)
+    return (v + (a * dt).astype(f32)).astype(f32), (u + (u_dt * dt).astype(f32)).astype(f32)
+
+
+def drift(x, v, dt, cells):
+    """x + v dt in float64 (v widened exactly), and for every particle the
+    Euclidean distance by which it lies outside its cell's cube afterwards"""
+    x = np.asarray(x, np.float64)
+    xn = x + np.asarray(v, np.float32).astype(np.float64) * float(dt)
+    loc = np.repeat(np.asarray(cells["loc"], np.float64), np.asarray(cells["count"]), axis=0)
+    w = np.repeat(np.asarray(cells["width"], np.float64), np.asarray(cells["count"]))[:, None]
+    e = np.maximum(np.maximum(loc - xn, xn - (loc + w)), 0.0)
+    return xn, np.sqrt((e * e).sum(1))
+
+
+def cfl_dt(h, v_sig, cfl):
+    """min over particles with V > 0 of (cfl (gamma_K h)) / V in float32 (+inf if none)"""
+    f32 = np.float32
+    h = np.asarray(h, f32); vs = np.asarray(v_sig, f32)
+    gk = f32(lib().or_gamma_k())
+    sel = vs > 0
+    if not sel.any():
+        return f32(np.inf)
+    return ((f32(cfl) * (gk * h[sel]).astype(f32)).astype(f32) / vs[sel]).astype(f32).min()
+
+
+def step_kdk(f: Dict[str, np.ndarray], cells, dt):
+    """kick by dt/2 (the given a, u_dt), drift by dt, FP64 density -> gradient
+    -> force at the new positions, kick by dt/2 with the new a, u_dt (rounded to
+    the store's float32).  Returns the new fields and the three loops' results."""
+    f = dict(f)
+    half = np.float32(0.5) * np.float32(dt)
+    f["v"], f["u"] = kick(f["v"], f["a"], f["u"], f["u_dt"], half)
+    f["x"], _ = drift(f["x"], f["v"], np.float64(np.float32(dt)), cells)
+    r = full_chain(f)
+    a32 = r["force"]["a"].astype(np.float32)
+    udt32 = r["force"]["u_dt"].astype(np.float32)
+    f["v"], f["u"] = kick(f["v"], a32, f["u"], udt32, half)
+    f["a"], f["u_dt"] = a32, udt32
+    return f, r
+
+
 def pack_resolution(cells) -> np.ndarray:
     """Per-particle position resolution of the packed FP32 offsets: 2^-22 times
     the width of the particle's cell (offsets span at most a few cell widths and

@@ -467,3 +467,62 @@ def test_h_iteration_fixed_point_perfect_lattice(start):
     # the densities returned belong to the final h
     d = oracle.density(f["x"], f["mass"], out["h"])
     np.testing.assert_array_equal(d["rho"], out["rho"])
+
+
+# --------------------------------------------------------------------------
+# time integration
+# --------------------------------------------------------------------------
+def test_kick_drift_exact_cases():
+    """products and sums that are exact in binary: kick(dt) twice equals
+    kick(2 dt); a drift moves by v dt exactly; the distance outside a cell is
+    the Euclidean one (a 3-4-5 case)"""
+    v = np.array([[1.0, -2.0, 0.5]], np.float32)
+    a = np.array([[0.5, 0.25, -4.0]], np.float32)
+    u, udt = np.array([2.0], np.float32), np.array([-0.5], np.float32)
+    v1, u1 = oracle.kick(v, a, u, udt, 0.25)
+    np.testing.assert_array_equal(v1, [[1.125, -1.9375, -0.5]])
+    assert u1[0] == 1.875
+    v2, u2 = oracle.kick(v1, a, u1, udt, 0.25)
+    v3, u3 = oracle.kick(v, a, u, udt, 0.5)
+    np.testing.assert_array_equal(v2, v3)
+    np.testing.assert_array_equal(u2, u3)
+    cells = np.zeros(1, dtype=[("loc", "<f8", 3), ("width", "<f8"), ("first", "<i8"), ("count", "<i4"),
+                               ("pad", "<i4")])
+    cells["width"], cells["count"] = 0.25, 2
+    x = np.array([[0.1, 0.2, 0.125], [0.125, 0.125, 0.125]])
+    vv = np.array([[1.0, 0.0, 0.0], [-0.75, 1.0, 0.0]], np.float32)
+    xn, out = oracle.drift(x, vv, 0.5, cells)
+    np.testing.assert_array_equal(xn, [[0.6, 0.2, 0.125], [-0.25, 0.625, 0.125]])
+    assert out[0] == pytest.approx(0.35, abs=1e-15)
+    assert out[1] == pytest.approx(np.hypot(0.25, 0.375), abs=1e-15)
+    xs, out0 = oracle.drift(x, np.zeros_like(vv), 0.5, cells)
+    np.testing.assert_array_equal(xs, x)
+    assert np.all(out0 == 0.0)
+
+
+def test_cfl_dt_closed_form():
+    gk = np.float32(np.sqrt(10.0 / 3.0))
+    h = np.array([1.0, 2.0, 0.5], np.float32)
+    vs = np.array([2.0, 0.0, 4.0], np.float32)
+    # particle 1 has V = 0 and is skipped; particle 2 gives cfl gk 0.5 / 4
+    assert oracle.cfl_dt(h, vs, 0.25) == np.float32(np.float32(0.25) * np.float32(gk * np.float32(0.5))) / np.float32(4)
+    assert oracle.cfl_dt(h, np.zeros(3, np.float32), 0.25) == np.inf
+
+
+def test_kdk_step_conserves_momentum():
+    """pairwise antisymmetric forces: one full step leaves the total momentum
+    at its start value up to the float32 rounding of the velocities"""
+    f = inputs.lattice_set(8, seed=4, jitter=0.1, velocity="gresho", v_disp=0.05)
+    cells = np.zeros(1, dtype=[("loc", "<f8", 3), ("width", "<f8"), ("first", "<i8"), ("count", "<i4"),
+                               ("pad", "<i4")])
+    cells["width"], cells["count"] = 1.0, f["x"].shape[0]
+    r0 = oracle.full_chain(f)
+    f0 = dict(f, a=r0["force"]["a"].astype(np.float32), u_dt=r0["force"]["u_dt"].astype(np.float32))
+    m = f["mass"].astype(np.float64)[:, None]
+    p0 = (m * f0["v"].astype(np.float64)).sum(0)
+    f1, r1 = oracle.step_kdk(f0, cells, 1e-3)
+    p1 = (m * f1["v"].astype(np.float64)).sum(0)
+    scale = (m * np.abs(f0["v"].astype(np.float64))).sum()
+    assert np.all(np.abs(p1 - p0) <= 1e-6 * scale)
+    # the forces themselves sum to zero in FP64
+    assert np.abs((m * r1["force"]["a"]).sum(0)).max() <= 1e-12 * (m * np.abs(r1["force"]["a"])).sum()
