@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--fission", default=None,
                     help="'all' or comma list of layouts: also time pack + unpack under every "
                          "loop-fission schedule")
+    ap.add_argument("--kdk", action="store_true",
+                    help="also time kick-drift-kick steps (CFL time step) around the loops")
     ap.add_argument("--hiter", action="store_true",
                     help="also time the smoothing-length iteration from h perturbed by up to 10 %%")
     ap.add_argument("--convert", default=None,
@@ -351,6 +353,9 @@ def main():
         names = sph.LAYOUTS if a.fission == "all" else a.fission.split(",")
         out["fission"] = fission_sweep(ps, plan, names, tuning, a.steps)
 
+    if a.kdk:
+        out["kdk"] = kdk_bench(ps, plan, tuning, a.layout, a.steps)
+
     if a.hiter:
         out["h_iteration"] = hiter_bench(ps, plan, tuning, a.layout)
 
@@ -457,6 +462,38 @@ def fission_sweep(ps, plan, names, tuning, steps):
             res[name][sname]["vs_by_particle"] = round(res[name][sname]["total_ms"] / base, 4)
         del st
         torch.cuda.empty_cache()
+    return res
+
+
+def kdk_bench(ps, plan, tuning, layout_name, steps, cfl=0.1):
+    """kick-drift-kick steps on a fresh store: dt from the CFL condition of the
+    first state, then `steps` timed steps (each synchronises once)"""
+    import time
+
+    import torch
+
+    from paper_2606_23891_amd import sph
+
+    st = sph.Store(sph.LAYOUTS.index(layout_name), ps.n)
+    st.put_all(ps.fields)
+    ws = torch.empty(sph.kdk_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    sws = ws[: sph.sph_batched_ws_bytes(plan)]
+    iws = ws[(sph.sph_batched_ws_bytes(plan) + 255) // 256 * 256:]
+    sph.sph_step_batched(plan, st, sws, tuning=tuning)
+    dt = sph.sph_cfl_dt(plan, st, iws, cfl=cfl)
+    sph.sph_step_kdk(plan, st, ws, dt, tuning=tuning)   # warm-up step
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sph.sph_step_kdk(plan, st, ws, dt, tuning=tuning)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    mo, mh = sph.sph_drift(plan, st, 0.0, iws)
+    res = {"ms_per_step": round(ms, 3), "dt": dt, "cfl": cfl, "steps": steps,
+           "max_outside_cell": mo, "max_h": mh}
+    log(f"kdk: {ms:.3f} ms per step (dt {dt:.3e}, {steps} steps)")
+    del st, ws
+    torch.cuda.empty_cache()
     return res
 
 

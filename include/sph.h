@@ -333,6 +333,33 @@ sph_status sph_h_iterate_ws_bytes(const sph_plan *plan, size_t *bytes);
 sph_status sph_h_iterate(const sph_plan *plan, const sph_store *store, const sph_params *params,
                          const sph_tuning *tuning, float eta, float tol, int32_t max_iter, void *ws,
                          size_t ws_bytes, int32_t *iterations, int64_t *unconverged, void *stream);
+/* Time integration around the loops (the step the loops serve, Sec. 2.1):
+ * a kick-drift-kick leapfrog with one global time step.  Operations are
+ * exactly as written, each rounded once, no fused multiply-add.
+ * sph_kick: v += a dt and u += u_dt dt in float32 (a, u_dt from the last
+ * force loop).  sph_drift: x += v dt in float64 (v widened exactly); with
+ * max_outside / max_h non-null it also returns, after synchronising `stream`,
+ * the largest distance (float64) by which a particle now lies outside its
+ * cell's cube and the largest h.  sph_cfl_dt: dt = min over particles with
+ * V > 0 of (cfl (gamma_K h)) / V, float32 (V the signal velocity of the last
+ * gradient loop; +inf if none), synchronises `stream`.  sph_step_kdk: kick by
+ * dt/2, drift by dt, then -- if gamma_K max h + 2 max_outside does not exceed
+ * the narrowest cell, so every pair within a support still meets in adjacent
+ * cells -- density, gradient and force (sph_step_batched) and a second kick by
+ * dt/2; otherwise it stops after the drift with *rebuild = 1 and SPH_E_PLAN:
+ * the caller rebuilds the plan from the drifted positions, runs the loops and
+ * the second kick.  Synchronises `stream` once (the reach check).  ws:
+ * sph_integrate_ws_bytes bytes for sph_drift / sph_cfl_dt; for sph_step_kdk
+ * sph_batched_ws_bytes rounded up to 256, then sph_integrate_ws_bytes. */
+sph_status sph_integrate_ws_bytes(const sph_plan *plan, size_t *bytes);
+sph_status sph_kick(const sph_store *store, float dt, void *stream);
+sph_status sph_drift(const sph_plan *plan, const sph_store *store, double dt, void *ws, size_t ws_bytes,
+                     double *max_outside, float *max_h, void *stream);
+sph_status sph_cfl_dt(const sph_plan *plan, const sph_store *store, float cfl, void *ws, size_t ws_bytes,
+                      float *dt, void *stream);
+sph_status sph_step_kdk(const sph_plan *plan, const sph_store *store, const sph_params *params,
+                        const sph_tuning *tuning, float dt, void *ws, size_t ws_bytes, int32_t *rebuild,
+                        void *stream);
 /* Capture sph_step_batched into an executable HIP graph (*graph_exec). */
 sph_status sph_graph_capture(const sph_plan *plan, const sph_store *store, const sph_params *params,
                              const sph_tuning *tuning, void *ws, size_t ws_bytes, void **graph_exec);

@@ -918,6 +918,114 @@ sph_status sph_h_iterate(const sph_plan *p, const sph_store *store, const sph_pa
     return SPH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// time integration around the loops
+// ---------------------------------------------------------------------------
+sph_status sph_integrate_ws_bytes(const sph_plan *p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(SPH_E_ARG, "null argument");
+    *bytes = integrate_ws_bytes(p);
+    return SPH_OK;
+}
+
+sph_status sph_kick(const sph_store *store, float dt, void *stream)
+{
+    sph_status s = check_store(store);
+    if (s) return s;
+    if (!std::isfinite(dt)) return fail(SPH_E_ARG, "dt is not finite");
+    return launch_kick(store, dt, (hipStream_t)stream);
+}
+
+static sph_status integrate_checks(const sph_plan *p, const sph_store *store, void *ws, size_t ws_bytes)
+{
+    sph_status s;
+    if ((s = batched_checks(p, 0)) || (s = check_store(store))) return s;
+    if (store->n != p->n) return fail(SPH_E_ARG, "store size differs from the plan's");
+    if (!ws || !aligned256(ws)) return fail(SPH_E_ARG, "workspace null or misaligned");
+    if (ws_bytes < integrate_ws_bytes(p))
+        return fail(SPH_E_CAPACITY, "workspace needs " + std::to_string(integrate_ws_bytes(p)) + " bytes");
+    return SPH_OK;
+}
+
+// the folded reduction result at the end of the workspace, copied to the host
+static sph_status read_fold(const sph_plan *p, void *ws, double out[2], hipStream_t st)
+{
+    const char *r = (const char *)ws + integrate_ws_bytes(p) - 256;
+    SPH_HIP(hipMemcpyAsync(out, r, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    SPH_HIP(hipStreamSynchronize(st));
+    return SPH_OK;
+}
+
+sph_status sph_drift(const sph_plan *p, const sph_store *store, double dt, void *ws, size_t ws_bytes,
+                     double *max_outside, float *max_h, void *stream)
+{
+    sph_status s;
+    if ((s = integrate_checks(p, store, ws, ws_bytes))) return s;
+    if (!std::isfinite(dt)) return fail(SPH_E_ARG, "dt is not finite");
+    if (p->n == 0) {
+        if (max_outside) *max_outside = 0.0;
+        if (max_h) *max_h = 0.0f;
+        return SPH_OK;
+    }
+    if ((s = launch_drift(p, store, dt, ws, (hipStream_t)stream))) return s;
+    if (max_outside || max_h) {
+        double r[2];
+        if ((s = read_fold(p, ws, r, (hipStream_t)stream))) return s;
+        if (max_outside) *max_outside = r[0];
+        if (max_h) *max_h = (float)r[1];
+    }
+    return SPH_OK;
+}
+
+sph_status sph_cfl_dt(const sph_plan *p, const sph_store *store, float cfl, void *ws, size_t ws_bytes, float *dt,
+                      void *stream)
+{
+    sph_status s;
+    if ((s = integrate_checks(p, store, ws, ws_bytes))) return s;
+    if (!(cfl > 0.0f) || !dt) return fail(SPH_E_ARG, "cfl must be positive and dt non-null");
+    *dt = __builtin_huge_valf();
+    if (p->n == 0) return SPH_OK;
+    if ((s = launch_cfl(p, store, cfl, ws, (hipStream_t)stream))) return s;
+    double r[2];
+    if ((s = read_fold(p, ws, r, (hipStream_t)stream))) return s;
+    *dt = (float)r[1];
+    return SPH_OK;
+}
+
+sph_status sph_step_kdk(const sph_plan *p, const sph_store *store, const sph_params *prm, const sph_tuning *tn,
+                        float dt, void *ws, size_t ws_bytes, int32_t *rebuild, void *stream)
+{
+    sph_status s;
+    size_t step_ws = 0;
+    sph_batched_ws_bytes(p, &step_ws);
+    step_ws = (step_ws + 255) / 256 * 256;
+    if (!p) return fail(SPH_E_ARG, "plan is null");
+    if (ws_bytes < step_ws) return fail(SPH_E_CAPACITY, "workspace too small");
+    if ((s = integrate_checks(p, store, (char *)ws + step_ws, ws_bytes - step_ws))) return s;
+    if (!prm) return fail(SPH_E_ARG, "params is null");
+    if (!std::isfinite(dt) || !(dt >= 0.0f)) return fail(SPH_E_ARG, "dt must be finite and non-negative");
+    if (rebuild) *rebuild = 0;
+    if (p->n == 0) return SPH_OK;
+    const hipStream_t st = (hipStream_t)stream;
+    void *iws = (char *)ws + step_ws;
+    const float half = 0.5f * dt;
+    if ((s = launch_kick(store, half, st))) return s;
+    if ((s = launch_drift(p, store, (double)dt, iws, st))) return s;
+    double r[2];
+    if ((s = read_fold(p, iws, r, st))) return s;
+    // every pair within a support must still meet in adjacent cells:
+    // H_max + 2 (largest distance outside a cell) <= the narrowest cell
+    double wmin = __builtin_huge_val();
+    for (const sph_cell &c : p->cells) wmin = std::min(wmin, c.width);
+    if ((double)kGammaK * r[1] + 2.0 * r[0] > wmin) {
+        if (rebuild) *rebuild = 1;
+        return fail(SPH_E_PLAN, "particles drifted beyond the plan's reach: rebuild the plan, then run the "
+                                "loops and the second half kick");
+    }
+    if ((s = step_batched(p, store, prm, tn, ws, step_ws, st))) return s;
+    return launch_kick(store, half, st);
+}
+
 sph_status sph_step_batched(const sph_plan *p, const sph_store *store, const sph_params *prm,
                             const sph_tuning *tn, void *ws, size_t ws_bytes, void *stream)
 {

@@ -221,6 +221,14 @@ sph_status launch_h_newton(const sph_plan *p, const sph_store *s, float eta, flo
 // count[1] = flagged tiles
 sph_status launch_flagged_tiles(const sph_plan *p, const int32_t *flags, int32_t *items, int32_t *blk,
                                 int32_t *count, hipStream_t st);
+// time integration: workspace of the drift / time-step reductions (the
+// folded result, two doubles, at its end: integrate_ws_bytes - 256), kick,
+// drift (x += v dt; result [largest distance outside a cell, largest h]) and
+// the CFL step (result [unused, smallest dt])
+size_t integrate_ws_bytes(const sph_plan *p);
+sph_status launch_kick(const sph_store *s, float dt, hipStream_t st);
+sph_status launch_drift(const sph_plan *p, const sph_store *s, double dt, void *ws, hipStream_t st);
+sph_status launch_cfl(const sph_plan *p, const sph_store *s, float cfl, void *ws, hipStream_t st);
 // the fission groups of a layout's pack (unpack) members: bit masks as in
 // sph_fission_passes, returned count (0 for an unknown layout)
 int fission_passes(int layout, int loop, int schedule, bool unpack, uint32_t *masks);

@@ -800,6 +800,176 @@ static sph_status h_newton_l(const HIterArgs &a, hipStream_t st)
     return SPH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// time integration around the loops: kick, drift and the CFL time step
+// (float32 and float64 operations exactly as written, no contraction)
+// ---------------------------------------------------------------------------
+struct KickArgs {
+    StoreArg store;
+    int64_t n;
+    float dt;
+};
+
+// v += a dt and u += u_dt dt, each a float32 product rounded, then a sum
+template <int L>
+__global__ __launch_bounds__(256) void k_kick(KickArgs a)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    static_for<0, 3>([&](auto cc) {
+        constexpr int C = decltype(cc)::value;
+        const float v = ld<L, FV, C, float>(a.store, p), acc = ld<L, FA, C, float>(a.store, p);
+        st<L, FV, C, float>(a.store, p, v + acc * a.dt);
+    });
+    const float u = ld<L, FU, 0, float>(a.store, p), udt = ld<L, FUDT, 0, float>(a.store, p);
+    st<L, FU, 0, float>(a.store, p, u + udt * a.dt);
+}
+
+struct DriftArgs {
+    StoreArg store;
+    const Chunk *tiles;
+    const sph_cell *cells;
+    int64_t ntile;
+    double dt;
+    double *blk_out;  // per block: largest distance of a particle outside its cell
+    float *blk_h;     // per block: largest h
+};
+
+__device__ __forceinline__ double wave_max_d(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ float wave_max_f(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ float wave_min_f(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// x += v dt in float64 (v widened exactly), one wave per tile; the distance
+// by which the drifted particle lies outside its cell's cube, in float64
+template <int L>
+__global__ __launch_bounds__(256) void k_drift(DriftArgs a)
+{
+    __shared__ double so[4];
+    __shared__ float sh[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+    double out = 0.0;
+    float hm = 0.0f;
+    if (c < a.ntile) {
+        const Chunk ch = a.tiles[c];
+        if (lane < ch.n) {
+            const int64_t p = ch.part0 + lane;
+            const sph_cell &cl = a.cells[ch.cell];
+            double e2 = 0.0;
+            static_for<0, 3>([&](auto cc) {
+                constexpr int C = decltype(cc)::value;
+                const double x = ld<L, FX, C, double>(a.store, p);
+                const double xn = x + (double)ld<L, FV, C, float>(a.store, p) * a.dt;
+                st<L, FX, C, double>(a.store, p, xn);
+                const double e = fmax(fmax(cl.loc[C] - xn, xn - (cl.loc[C] + cl.width)), 0.0);
+                e2 = e2 + e * e;
+            });
+            out = sqrt(e2);
+            hm = ld<L, FH, 0, float>(a.store, p);
+        }
+    }
+    out = wave_max_d(out);
+    hm = wave_max_f(hm);
+    if (lane == 0) {
+        so[wv] = out;
+        sh[wv] = hm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.blk_out[blockIdx.x] = fmax(fmax(so[0], so[1]), fmax(so[2], so[3]));
+        a.blk_h[blockIdx.x] = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+    }
+}
+
+// per block: the smallest cfl (gamma_K h) / v_sig over particles with v_sig > 0
+struct CflArgs {
+    StoreArg store;
+    int64_t n;
+    float cfl;
+    float *blk_dt;
+};
+
+template <int L>
+__global__ __launch_bounds__(256) void k_cfl(CflArgs a)
+{
+    __shared__ float sm[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float dt = __builtin_huge_valf();
+    if (p < a.n) {
+        const float vs = ld<L, FVSIG, 0, float>(a.store, p);
+        if (vs > 0.0f) dt = (a.cfl * (kGammaK * ld<L, FH, 0, float>(a.store, p))) / vs;
+    }
+    dt = wave_min_f(dt);
+    if (lane == 0) sm[wv] = dt;
+    __syncthreads();
+    if (threadIdx.x == 0) a.blk_dt[blockIdx.x] = fminf(fminf(sm[0], sm[1]), fminf(sm[2], sm[3]));
+}
+
+// one block folds the per-block partials: out[0] = max of d, out[1] = max of
+// f (as float bits in a double slot), or the min of f when MIN
+template <bool MIN>
+__global__ __launch_bounds__(256) void k_fold(const double *d, const float *f, int64_t nblk, double *out)
+{
+    __shared__ double sd[4];
+    __shared__ float sf[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double md = 0.0;
+    float mf = MIN ? __builtin_huge_valf() : 0.0f;
+    for (int64_t i = threadIdx.x; i < nblk; i += blockDim.x) {
+        if (d) md = fmax(md, d[i]);
+        mf = MIN ? fminf(mf, f[i]) : fmaxf(mf, f[i]);
+    }
+    md = wave_max_d(md);
+    mf = MIN ? wave_min_f(mf) : wave_max_f(mf);
+    if (lane == 0) {
+        sd[wv] = md;
+        sf[wv] = mf;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = fmax(fmax(sd[0], sd[1]), fmax(sd[2], sd[3]));
+        out[1] = MIN ? (double)fminf(fminf(sf[0], sf[1]), fminf(sf[2], sf[3]))
+                     : (double)fmaxf(fmaxf(sf[0], sf[1]), fmaxf(sf[2], sf[3]));
+    }
+}
+
+template <int L>
+static sph_status kick_l(const KickArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_kick<L>), dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+    SPH_CHECK_LAUNCH("kick launch");
+    return SPH_OK;
+}
+
+template <int L>
+static sph_status drift_l(const DriftArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_drift<L>), dim3((unsigned)((a.ntile + 3) / 4)), dim3(256), 0, st, a);
+    SPH_CHECK_LAUNCH("drift launch");
+    return SPH_OK;
+}
+
+template <int L>
+static sph_status cfl_l(const CflArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_cfl<L>), dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+    SPH_CHECK_LAUNCH("time-step launch");
+    return SPH_OK;
+}
+
 #define SPH_BY_LAYOUT(layout, fn, ...)                                              \
     switch (layout) {                                                               \
     case 0: return fn<0>(__VA_ARGS__); case 1: return fn<1>(__VA_ARGS__);            \
@@ -935,6 +1105,80 @@ sph_status launch_flagged_tiles(const sph_plan *p, const int32_t *flags, int32_t
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, st, blk, (const int32_t *)blk_moved, nblk, count);
     hipLaunchKernelGGL(k_flag_scatter, dim3((unsigned)nblk), dim3(256), 0, st, flags, (int64_t)p->ntile, blk, items);
     SPH_CHECK_LAUNCH("tile list launch");
+    return SPH_OK;
+}
+
+size_t integrate_ws_bytes(const sph_plan *p)
+{
+    const size_t nb = (size_t)std::max<int64_t>((p->ntile + 3) / 4, (p->n + 255) / 256);
+    return (nb * 8 + 255) / 256 * 256 + (nb * 4 + 255) / 256 * 256 + 256;
+}
+
+sph_status launch_kick(const sph_store *s, float dt, hipStream_t st)
+{
+    KickArgs a{store_arg(s), s->n, dt};
+    if (a.n == 0) return SPH_OK;
+    SPH_BY_LAYOUT(s->layout, kick_l, a, st);
+}
+
+sph_status launch_drift(const sph_plan *p, const sph_store *s, double dt, void *ws, hipStream_t st)
+{
+    const size_t nb = (size_t)std::max<int64_t>((p->ntile + 3) / 4, (p->n + 255) / 256);
+    DriftArgs a{};
+    a.store = store_arg(s);
+    a.tiles = p->d_tiles;
+    a.cells = p->d_cells;
+    a.ntile = p->ntile;
+    a.dt = dt;
+    a.blk_out = (double *)ws;
+    a.blk_h = (float *)((char *)ws + (nb * 8 + 255) / 256 * 256);
+    double *out = (double *)((char *)a.blk_h + (nb * 4 + 255) / 256 * 256);
+    if (a.ntile == 0) return SPH_OK;
+    const int64_t nblk = (a.ntile + 3) / 4;
+    sph_status r;
+    switch (s->layout) {
+    case 0: r = drift_l<0>(a, st); break;
+    case 1: r = drift_l<1>(a, st); break;
+    case 2: r = drift_l<2>(a, st); break;
+    case 3: r = drift_l<3>(a, st); break;
+    case 4: r = drift_l<4>(a, st); break;
+    case 5: r = drift_l<5>(a, st); break;
+    case 6: r = drift_l<6>(a, st); break;
+    case 7: r = drift_l<7>(a, st); break;
+    case 8: r = drift_l<8>(a, st); break;
+    default: return fail(SPH_E_LAYOUT, "unknown layout");
+    }
+    if (r) return r;
+    hipLaunchKernelGGL(k_fold<false>, dim3(1), dim3(256), 0, st, (const double *)a.blk_out, (const float *)a.blk_h,
+                       nblk, out);
+    SPH_CHECK_LAUNCH("fold launch");
+    return SPH_OK;
+}
+
+sph_status launch_cfl(const sph_plan *p, const sph_store *s, float cfl, void *ws, hipStream_t st)
+{
+    const size_t nb = (size_t)std::max<int64_t>((p->ntile + 3) / 4, (p->n + 255) / 256);
+    CflArgs a{store_arg(s), s->n, cfl, (float *)((char *)ws + (nb * 8 + 255) / 256 * 256)};
+    double *out = (double *)((char *)a.blk_dt + (nb * 4 + 255) / 256 * 256);
+    if (a.n == 0) return SPH_OK;
+    const int64_t nblk = (a.n + 255) / 256;
+    sph_status r;
+    switch (s->layout) {
+    case 0: r = cfl_l<0>(a, st); break;
+    case 1: r = cfl_l<1>(a, st); break;
+    case 2: r = cfl_l<2>(a, st); break;
+    case 3: r = cfl_l<3>(a, st); break;
+    case 4: r = cfl_l<4>(a, st); break;
+    case 5: r = cfl_l<5>(a, st); break;
+    case 6: r = cfl_l<6>(a, st); break;
+    case 7: r = cfl_l<7>(a, st); break;
+    case 8: r = cfl_l<8>(a, st); break;
+    default: return fail(SPH_E_LAYOUT, "unknown layout");
+    }
+    if (r) return r;
+    hipLaunchKernelGGL(k_fold<true>, dim3(1), dim3(256), 0, st, (const double *)nullptr, (const float *)a.blk_dt,
+                       nblk, out);
+    SPH_CHECK_LAUNCH("fold launch");
     return SPH_OK;
 }
 

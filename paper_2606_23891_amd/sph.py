@@ -90,6 +90,11 @@ _SIGS = {
     "sph_interact_cells": ([vp, i32, vp, sz, vp, vp, vp, sz, vp, vp, sz, vp], i32),
     "sph_unpack_cells": ([vp, i32, vp, sz, vp, vp, vp], i32),
     "sph_step_batched": ([vp, vp, vp, vp, vp, sz, vp], i32),
+    "sph_integrate_ws_bytes": ([vp, C.POINTER(sz)], i32),
+    "sph_kick": ([vp, C.c_float, vp], i32),
+    "sph_drift": ([vp, vp, C.c_double, vp, sz, C.POINTER(C.c_double), C.POINTER(C.c_float), vp], i32),
+    "sph_cfl_dt": ([vp, vp, C.c_float, vp, sz, C.POINTER(C.c_float), vp], i32),
+    "sph_step_kdk": ([vp, vp, vp, vp, C.c_float, vp, sz, C.POINTER(i32), vp], i32),
     "sph_h_iterate_ws_bytes": ([vp, C.POINTER(sz)], i32),
     "sph_h_iterate": ([vp, vp, vp, vp, C.c_float, C.c_float, i32, vp, sz, C.POINTER(i32), C.POINTER(i64), vp],
                       i32),
@@ -418,6 +423,47 @@ def sph_interact_cells(plan, loop: int, buf, res, ws, params=None, tuning=None, 
 def sph_unpack_cells(plan, loop: int, res, store, tuning=None, stream=None):
     _check(lib().sph_unpack_cells(_h(plan), loop, _ptr(res), _nbytes(res), _s(store),
                                   C.byref(tuning) if tuning else None, _stream(stream)), "sph_unpack_cells")
+
+
+def sph_integrate_ws_bytes(plan) -> int:
+    b = sz()
+    _check(lib().sph_integrate_ws_bytes(_h(plan), C.byref(b)), "sph_integrate_ws_bytes")
+    return b.value
+
+
+def sph_kick(store, dt: float, stream=None):
+    _check(lib().sph_kick(_s(store), float(dt), _stream(stream)), "sph_kick")
+
+
+def sph_drift(plan, store, dt: float, ws, stream=None, report=True):
+    """x += v dt; returns (largest distance outside a cell, largest h) when report"""
+    mo, mh = C.c_double(), C.c_float()
+    _check(lib().sph_drift(_h(plan), _s(store), float(dt), _ptr(ws), _nbytes(ws),
+                           C.byref(mo) if report else None, C.byref(mh) if report else None, _stream(stream)),
+           "sph_drift")
+    return (mo.value, mh.value) if report else None
+
+
+def sph_cfl_dt(plan, store, ws, cfl: float = 0.1, stream=None) -> float:
+    dt = C.c_float()
+    _check(lib().sph_cfl_dt(_h(plan), _s(store), float(cfl), _ptr(ws), _nbytes(ws), C.byref(dt),
+                            _stream(stream)), "sph_cfl_dt")
+    return dt.value
+
+
+def kdk_ws_bytes(plan) -> int:
+    """workspace of sph_step_kdk: the batched step's, rounded to 256, then the integrator's"""
+    return (sph_batched_ws_bytes(plan) + 255) // 256 * 256 + sph_integrate_ws_bytes(plan)
+
+
+def sph_step_kdk(plan, store, ws, dt: float, params=None, tuning=None, stream=None):
+    """one kick-drift-kick step; returns 1 when the plan must be rebuilt (raises
+    SphError then, with the status SPH_E_PLAN, after the drift)"""
+    p = params if params is not None else default_params()
+    rb = i32()
+    _check(lib().sph_step_kdk(_h(plan), _s(store), C.byref(p), C.byref(tuning) if tuning else None, float(dt),
+                              _ptr(ws), _nbytes(ws), C.byref(rb), _stream(stream)), "sph_step_kdk")
+    return rb.value
 
 
 def sph_h_iterate_ws_bytes(plan) -> int:
