@@ -158,12 +158,43 @@ def tune(plan, store, log=print):
     return best, times
 
 
+def choose_layout(plan, fields, layouts=None, tuning=None, log=print):
+    """Time pack + unpack of the three loops (batched form) for each candidate
+    store layout on the same particles and return (fastest layout name,
+    {layout: ms}): the measured choice among the decompositions (a store is
+    then moved into it with sph_store_convert)."""
+    import torch
+
+    from . import sph
+
+    names = layouts or sph.LAYOUTS
+    bufs = {L: sph.cell_buffers(plan, L) for L in range(3)}
+    times = {}
+    for name in names:
+        st = sph.Store(sph.LAYOUTS.index(name), plan.n)
+        st.put_all(fields)
+
+        def run():
+            for L in range(3):
+                pack, res = bufs[L]
+                sph.sph_pack_cells(plan, L, st, pack, tuning)
+                sph.sph_unpack_cells(plan, L, res, st, tuning)
+        times[name] = _timed(run)
+        log(f"layout {name}: pack+unpack {times[name]:.3f} ms")
+        del st
+        torch.cuda.empty_cache()
+    best = min(times, key=times.get)
+    return best, times
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--grid", type=int, default=None)
     ap.add_argument("--n-side", type=int, default=None)
     ap.add_argument("--layout", default="SAOS_SHARED")
+    ap.add_argument("--choose-layout", action="store_true",
+                    help="only time pack + unpack per store layout and print the fastest")
     a = ap.parse_args()
     import torch
 
@@ -176,6 +207,10 @@ def main():
         kw["n_side"] = a.n_side
     ps = inputs.make_config(a.config, **kw)
     plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    if a.choose_layout:
+        best, times = choose_layout(plan, ps.fields)
+        print(json.dumps({"best_layout": best, "pack_unpack_ms": times}))
+        return
     store = sph.Store(sph.LAYOUTS.index(a.layout), ps.n)
     store.put_all(ps.fields)
     dev = device_key(torch.cuda.get_device_properties(0))

@@ -201,3 +201,25 @@ def test_offload_async_matches_offload_step(layout):
         assert host_s.raw() == ref_h, sched
         assert dev_s.raw() == ref_d, sched
     plan.close()
+
+
+def test_layout_choice_and_conversion():
+    """the tuner's measured layout choice is the fastest of its own timings,
+    and a store converted into it holds the same fields"""
+    import torch
+
+    from paper_2606_23891_amd import tune
+    ps = inputs.make_config(1, n_side=32)
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    log("layout choice")
+    best, times = tune.choose_layout(plan, ps.fields, ["AOS", "SAOS_SHARED", "SOA"], log=log)
+    assert set(times) == {"AOS", "SAOS_SHARED", "SOA"} and all(t > 0 for t in times.values())
+    assert times[best] == min(times.values())
+    src = sph.Store(sph.LAYOUTS.index("AOS"), ps.n)
+    src.put_all(ps.fields)
+    dst = sph.Store(sph.LAYOUTS.index(best), ps.n)
+    sph.sph_store_convert(src, dst)
+    torch.cuda.synchronize()
+    for k in ps.fields:
+        assert dst.get(k).tobytes() == src.get(k).tobytes(), k
+    plan.close()
