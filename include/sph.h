@@ -15,13 +15,18 @@
  *
  * Conventions shared by every call
  *  - Every call returns sph_status; nothing throws across the ABI.  On an
- *    error nothing has been enqueued and no memory has been written.
+ *    error nothing has been enqueued and no memory has been written, except
+ *    where a call says otherwise (sph_step_kdk stopping for a plan rebuild
+ *    after its drift; a HIP failure in the middle of a multi-launch call).
  *  - Device pointers are HIP device (or host-mapped) addresses owned by the
  *    caller; the library never frees caller memory.  Store substruct arrays
  *    and buffers must be 256-byte aligned.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
  *    asynchronously on it; faults inside kernels surface at the caller's next
- *    synchronisation.  HIP errors map to SPH_E_HIP, detail in sph_last_error().
+ *    synchronisation.  Calls that return a device-side result to the host
+ *    (sph_drift with its outputs, sph_cfl_dt, sph_h_iterate, sph_step_kdk)
+ *    synchronise the stream.  HIP errors map to SPH_E_HIP, detail in
+ *    sph_last_error().
  *  - Plans are library-owned and immutable after creation; one plan may be used
  *    from several threads and streams at once.  No call keeps global mutable
  *    state besides the thread-local error text.
