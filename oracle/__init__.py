@@ -172,8 +172,10 @@ def h_newton_step(h, m, rho, rho_dh, cell_width, eta, tol):
     rho)^(1/3).  Newton: dh = -f / f' with f' = h^3 rho' + 3 h^2 rho, which is
     dh = -h (rho - n) / (3 rho + h rho') for n = m eta^3 / h^3; where that
     denominator is not positive, the fixed-point step to eta (m / rho)^(1/3).
-    |dh| <= tol h: converged, h kept.  Otherwise h + dh clipped to [h/2, 2h] and
-    to gamma_K h <= the cell width.  Returns (new h as float32, moved mask)."""
+    |dh| <= tol h: converged, h kept; otherwise h + dh clipped to [h/2, 2h].
+    Either way h is then held to gamma_K h <= the cell width (so a particle
+    above it moves even when converged).  Returns (new h as float32, moved
+    mask)."""
     h64 = np.asarray(h, np.float64)
     rho = np.asarray(rho, np.float64)
     n = np.asarray(m, np.float64) * eta ** 3 / h64 ** 3
@@ -183,9 +185,10 @@ def h_newton_step(h, m, rho, rho_dh, cell_width, eta, tol):
     fixed = h64 * (np.cbrt(n / rho) - 1.0)
     dh = np.where(den > 0.0, newton, fixed)
     conv = np.abs(dh) <= tol * h64
-    hn = np.minimum(np.clip(h64 + dh, 0.5 * h64, 2.0 * h64), np.asarray(cell_width, np.float64) / GAMMA_K)
+    hn = np.where(conv, h64, np.clip(h64 + dh, 0.5 * h64, 2.0 * h64))
+    hn = np.minimum(hn, np.asarray(cell_width, np.float64) / GAMMA_K)
     hn32 = hn.astype(np.float32)
-    moved = ~conv & (hn32 != np.asarray(h, np.float32))
+    moved = hn32 != np.asarray(h, np.float32)
     out = np.asarray(h, np.float32).copy()
     out[moved] = hn32[moved]
     return out, moved

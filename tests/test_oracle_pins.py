@@ -435,6 +435,9 @@ def test_h_newton_step_branches():
     assert float(h[0]) == pytest.approx(0.2, rel=1e-7)
     h, _ = oracle.h_newton_step(np.array([0.6], np.float32), [m], [rho], [0.0], [1.0], eta, 1e-6)
     assert float(h[0]) == pytest.approx(1.0 / oracle.GAMMA_K, rel=1e-7)
+    # the cap holds a converged h too: it moves down to the cap
+    h, moved = oracle.h_newton_step(h1, [m], [rho], [0.0], [1.0], eta, 1e-5)
+    assert moved[0] and float(h[0]) == pytest.approx(1.0 / oracle.GAMMA_K, rel=1e-7)
 
 
 @pytest.mark.parametrize("start", [0.8, 1.3])
