@@ -326,8 +326,8 @@ sph_status sph_step_batched(const sph_plan *plan, const sph_store *store, const 
  * tiles holding a particle that moved), then one Newton step per particle on
  * f(h) = rho h^3 - m eta^3 using the density and its h-derivative rho_dh: a
  * particle whose step is at most tol h keeps its h and the density computed
- * with it; any other moves to h + dh, limited to [h/2, 2h] and to a support
- * gamma_K h no wider than its own cell.  Stops when no particle moved or after
+ * with it; any other moves to h + dh, limited to [h/2, 2h]; every h is then
+ * held to a support gamma_K h no wider than its own cell.  Stops when no particle moved or after
  * max_iter passes; *iterations receives the passes run and *unconverged the
  * particles that still moved in the last one (their density belongs to their
  * previous h).  The store's h, rho, rho_dh and wcount are updated in place.

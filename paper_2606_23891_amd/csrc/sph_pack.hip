@@ -678,8 +678,8 @@ struct HIterArgs {
 // h^3 the density at which h would be consistent; where the denominator is
 // not positive the step is the fixed-point one, h eta-scaled to the current
 // density.  A particle whose step is within tol h keeps its h (and with it the
-// density just computed); any other takes h + dh limited to [h/2, 2h] and to
-// a support no wider than its cell.
+// density just computed); any other takes h + dh limited to [h/2, 2h].  Every
+// h, moved or not, is then held to a support no wider than its cell.
 template <int L>
 __global__ __launch_bounds__(256) void k_h_newton(HIterArgs a)
 {
@@ -698,14 +698,12 @@ __global__ __launch_bounds__(256) void k_h_newton(HIterArgs a)
         const float n = m * a.eta3 / (h * h * h);
         const float den = 3.0f * rho + h * drho;
         const float dh = den > 0.0f ? -h * (rho - n) / den : h * (cbrtf(n / rho) - 1.0f);
-        if (!(fabsf(dh) <= a.tol * h)) {
-            const float hcap = (float)(a.cells[ch.cell].width / (double)kGammaK);
-            float hn = fminf(fmaxf(h + dh, 0.5f * h), 2.0f * h);
-            hn = fminf(hn, hcap);
-            if (hn != h) {
-                st<L, FH, 0, float>(a.store, p, hn);
-                moved = true;
-            }
+        float hn = h;
+        if (!(fabsf(dh) <= a.tol * h)) hn = fminf(fmaxf(h + dh, 0.5f * h), 2.0f * h);
+        hn = fminf(hn, (float)(a.cells[ch.cell].width / (double)kGammaK));
+        if (hn != h) {
+            st<L, FH, 0, float>(a.store, p, hn);
+            moved = true;
         }
     }
     const uint64_t bal = __ballot(moved);

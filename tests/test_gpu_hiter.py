@@ -84,3 +84,35 @@ def test_h_iteration_pass_limit_and_arguments():
     with pytest.raises(sph.SphError):
         sph.sph_h_iterate(plan, st, ws[:256], eta=ETA, tol=TOL, max_iter=5)
     plan.close()
+
+
+def test_h_iteration_octree_with_cell_caps():
+    """the clustered set's cells with eta = 3: supports of several hundred
+    neighbours, so the dense regions reach the cap gamma_K h <= cell width and
+    stay there; GPU and oracle apply the same limits, so the final h agree and
+    the stored densities are those of the final h"""
+    import torch
+    ps = inputs.make_config(3, n_side=24)
+    eta = 3.0   # supports of several hundred neighbours: the dense regions reach the cap
+    h0 = (_perturbed(ps, 7) * np.float32(eta / ETA)).astype(np.float32)
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    st = device_store(ps, sph.LAYOUTS.index("SOA"), extra={"h": h0})
+    ws = torch.zeros(sph.sph_h_iterate_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    log(f"h iteration octree n={ps.n} cells={len(ps.cells)}")
+    passes, still = sph.sph_h_iterate(plan, st, ws, eta=eta, tol=TOL, max_iter=40)
+    torch.cuda.synchronize()
+    hg = st.get("h")
+    width = _cell_width(ps)
+    ref = oracle.h_iterate(ps.fields["x"], ps.fields["mass"], h0, width, eta=eta, tol=TOL, max_iter=40)
+    log(f"octree: GPU passes {passes} left {still}; oracle passes {ref['passes']} left {ref['unconverged']}; "
+        f"capped {int(np.sum(hg >= (width / oracle.GAMMA_K).astype(np.float32)))}")
+    assert still == 0 and ref["unconverged"] == 0
+    hr = ref["h"].astype(np.float64)
+    assert np.max(np.abs(hg - hr) / hr) <= 3 * TOL
+    capped = hg.astype(np.float64) * oracle.GAMMA_K >= width * (1 - 1e-6)
+    assert capped.sum() > 100
+    assert np.all(oracle.GAMMA_K * hg.astype(np.float64) <= width * (1 + 1e-6))
+    ref_d = oracle.density(ps.fields["x"], ps.fields["mass"], hg, epsx=oracle.pack_resolution(ps.cells))
+    errs = compare_loop(0, outputs(st, 0), ref_d)
+    assert max(errs.values()) <= 1e-5, errs
+    plan.close()
