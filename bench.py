@@ -126,8 +126,8 @@ def workload_name(k, ps):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
-                                   "part of this build (see the design notes on sharding)",
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the library has no "
+                                   "multi-GPU path (how it would shard is described in the design notes)",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
