@@ -17,6 +17,7 @@
 // store; the signal velocity keeps the larger value.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "sph_internal.hpp"
@@ -849,18 +850,20 @@ __device__ __forceinline__ float wave_min_f(float v)
     return v;
 }
 
-// x += v dt in float64 (v widened exactly), one wave per tile; the distance
-// by which the drifted particle lies outside its cell's cube, in float64
+// x += v dt in float64 (v widened exactly), one wave per tile, the waves
+// striding over the tiles (a bounded grid keeps the per-block partials few);
+// the distance by which the drifted particle lies outside its cell's cube, in
+// float64
 template <int L>
 __global__ __launch_bounds__(256) void k_drift(DriftArgs a)
 {
     __shared__ double so[4];
     __shared__ float sh[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
     double out = 0.0;
     float hm = 0.0f;
-    if (c < a.ntile) {
+    for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv; c < a.ntile;
+         c += (int64_t)gridDim.x * (blockDim.x >> 6)) {
         const Chunk ch = a.tiles[c];
         if (lane < ch.n) {
             const int64_t p = ch.part0 + lane;
@@ -874,8 +877,8 @@ __global__ __launch_bounds__(256) void k_drift(DriftArgs a)
                 const double e = fmax(fmax(cl.loc[C] - xn, xn - (cl.loc[C] + cl.width)), 0.0);
                 e2 = e2 + e * e;
             });
-            out = sqrt(e2);
-            hm = ld<L, FH, 0, float>(a.store, p);
+            out = fmax(out, sqrt(e2));
+            hm = fmaxf(hm, ld<L, FH, 0, float>(a.store, p));
         }
     }
     out = wave_max_d(out);
@@ -904,11 +907,10 @@ __global__ __launch_bounds__(256) void k_cfl(CflArgs a)
 {
     __shared__ float sm[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float dt = __builtin_huge_valf();
-    if (p < a.n) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.n; p += (int64_t)gridDim.x * blockDim.x) {
         const float vs = ld<L, FVSIG, 0, float>(a.store, p);
-        if (vs > 0.0f) dt = (a.cfl * (kGammaK * ld<L, FH, 0, float>(a.store, p))) / vs;
+        if (vs > 0.0f) dt = fminf(dt, (a.cfl * (kGammaK * ld<L, FH, 0, float>(a.store, p))) / vs);
     }
     dt = wave_min_f(dt);
     if (lane == 0) sm[wv] = dt;
@@ -952,10 +954,14 @@ static sph_status kick_l(const KickArgs &a, hipStream_t st)
     return SPH_OK;
 }
 
+// blocks of the reductions' first stage (grid-stride beyond)
+constexpr int64_t kFoldBlocks = 2048;
+
 template <int L>
 static sph_status drift_l(const DriftArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_drift<L>), dim3((unsigned)((a.ntile + 3) / 4)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_drift<L>), dim3((unsigned)std::min<int64_t>((a.ntile + 3) / 4, kFoldBlocks)), dim3(256), 0,
+                       st, a);
     SPH_CHECK_LAUNCH("drift launch");
     return SPH_OK;
 }
@@ -963,7 +969,8 @@ static sph_status drift_l(const DriftArgs &a, hipStream_t st)
 template <int L>
 static sph_status cfl_l(const CflArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_cfl<L>), dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_cfl<L>), dim3((unsigned)std::min<int64_t>((a.n + 255) / 256, kFoldBlocks)), dim3(256), 0,
+                       st, a);
     SPH_CHECK_LAUNCH("time-step launch");
     return SPH_OK;
 }
@@ -1106,9 +1113,14 @@ sph_status launch_flagged_tiles(const sph_plan *p, const int32_t *flags, int32_t
     return SPH_OK;
 }
 
+static size_t fold_blocks(const sph_plan *p)
+{
+    return (size_t)std::min<int64_t>(std::max<int64_t>((p->ntile + 3) / 4, (p->n + 255) / 256), kFoldBlocks);
+}
+
 size_t integrate_ws_bytes(const sph_plan *p)
 {
-    const size_t nb = (size_t)std::max<int64_t>((p->ntile + 3) / 4, (p->n + 255) / 256);
+    const size_t nb = fold_blocks(p);
     return (nb * 8 + 255) / 256 * 256 + (nb * 4 + 255) / 256 * 256 + 256;
 }
 
@@ -1121,7 +1133,7 @@ sph_status launch_kick(const sph_store *s, float dt, hipStream_t st)
 
 sph_status launch_drift(const sph_plan *p, const sph_store *s, double dt, void *ws, hipStream_t st)
 {
-    const size_t nb = (size_t)std::max<int64_t>((p->ntile + 3) / 4, (p->n + 255) / 256);
+    const size_t nb = fold_blocks(p);
     DriftArgs a{};
     a.store = store_arg(s);
     a.tiles = p->d_tiles;
@@ -1132,7 +1144,7 @@ sph_status launch_drift(const sph_plan *p, const sph_store *s, double dt, void *
     a.blk_h = (float *)((char *)ws + (nb * 8 + 255) / 256 * 256);
     double *out = (double *)((char *)a.blk_h + (nb * 4 + 255) / 256 * 256);
     if (a.ntile == 0) return SPH_OK;
-    const int64_t nblk = (a.ntile + 3) / 4;
+    const int64_t nblk = std::min<int64_t>((a.ntile + 3) / 4, kFoldBlocks);
     sph_status r;
     switch (s->layout) {
     case 0: r = drift_l<0>(a, st); break;
@@ -1155,11 +1167,11 @@ sph_status launch_drift(const sph_plan *p, const sph_store *s, double dt, void *
 
 sph_status launch_cfl(const sph_plan *p, const sph_store *s, float cfl, void *ws, hipStream_t st)
 {
-    const size_t nb = (size_t)std::max<int64_t>((p->ntile + 3) / 4, (p->n + 255) / 256);
+    const size_t nb = fold_blocks(p);
     CflArgs a{store_arg(s), s->n, cfl, (float *)((char *)ws + (nb * 8 + 255) / 256 * 256)};
     double *out = (double *)((char *)a.blk_dt + (nb * 4 + 255) / 256 * 256);
     if (a.n == 0) return SPH_OK;
-    const int64_t nblk = (a.n + 255) / 256;
+    const int64_t nblk = std::min<int64_t>((a.n + 255) / 256, kFoldBlocks);
     sph_status r;
     switch (s->layout) {
     case 0: r = cfl_l<0>(a, st); break;
