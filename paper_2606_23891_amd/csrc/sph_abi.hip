@@ -1,6 +1,7 @@
 // libsph C-ABI: validation, plan construction, layout queries, store access,
-// and the per-task / batched entry points (the kernels live in sph_pack.hip
-// and sph_interact.hip).
+// and the per-task / batched / offload entry points, the smoothing-length
+// iteration and the time integration (the kernels live in sph_pack.hip,
+// sph_interact.hip and sph_adjoint.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

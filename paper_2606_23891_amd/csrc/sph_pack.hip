@@ -15,6 +15,11 @@
 // by the interaction kernels to skip far tiles.
 // Unpack: per-task results are added (float32, fixed slot order) into the
 // store; the signal velocity keeps the larger value.
+//
+// Also here, as the other kernels that read or write the store directly: the
+// loop-fission passes of pack and unpack (Sec. 3.3), the whole-store layout
+// conversion, the smoothing-length Newton step with its tile compaction, and
+// the kick, drift and time-step kernels of the time integration.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
