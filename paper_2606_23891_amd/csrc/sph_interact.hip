@@ -135,8 +135,7 @@ struct Lds;
 
 template <int WIN, bool CNT>
 struct Lds<0, WIN, CNT> {
-    float4 ph[WIN];  // x y z -|x|^2
-    float m[WIN];
+    float4 ph[WIN];  // x y z m
     uint32_t mask[WIN / 32][64];
 };
 template <int WIN, bool CNT>
@@ -375,8 +374,7 @@ __device__ __forceinline__ void stage_j(const InteractArgs &a, Lds<LOOP, WIN, CN
 {
     const float x = (r.p0.x + tx) - cx, y = (r.p0.y + ty) - cy, z = (r.p0.z + tz) - cz;
     if constexpr (LOOP == 0) {
-        L.ph[k] = make_float4(x, y, z, -fmaf(z, z, fmaf(y, y, x * x)));
-        L.m[k] = r.m;
+        L.ph[k] = make_float4(x, y, z, r.m);
     } else if constexpr (LOOP == 1) {
         L.ph[k] = make_float4(x, y, z, -fmaf(z, z, fmaf(y, y, x * x)));
         L.c1[k] = make_float4(r.p1.x, r.p1.y, r.p1.z, r.p1.w);
@@ -484,8 +482,8 @@ __device__ __forceinline__ void test_words_mfma(Lds<LOOP, WIN, CNT> &L, int nc, 
     for (int w = 0; w < nw; ++w) {
         const int kb = 32 * w;
         float axy, azw;
-        if constexpr (LOOP == 2) {
-            const float4 v = L.ph[kb + slot];  // x y z vx: -|x|^2 rebuilt
+        if constexpr (LOOP != 1) {
+            const float4 v = L.ph[kb + slot];  // x y z vx / m: -|x|^2 rebuilt
             axy = comp ? v.y : v.x;
             azw = comp ? -fmaf(v.z, v.z, fmaf(v.y, v.y, v.x * v.x)) : v.z;
         } else {
@@ -542,7 +540,7 @@ __device__ __forceinline__ Cand<LOOP> cand_load(const Lds<LOOP, WIN, CNT> &L, in
     c.y = p.y;
     c.z = p.z;
     if constexpr (LOOP == 0) {
-        c.m = *(const float *)((const char *)L.m + o4);
+        c.m = p.w;
     } else {
         c.c1 = L.c1[k];
         c.c2 = L.c2[k];
