@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--fission", default=None,
                     help="'all' or comma list of layouts: also time pack + unpack under every "
                          "loop-fission schedule")
+    ap.add_argument("--adjoint", default=None,
+                    help="comma list of lattice sides: also time the adjoint (forward, forward + backward) on "
+                         "the Gresho lattice of that many particles per side")
     ap.add_argument("--kdk", action="store_true",
                     help="also time kick-drift-kick steps (CFL time step) around the loops")
     ap.add_argument("--hiter", action="store_true",
@@ -353,6 +356,9 @@ def main():
         names = sph.LAYOUTS if a.fission == "all" else a.fission.split(",")
         out["fission"] = fission_sweep(ps, plan, names, tuning, a.steps)
 
+    if a.adjoint:
+        out["adjoint"] = [adjoint_bench(int(k)) for k in a.adjoint.split(",")]
+
     if a.kdk:
         out["kdk"] = kdk_bench(ps, plan, tuning, a.layout, a.steps)
 
@@ -462,6 +468,56 @@ def fission_sweep(ps, plan, names, tuning, steps):
             res[name][sname]["vs_by_particle"] = round(res[name][sname]["total_ms"] / base, 4)
         del st
         torch.cuda.empty_cache()
+    return res
+
+
+def adjoint_bench(n_side, reps=5):
+    """forward (accelerations in FP64 from float64 positions) and forward +
+    backward (hand-written adjoint kernels) of the autograd Function, L =
+    sum |a|^2, on the jittered Gresho lattice with a velocity dispersion; the
+    viscosity switch is held at the fields' alpha_v (the adjoint treats it as
+    a constant, so its value does not change the work)"""
+    import numpy as np
+    import torch
+
+    from paper_2606_23891_amd import autograd, inputs, sph
+
+    ps = inputs.make_config(4, n_side=n_side)
+    f = ps.fields
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    T = lambda arr, dt: torch.tensor(np.ascontiguousarray(arr), dtype=dt, device="cuda")
+    ctx = autograd.make_context(plan, T(f["h"], torch.float32), T(f["u"], torch.float32),
+                                T(f["alpha_v"], torch.float32), T(f["alpha_d"], torch.float32))
+    x = T(f["x"], torch.float64).requires_grad_(True)
+    v = T(f["v"], torch.float32).requires_grad_(True)
+    m = T(f["mass"], torch.float32).requires_grad_(True)
+    stream = torch.cuda.current_stream()
+
+    def fwd():
+        with torch.no_grad():
+            return autograd.acceleration(x, v, m, ctx)
+
+    def fwd_bwd():
+        a = autograd.acceleration(x, v, m, ctx)
+        (a.double() ** 2).sum().backward()
+
+    res = {"n": ps.n, "workload": f"gresho-{n_side}^3 lattice, velocity dispersion 0.02"}
+    for name, fn in (("forward_ms", fwd), ("forward_backward_ms", fwd_bwd)):
+        for _ in range(3):   # untimed: a process's first backward passes run slower (one-time set-up)
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = round(e0.elapsed_time(e1) / reps, 3)
+    res["backward_over_forward"] = round((res["forward_backward_ms"] - res["forward_ms"]) / res["forward_ms"], 3)
+    log(f"adjoint {n_side}^3: forward {res['forward_ms']:.2f} ms, forward+backward {res['forward_backward_ms']:.2f} ms")
+    plan.close()
+    del ctx, x, v, m
+    torch.cuda.empty_cache()
     return res
 
 
