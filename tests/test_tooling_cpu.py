@@ -77,3 +77,27 @@ def test_tuning_cache_keys_and_apply(tmp_path, monkeypatch):
     assert t.pack_schedule == 3
     assert list(t.window) == [512, 256, 128] and (t.blocks_per_cu, t.queue, t.pack_waves) == (2, 2, 8)
     assert list(t.blocks_per_loop) == [8, 4, 2]
+
+
+def test_bench_stage_kernel_names():
+    """the kernels the benchmark attributes to each stage (its roofline and
+    traffic lookups use these names), fused and under a fission schedule"""
+    import importlib.util
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    sys.modules["bench_mod"] = bench
+    spec.loader.exec_module(bench)
+    t = types.SimpleNamespace(window=[256, 128, 128], pack_schedule=0)
+    assert bench.stage_kernels("pack_force", 4, t) == ["void sph::k_pack<4, 2>(sph::PackArgs)"]
+    assert bench.stage_kernels("unpack_density", 4, t) == [
+        "void sph::k_unpack_chunks<4, 0, true, false>(sph::UnpackArgs)"]
+    assert bench.stage_kernels("force", 4, t) == ["void sph::k_prep<2>(sph::PrepArgs)",
+                                                  "void sph::k_interact<2, 1, 128, false>(sph::InteractArgs)"]
+    assert bench.stage_kernels("density", 8, t) == ["void sph::k_interact<0, 1, 256, false>(sph::InteractArgs)"]
+    t.pack_schedule = 2
+    assert bench.stage_kernels("pack_gradient", 8, t) == [
+        "void sph::k_pack_pass<8, 1>(sph::PackArgs, unsigned int)"]
+    assert bench.stage_kernels("unpack_force", 8, t) == [
+        "void sph::k_unpack_chunks<8, 2, true, true>(sph::UnpackArgs)"]
