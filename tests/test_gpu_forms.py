@@ -34,18 +34,23 @@ def test_graph_replays_match_eager_step():
     s2 = _snapshot(st2)
     for k in OUT_FIELDS:
         assert np.array_equal(s2[k], ref[k]), k
-    g = sph.Graph(plan, st, ws)
-    for rep in range(4):
-        log(f"graph replay {rep}")
-        st.put("rho", np.zeros(ps.n, np.float32))       # eager work between replays
-        st.put("a", np.full((ps.n, 3), 7.0, np.float32))
-        torch.cuda.synchronize()
-        g.launch()
-        torch.cuda.synchronize()
-        got = _snapshot(st)
-        for k in OUT_FIELDS:
-            assert np.array_equal(got[k], ref[k]), (rep, k)
-    g.close()
+    # the fused kernels and a split schedule (several pack / unpack launches
+    # per loop inside the graph) replay to the same bits
+    for sched in (0, 4):
+        tn = sph.default_tuning()
+        tn.pack_schedule = sched
+        g = sph.Graph(plan, st, ws, tuning=tn)
+        for rep in range(4):
+            log(f"graph replay {rep} schedule {sched}")
+            st.put("rho", np.zeros(ps.n, np.float32))       # eager work between replays
+            st.put("a", np.full((ps.n, 3), 7.0, np.float32))
+            torch.cuda.synchronize()
+            g.launch()
+            torch.cuda.synchronize()
+            got = _snapshot(st)
+            for k in OUT_FIELDS:
+                assert np.array_equal(got[k], ref[k]), (sched, rep, k)
+        g.close()
     plan.close()
 
 

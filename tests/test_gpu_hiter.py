@@ -66,7 +66,7 @@ def test_h_iteration_pass_limit_and_arguments():
     ps = inputs.make_config(0, n_side=16, grid=4)
     h0 = _perturbed(ps, 5)
     plan = sph.Plan(ps.cells, ps.tasks, ps.n)
-    st = device_store(ps, sph.LAYOUTS.index("SOA"), extra={"h": h0})
+    st = device_store(ps, sph.LAYOUTS.index("AOS"), extra={"h": h0})
     ws = torch.zeros(sph.sph_h_iterate_ws_bytes(plan), dtype=torch.uint8, device="cuda")
     log("h iteration, one pass")
     passes, still = sph.sph_h_iterate(plan, st, ws, eta=ETA, tol=TOL, max_iter=1)
