@@ -348,7 +348,7 @@ sph_status sph_h_iterate(const sph_plan *plan, const sph_store *store, const sph
  * cell's cube and the largest h.  sph_cfl_dt: dt = min over particles with
  * V > 0 of (cfl (gamma_K h)) / V, float32 (V the signal velocity of the last
  * gradient loop; +inf if none), synchronises `stream`.  sph_step_kdk: kick by
- * dt/2, drift by dt, then -- if gamma_K max h + 2 max_outside does not exceed
+ * dt/2 and drift by dt (one pass over the particles), then -- if gamma_K max h + 2 max_outside does not exceed
  * the narrowest cell, so every pair within a support still meets in adjacent
  * cells -- density, gradient and force (sph_step_batched) and a second kick by
  * dt/2; otherwise it stops after the drift with *rebuild = 1 and SPH_E_PLAN:

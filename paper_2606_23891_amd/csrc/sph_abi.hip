@@ -1010,8 +1010,8 @@ sph_status sph_step_kdk(const sph_plan *p, const sph_store *store, const sph_par
     const hipStream_t st = (hipStream_t)stream;
     void *iws = (char *)ws + step_ws;
     const float half = 0.5f * dt;
-    if ((s = launch_kick(store, half, st))) return s;
-    if ((s = launch_drift(p, store, (double)dt, iws, st))) return s;
+    // the first half kick and the drift in one pass over the particles
+    if ((s = launch_drift(p, store, (double)dt, iws, st, true, half))) return s;
     double r[2];
     if ((s = read_fold(p, iws, r, st))) return s;
     // every pair within a support must still meet in adjacent cells:

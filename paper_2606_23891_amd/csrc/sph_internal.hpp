@@ -227,7 +227,10 @@ sph_status launch_flagged_tiles(const sph_plan *p, const int32_t *flags, int32_t
 // the CFL step (result [unused, smallest dt])
 size_t integrate_ws_bytes(const sph_plan *p);
 sph_status launch_kick(const sph_store *s, float dt, hipStream_t st);
-sph_status launch_drift(const sph_plan *p, const sph_store *s, double dt, void *ws, hipStream_t st);
+// kick: the kick by kick_dt first, in the same pass (as launch_kick, then the
+// drift)
+sph_status launch_drift(const sph_plan *p, const sph_store *s, double dt, void *ws, hipStream_t st,
+                        bool kick = false, float kick_dt = 0.0f);
 sph_status launch_cfl(const sph_plan *p, const sph_store *s, float cfl, void *ws, hipStream_t st);
 // the fission groups of a layout's pack (unpack) members: bit masks as in
 // sph_fission_passes, returned count (0 for an unknown layout)

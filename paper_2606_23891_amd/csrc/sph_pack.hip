@@ -837,6 +837,8 @@ struct DriftArgs {
     double dt;
     double *blk_out;  // per block: largest distance of a particle outside its cell
     float *blk_h;     // per block: largest h
+    float kick_dt;    // KICK: the kick before the drift (v, u += a, u_dt times this)
+    int kick;
 };
 
 __device__ __forceinline__ double wave_max_d(double v)
@@ -858,8 +860,9 @@ __device__ __forceinline__ float wave_min_f(float v)
 // x += v dt in float64 (v widened exactly), one wave per tile, the waves
 // striding over the tiles (a bounded grid keeps the per-block partials few);
 // the distance by which the drifted particle lies outside its cell's cube, in
-// float64
-template <int L>
+// float64.  KICK: the half kick of a kick-drift-kick step first, in the same
+// pass (the same operations as k_kick, then the drift with the kicked v).
+template <int L, bool KICK>
 __global__ __launch_bounds__(256) void k_drift(DriftArgs a)
 {
     __shared__ double so[4];
@@ -873,11 +876,20 @@ __global__ __launch_bounds__(256) void k_drift(DriftArgs a)
         if (lane < ch.n) {
             const int64_t p = ch.part0 + lane;
             const sph_cell &cl = a.cells[ch.cell];
+            if constexpr (KICK) {
+                const float u = ld<L, FU, 0, float>(a.store, p), udt = ld<L, FUDT, 0, float>(a.store, p);
+                st<L, FU, 0, float>(a.store, p, u + udt * a.kick_dt);
+            }
             double e2 = 0.0;
             static_for<0, 3>([&](auto cc) {
                 constexpr int C = decltype(cc)::value;
+                float v = ld<L, FV, C, float>(a.store, p);
+                if constexpr (KICK) {
+                    v = v + ld<L, FA, C, float>(a.store, p) * a.kick_dt;
+                    st<L, FV, C, float>(a.store, p, v);
+                }
                 const double x = ld<L, FX, C, double>(a.store, p);
-                const double xn = x + (double)ld<L, FV, C, float>(a.store, p) * a.dt;
+                const double xn = x + (double)v * a.dt;
                 st<L, FX, C, double>(a.store, p, xn);
                 const double e = fmax(fmax(cl.loc[C] - xn, xn - (cl.loc[C] + cl.width)), 0.0);
                 e2 = e2 + e * e;
@@ -965,8 +977,9 @@ constexpr int64_t kFoldBlocks = 2048;
 template <int L>
 static sph_status drift_l(const DriftArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_drift<L>), dim3((unsigned)std::min<int64_t>((a.ntile + 3) / 4, kFoldBlocks)), dim3(256), 0,
-                       st, a);
+    const dim3 grid((unsigned)std::min<int64_t>((a.ntile + 3) / 4, kFoldBlocks));
+    if (a.kick) hipLaunchKernelGGL((k_drift<L, true>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_drift<L, false>), grid, dim3(256), 0, st, a);
     SPH_CHECK_LAUNCH("drift launch");
     return SPH_OK;
 }
@@ -1136,10 +1149,13 @@ sph_status launch_kick(const sph_store *s, float dt, hipStream_t st)
     SPH_BY_LAYOUT(s->layout, kick_l, a, st);
 }
 
-sph_status launch_drift(const sph_plan *p, const sph_store *s, double dt, void *ws, hipStream_t st)
+sph_status launch_drift(const sph_plan *p, const sph_store *s, double dt, void *ws, hipStream_t st, bool kick,
+                        float kick_dt)
 {
     const size_t nb = fold_blocks(p);
     DriftArgs a{};
+    a.kick = kick ? 1 : 0;
+    a.kick_dt = kick_dt;
     a.store = store_arg(s);
     a.tiles = p->d_tiles;
     a.cells = p->d_cells;
