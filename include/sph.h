@@ -405,30 +405,38 @@ sph_status sph_offload_step_async(const sph_plan *plan, const sph_store *host, c
                                   void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------- */
-/* Adjoint of L = sum_i |a_i|^2 through density and force (hand-written).   */
+/* Adjoint of L = sum_i |a_i|^2 through density and force (hand-written),   */
+/* the differentiable form of the loops of Sec. 2.1.                        */
 /* The artificial-viscosity switch alpha~ = alpha_v B and alpha_d are held  */
-/* fixed; h and u are constants.  Density is recomputed in backward.        */
-/* Inputs are per-particle device arrays in store order:                    */
-/*   x float64[n][3], v float32[n][3], m, h, u, atilde, alpha_d float32[n].  */
+/* fixed; h and u are constants.  Inputs are per-particle device arrays in  */
+/* store order: x float64[n][3], v float32[n][3], m, h, u, atilde, alpha_d  */
+/* float32[n].  Arithmetic is float64, since a and the small components   */
+/* of the gradient are sums of nearly cancelling pair terms, and the        */
+/* outputs are float64.  The plan's cells must tile the store in order; */
+/* ws (sph_adjoint_ws_bytes, 256-byte aligned) is scratch overwritten by    */
+/* every call.  All calls are asynchronous on `stream`.                     */
 /* ---------------------------------------------------------------------- */
-/* Forward: rho, rho_dh (float32[n]) and a (float32[n][3]), u_dt (float32[n]). */
+/* Forward: rho, rho_dh (float64[n]), a (float64[n][3]), u_dt (float64[n]). */
 sph_status sph_adjoint_forward(const sph_plan *plan, const double *x, const float *v, const float *m,
                                const float *h, const float *u, const float *atilde,
-                               const float *alpha_d, const sph_params *params, float *rho,
-                               float *rho_dh, float *a, float *u_dt, void *ws, size_t ws_bytes,
+                               const float *alpha_d, const sph_params *params, double *rho,
+                               double *rho_dh, double *a, double *u_dt, void *ws, size_t ws_bytes,
                                void *stream);
-/* Backward of force: given a_bar = dL/da (float32[n][3]), writes dL/dx,
- * dL/dv, dL/dm contributions (float32, overwritten) and rho_bar, rhodh_bar. */
+/* Backward of force: given a_bar = dL/da (float64[n][3]), recomputes the
+ * density of x (pair terms and densities are never stored between calls) and
+ * writes (overwrites) the force loop's contributions to dL/dx (float64[n][3]),
+ * dL/dv (float64[n][3]) and dL/dm (float64[n]), and rho_bar = dL/drho,
+ * rhodh_bar = dL/drho_dh (float64[n]). */
 sph_status sph_force_adjoint(const sph_plan *plan, const double *x, const float *v, const float *m,
                              const float *h, const float *u, const float *atilde,
-                             const float *alpha_d, const float *rho, const float *rho_dh,
-                             const sph_params *params, const float *a_bar, float *x_bar, float *v_bar,
-                             float *m_bar, float *rho_bar, float *rhodh_bar, void *ws,
-                             size_t ws_bytes, void *stream);
-/* Backward of density: accumulates (+=) dL/dx and dL/dm from rho_bar, rhodh_bar. */
+                             const float *alpha_d, const sph_params *params, const double *a_bar,
+                             double *x_bar, double *v_bar, double *m_bar, double *rho_bar,
+                             double *rhodh_bar, void *ws, size_t ws_bytes, void *stream);
+/* Backward of density: accumulates (+=) dL/dx and dL/dm (float64) from
+ * rho_bar, rhodh_bar. */
 sph_status sph_density_adjoint(const sph_plan *plan, const double *x, const float *m, const float *h,
-                               const float *rho_bar, const float *rhodh_bar, float *x_bar,
-                               float *m_bar, void *ws, size_t ws_bytes, void *stream);
+                               const double *rho_bar, const double *rhodh_bar, double *x_bar,
+                               double *m_bar, void *ws, size_t ws_bytes, void *stream);
 /* Workspace of the three adjoint calls. */
 sph_status sph_adjoint_ws_bytes(const sph_plan *plan, size_t *bytes);
 

@@ -60,10 +60,14 @@ def lib():
     for name in ("or_W", "or_dWdh", "or_F", "or_dWdr", "or_d2Wdhdr", "or_dFdr"):
         getattr(L, name).restype = d
         getattr(L, name).argtypes = [d, d]
-    L.or_density.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
-    L.or_gradient.argtypes = [i64, vp, vp, vp, vp, vp, vp, d, d, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.or_density.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.or_gradient.argtypes = [i64, vp, vp, vp, vp, vp, vp, d, d, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                              vp]
     L.or_force.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, d, d, i64, vp, vp,
-                           vp, vp, vp, vp, vp, vp]
+                           vp, vp, vp, vp, vp, vp, vp]
+    L.or_grid_build.argtypes = [i64, vp, d]
+    L.or_grid_build.restype = vp
+    L.or_grid_free.argtypes = [vp]
     L.or_balsara.argtypes = [i64, vp, vp, vp, vp, vp, vp, d, d, vp]
     L.or_layout_info.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(sz)]
     L.or_field_location.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(sz),
@@ -101,10 +105,32 @@ def _eps(epsx):
     return None if epsx is None else _c(epsx, np.float64)
 
 
-def density(x, m, h, rows=None, epsx=None) -> Dict[str, np.ndarray]:
+class _Grid:
+    """Candidate grid for a loop call (grid=True): cells at least as wide as
+    the largest support (with the edge band's margin), so the loops skip only
+    particles that cannot interact; None when the box holds fewer than 3
+    cells per side (the loops then visit every particle)."""
+
+    def __init__(self, use: bool, x: np.ndarray, h: np.ndarray, epsx):
+        self.ptr = None
+        if use and x.shape[0]:
+            reach = 1.0001 * GAMMA_K * float(np.max(h)) + (0.0 if epsx is None else 2.0 * float(np.max(epsx)))
+            self.ptr = lib().or_grid_build(x.shape[0], _p(x), reach)
+
+    def __enter__(self):
+        return self.ptr
+
+    def __exit__(self, *exc):
+        if self.ptr:
+            lib().or_grid_free(self.ptr)
+
+
+def density(x, m, h, rows=None, epsx=None, grid=False) -> Dict[str, np.ndarray]:
     """FP64 density sums.  S: arithmetic error scale; P: position error scale for
     the per-particle position resolution epsx (0 when epsx is None); band: pairs
-    whose distance to the support edge is within 1e-6 H + epsx_i + epsx_j."""
+    whose distance to the support edge is within 1e-6 H + epsx_i + epsx_j.
+    grid=True visits candidates from a uniform grid instead of every particle
+    (same results, bit for bit)."""
     L = lib()
     x = _c(x, np.float64); m = _c(m, np.float32); h = _c(h, np.float32)
     n = x.shape[0]
@@ -113,13 +139,15 @@ def density(x, m, h, rows=None, epsx=None) -> Dict[str, np.ndarray]:
     out = {k: np.zeros(nr) for k in ("rho", "rho_dh", "wcount")}
     S = np.zeros((nr, 3)); P = np.zeros((nr, 3)); cnt = np.zeros(nr, np.int32); band = np.zeros(nr, np.int32)
     epsx = _eps(epsx)
-    L.or_density(n, _p(x), _p(m), _p(h), nr, _p(rows), _p(epsx), _p(out["rho"]), _p(out["rho_dh"]),
-                 _p(out["wcount"]), _p(S), _p(P), _p(cnt), _p(band))
+    with _Grid(grid, x, h, epsx) as g:
+        L.or_density(n, _p(x), _p(m), _p(h), nr, _p(rows), _p(epsx), _p(out["rho"]), _p(out["rho_dh"]),
+                     _p(out["wcount"]), _p(S), _p(P), _p(cnt), _p(band), g)
     out.update(S=S, P=P, count=cnt, band=band)
     return out
 
 
-def gradient(x, v, m, h, u, rho, rows=None, gamma=GAMMA_AD, beta=BETA_VISC, epsx=None) -> Dict[str, np.ndarray]:
+def gradient(x, v, m, h, u, rho, rows=None, gamma=GAMMA_AD, beta=BETA_VISC, epsx=None,
+             grid=False) -> Dict[str, np.ndarray]:
     L = lib()
     x = _c(x, np.float64); v = _c(v, np.float32); m = _c(m, np.float32); h = _c(h, np.float32)
     u = _c(u, np.float32); rho = _c(rho, np.float64)
@@ -129,13 +157,14 @@ def gradient(x, v, m, h, u, rho, rows=None, gamma=GAMMA_AD, beta=BETA_VISC, epsx
     D = np.zeros(nr); R = np.zeros((nr, 3)); Lp = np.zeros(nr); V = np.zeros(nr)
     S = np.zeros((nr, 5)); P = np.zeros((nr, 5)); cnt = np.zeros(nr, np.int32); band = np.zeros(nr, np.int32)
     epsx = _eps(epsx)
-    L.or_gradient(n, _p(x), _p(v), _p(m), _p(h), _p(u), _p(rho), gamma, beta, nr, _p(rows), _p(epsx),
-                  _p(D), _p(R), _p(Lp), _p(V), _p(S), _p(P), _p(cnt), _p(band))
+    with _Grid(grid, x, h, epsx) as g:
+        L.or_gradient(n, _p(x), _p(v), _p(m), _p(h), _p(u), _p(rho), gamma, beta, nr, _p(rows), _p(epsx),
+                      _p(D), _p(R), _p(Lp), _p(V), _p(S), _p(P), _p(cnt), _p(band), g)
     return {"div_v": D, "rot_v": R, "lap_u": Lp, "v_sig": V, "S": S, "P": P, "count": cnt, "band": band}
 
 
 def force(x, v, m, h, u, rho, rho_dh, D, R, alpha_v, alpha_d, atilde=None, rows=None,
-          gamma=GAMMA_AD, beta=BETA_VISC, eps=BALSARA_EPS, epsx=None) -> Dict[str, np.ndarray]:
+          gamma=GAMMA_AD, beta=BETA_VISC, eps=BALSARA_EPS, epsx=None, grid=False) -> Dict[str, np.ndarray]:
     L = lib()
     x = _c(x, np.float64); v = _c(v, np.float32); m = _c(m, np.float32); h = _c(h, np.float32)
     u = _c(u, np.float32); rho = _c(rho, np.float64); rho_dh = _c(rho_dh, np.float64)
@@ -148,9 +177,10 @@ def force(x, v, m, h, u, rho, rho_dh, D, R, alpha_v, alpha_d, atilde=None, rows=
     a = np.zeros((nr, 3)); udt = np.zeros(nr); S = np.zeros((nr, 4)); P = np.zeros((nr, 4))
     cnt = np.zeros(nr, np.int32); band = np.zeros(nr, np.int32)
     epsx = _eps(epsx)
-    L.or_force(n, _p(x), _p(v), _p(m), _p(h), _p(u), _p(rho), _p(rho_dh), _p(D), _p(R),
-               _p(alpha_v), _p(alpha_d), _p(atilde), gamma, beta, eps, nr, _p(rows), _p(epsx),
-               _p(a), _p(udt), _p(S), _p(P), _p(cnt), _p(band))
+    with _Grid(grid, x, h, epsx) as g:
+        L.or_force(n, _p(x), _p(v), _p(m), _p(h), _p(u), _p(rho), _p(rho_dh), _p(D), _p(R),
+                   _p(alpha_v), _p(alpha_d), _p(atilde), gamma, beta, eps, nr, _p(rows), _p(epsx),
+                   _p(a), _p(udt), _p(S), _p(P), _p(cnt), _p(band), g)
     return {"a": a, "u_dt": udt, "S": S, "P": P, "count": cnt, "band": band}
 
 

@@ -7,7 +7,10 @@
  *
  * Everything here is the plain definition, evaluated slowly and obviously:
  *   - interaction loops are O(N^2) brute force over all particles with the
- *     minimum-image convention in the periodic unit box, in FP64;
+ *     minimum-image convention in the periodic unit box, in FP64; an optional
+ *     uniform grid only skips particles beyond a given reach (it hands the
+ *     loop the same j in the same ascending order, minus ones that cannot
+ *     interact), so its results are those of the brute force bit for bit;
  *   - pack / unpack walk tasks, cells and particles in order, one field at a
  *     time, through the oracle's own particle-layout tables.
  *
@@ -111,6 +114,94 @@ static inline double mi(double d)
     return d;
 }
 
+
+/* ------------------------------------------------------------------------ */
+/* Optional candidate grid.  Cells of width >= reach over the unit box; the  */
+/* candidates of particle i are the particles of the 27 cells around its    */
+/* own, sorted ascending, so a loop visits them in the brute-force order.   */
+/* Every j within reach of i (minimum image) is among them.  With fewer     */
+/* than 3 cells per side there is no grid (NULL): the loops then visit all  */
+/* j.                                                                        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t G;
+    int64_t *start; /* G^3 + 1 offsets into idx */
+    int64_t *idx;   /* particle indices grouped by cell, ascending in a cell */
+    int64_t maxc;   /* most particles in one cell */
+} or_grid;
+
+static int64_t grid_axis(double xv, int64_t G)
+{
+    double w = xv - floor(xv);
+    int64_t c = (int64_t)(w * (double)G);
+    return c < 0 ? 0 : (c >= G ? G - 1 : c);
+}
+
+void *or_grid_build(int64_t n, const double *x, double reach)
+{
+    if (!(reach > 0.0)) return NULL;
+    int64_t G = (int64_t)floor(1.0 / reach);
+    if (G < 3) return NULL;
+    if (G > 1024) G = 1024;
+    or_grid *g = (or_grid *)calloc(1, sizeof(or_grid));
+    int64_t nc = G * G * G;
+    g->G = G;
+    g->start = (int64_t *)calloc((size_t)nc + 1, sizeof(int64_t));
+    g->idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *cell = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; i++) {
+        cell[i] = (grid_axis(x[3 * i + 2], G) * G + grid_axis(x[3 * i + 1], G)) * G + grid_axis(x[3 * i], G);
+        g->start[cell[i] + 1]++;
+    }
+    g->maxc = 0;
+    for (int64_t c = 0; c < nc; c++) {
+        if (g->start[c + 1] > g->maxc) g->maxc = g->start[c + 1];
+        g->start[c + 1] += g->start[c];
+    }
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)nc);
+    memcpy(fill, g->start, sizeof(int64_t) * (size_t)nc);
+    for (int64_t i = 0; i < n; i++) g->idx[fill[cell[i]]++] = i; /* ascending within a cell */
+    free(fill);
+    free(cell);
+    return g;
+}
+
+void or_grid_free(void *p)
+{
+    or_grid *g = (or_grid *)p;
+    if (!g) return;
+    free(g->start);
+    free(g->idx);
+    free(g);
+}
+
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t u = *(const int64_t *)a, v = *(const int64_t *)b;
+    return (u > v) - (u < v);
+}
+
+/* candidates of particle i into buf (room for 27 maxc); returns the count */
+static int64_t grid_cands(const or_grid *g, const double *x, int64_t i, int64_t *buf)
+{
+    const int64_t G = g->G;
+    const int64_t cx = grid_axis(x[3 * i], G), cy = grid_axis(x[3 * i + 1], G), cz = grid_axis(x[3 * i + 2], G);
+    int64_t nb = 0;
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                int64_t c = (((cz + dz + G) % G) * G + (cy + dy + G) % G) * G + (cx + dx + G) % G;
+                for (int64_t t = g->start[c]; t < g->start[c + 1]; t++) buf[nb++] = g->idx[t];
+            }
+    qsort(buf, (size_t)nb, sizeof(int64_t), cmp_i64);
+    return nb;
+}
+
+static int64_t *cand_buffer(const or_grid *g)
+{
+    return g ? (int64_t *)malloc(sizeof(int64_t) * (size_t)(27 * g->maxc + 1)) : NULL;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Density loop: over all j including i with r < H_i                         */
 /*   rho_i = sum m_j W(r, h_i);  rho_dh_i = sum m_j dW/dh(r, h_i);            */
@@ -124,16 +215,22 @@ static inline double mi(double d)
 void or_density(int64_t n, const double *x, const float *m, const float *h,
                 int64_t nrow, const int64_t *rows,
                 const double *epsx, double *rho, double *rho_dh, double *wcount, double *S, double *P,
-                int32_t *cnt, int32_t *band)
+                int32_t *cnt, int32_t *band, const void *grid)
 {
     int64_t nr = rows ? nrow : n;
-#pragma omp parallel for schedule(dynamic, 16)
+    const or_grid *g = (const or_grid *)grid;
+#pragma omp parallel
+    {
+    int64_t *cand = cand_buffer(g);
+#pragma omp for schedule(dynamic, 16)
     for (int64_t k = 0; k < nr; k++) {
         int64_t i = rows ? rows[k] : k;
         double H = OR_GAMMA_K * (double)h[i];
         double sr = 0, sd = 0, sw = 0, s0 = 0, s1 = 0, s2 = 0, q0 = 0, q1 = 0, q2 = 0;
         int32_t c = 0, b = 0;
-        for (int64_t j = 0; j < n; j++) {
+        int64_t nc = g ? grid_cands(g, x, i, cand) : n;
+        for (int64_t t = 0; t < nc; t++) {
+            int64_t j = g ? cand[t] : t;
             double dx = mi(x[3 * i] - x[3 * j]);
             double dy = mi(x[3 * i + 1] - x[3 * j + 1]);
             double dz = mi(x[3 * i + 2] - x[3 * j + 2]);
@@ -162,6 +259,8 @@ void or_density(int64_t n, const double *x, const float *m, const float *h,
         if (cnt) cnt[k] = c;
         if (band) band[k] = b;
     }
+    free(cand);
+    }
 }
 
 /* per-particle quantities every consumer derives from the stored ones */
@@ -178,10 +277,14 @@ void or_gradient(int64_t n, const double *x, const float *v, const float *m, con
                  const float *u, const double *rhoj, double gam, double beta,
                  int64_t nrow, const int64_t *rows, const double *epsx,
                  double *D, double *R, double *L, double *V, double *S, double *P, int32_t *cnt,
-                 int32_t *band)
+                 int32_t *band, const void *grid)
 {
     int64_t nr = rows ? nrow : n;
-#pragma omp parallel for schedule(dynamic, 16)
+    const or_grid *g = (const or_grid *)grid;
+#pragma omp parallel
+    {
+    int64_t *cand = cand_buffer(g);
+#pragma omp for schedule(dynamic, 16)
     for (int64_t k = 0; k < nr; k++) {
         int64_t i = rows ? rows[k] : k;
         double H = OR_GAMMA_K * (double)h[i];
@@ -190,7 +293,9 @@ void or_gradient(int64_t n, const double *x, const float *v, const float *m, con
         double ad = 0, ar0 = 0, ar1 = 0, ar2 = 0, al = 0;
         double pd = 0, pr0 = 0, pr1 = 0, pr2 = 0, pl = 0;
         int32_t c = 0, b = 0;
-        for (int64_t j = 0; j < n; j++) {
+        int64_t nc = g ? grid_cands(g, x, i, cand) : n;
+        for (int64_t t = 0; t < nc; t++) {
+            int64_t j = g ? cand[t] : t;
             if (j == i) continue;
             double rx = mi(x[3 * i] - x[3 * j]);
             double ry = mi(x[3 * i + 1] - x[3 * j + 1]);
@@ -236,6 +341,8 @@ void or_gradient(int64_t n, const double *x, const float *v, const float *m, con
         if (P) { P[5 * k] = pd; P[5 * k + 1] = pr0; P[5 * k + 2] = pr1; P[5 * k + 3] = pr2; P[5 * k + 4] = pl; }
         if (cnt) cnt[k] = c;
         if (band) band[k] = b;
+    }
+    free(cand);
     }
 }
 
@@ -298,21 +405,28 @@ void or_force(int64_t n, const double *x, const float *v, const float *m, const 
               const float *u, const double *rho, const double *rho_dh, const double *D,
               const double *R, const float *alpha_v, const float *alpha_d, const double *atilde,
               double gam, double beta, double eps, int64_t nrow, const int64_t *rows, const double *epsx,
-              double *acc, double *udt, double *S, double *P, int32_t *cnt, int32_t *band)
+              double *acc, double *udt, double *S, double *P, int32_t *cnt, int32_t *band,
+              const void *grid)
 {
+    const or_grid *g = (const or_grid *)grid;
     int64_t nr = rows ? nrow : n;
     or_pp *pp = (or_pp *)malloc(sizeof(or_pp) * (size_t)n);
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < n; j++)
         pp[j] = per_particle(j, h, u, rho, rho_dh, D, R, alpha_v, alpha_d, atilde, gam, eps);
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel
+    {
+    int64_t *cand = cand_buffer(g);
+#pragma omp for schedule(dynamic, 16)
     for (int64_t k = 0; k < nr; k++) {
         int64_t i = rows ? rows[k] : k;
         or_pp pi = pp[i];
         double a0 = 0, a1 = 0, a2 = 0, du = 0;
         double s0 = 0, s1 = 0, s2 = 0, sd = 0, q0 = 0, q1 = 0, q2 = 0, qd = 0;
         int32_t c = 0, b = 0;
-        for (int64_t j = 0; j < n; j++) {
+        int64_t nc = g ? grid_cands(g, x, i, cand) : n;
+        for (int64_t t = 0; t < nc; t++) {
+            int64_t j = g ? cand[t] : t;
             if (j == i) continue;
             or_pp pj = pp[j];
             double rx = mi(x[3 * i] - x[3 * j]);
@@ -379,6 +493,8 @@ void or_force(int64_t n, const double *x, const float *v, const float *m, const 
         if (P) { P[4 * k] = q0; P[4 * k + 1] = q1; P[4 * k + 2] = q2; P[4 * k + 3] = qd; }
         if (cnt) cnt[k] = c;
         if (band) band[k] = b;
+    }
+    free(cand);
     }
     free(pp);
 }

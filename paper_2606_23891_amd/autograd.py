@@ -1,9 +1,10 @@
 """torch.autograd.Function over the hand-written SPH adjoint kernels.
 
 ``acceleration(x, v, m, ...)`` returns the force loop's accelerations a(x, v, m)
-with the density recomputed inside; its backward calls the HIP adjoint
-kernels (force adjoint, then density adjoint) through the C-ABI.  h, u, the
-viscosity switch alpha~ and alpha_d are constants.  All arithmetic runs in the
+(float64) with the density computed inside; its backward calls the HIP adjoint
+kernels (force adjoint, which recomputes the density, then density adjoint)
+through the C-ABI.  h, u, the viscosity switch alpha~ and alpha_d are
+constants.  All arithmetic runs in the
 library's kernels; this module only allocates tensors and marshals pointers.
 """
 from __future__ import annotations
@@ -35,10 +36,10 @@ def _p(t):
 def adjoint_forward(ctx: _Ctx, x, v, m):
     n = x.shape[0]
     dev = x.device
-    rho = torch.empty(n, dtype=torch.float32, device=dev)
-    rdh = torch.empty(n, dtype=torch.float32, device=dev)
-    a = torch.empty(n, 3, dtype=torch.float32, device=dev)
-    udt = torch.empty(n, dtype=torch.float32, device=dev)
+    rho = torch.empty(n, dtype=torch.float64, device=dev)
+    rdh = torch.empty(n, dtype=torch.float64, device=dev)
+    a = torch.empty(n, 3, dtype=torch.float64, device=dev)
+    udt = torch.empty(n, dtype=torch.float64, device=dev)
     L = sph.lib()
     sph._check(L.sph_adjoint_forward(ctx.plan.ptr, _p(x), _p(v), _p(m), _p(ctx.h), _p(ctx.u), _p(ctx.atilde),
                                      _p(ctx.alpha_d), C.byref(ctx.params), _p(rho), _p(rdh), _p(a), _p(udt),
@@ -46,20 +47,20 @@ def adjoint_forward(ctx: _Ctx, x, v, m):
     return a, rho, rdh, udt
 
 
-def adjoint_backward(ctx: _Ctx, x, v, m, rho, rdh, a_bar):
+def adjoint_backward(ctx: _Ctx, x, v, m, a_bar):
     n = x.shape[0]
     dev = x.device
-    xb = torch.empty(n, 3, dtype=torch.float32, device=dev)
-    vb = torch.empty(n, 3, dtype=torch.float32, device=dev)
-    mb = torch.empty(n, dtype=torch.float32, device=dev)
-    rb = torch.empty(n, dtype=torch.float32, device=dev)
-    db = torch.empty(n, dtype=torch.float32, device=dev)
-    a_bar = a_bar.contiguous().to(torch.float32)
+    xb = torch.empty(n, 3, dtype=torch.float64, device=dev)
+    vb = torch.empty(n, 3, dtype=torch.float64, device=dev)
+    mb = torch.empty(n, dtype=torch.float64, device=dev)
+    rb = torch.empty(n, dtype=torch.float64, device=dev)
+    db = torch.empty(n, dtype=torch.float64, device=dev)
+    a_bar = a_bar.contiguous().to(torch.float64)
     L = sph.lib()
     sph._check(L.sph_force_adjoint(ctx.plan.ptr, _p(x), _p(v), _p(m), _p(ctx.h), _p(ctx.u), _p(ctx.atilde),
-                                   _p(ctx.alpha_d), _p(rho), _p(rdh), C.byref(ctx.params), _p(a_bar), _p(xb),
-                                   _p(vb), _p(mb), _p(rb), _p(db), _p(ctx.ws), ctx.ws.numel(),
-                                   sph._stream(None)), "sph_force_adjoint")
+                                   _p(ctx.alpha_d), C.byref(ctx.params), _p(a_bar), _p(xb), _p(vb), _p(mb),
+                                   _p(rb), _p(db), _p(ctx.ws), ctx.ws.numel(), sph._stream(None)),
+               "sph_force_adjoint")
     sph._check(L.sph_density_adjoint(ctx.plan.ptr, _p(x), _p(m), _p(ctx.h), _p(rb), _p(db), _p(xb), _p(mb),
                                      _p(ctx.ws), ctx.ws.numel(), sph._stream(None)), "sph_density_adjoint")
     return xb, vb, mb
@@ -71,15 +72,15 @@ class SphAcceleration(torch.autograd.Function):
         x = x.contiguous()
         v = v.contiguous()
         m = m.contiguous()
-        a, rho, rdh, _ = adjoint_forward(ctx, x, v, m)
-        fctx.save_for_backward(x, v, m, rho, rdh)
+        a, _, _, _ = adjoint_forward(ctx, x, v, m)
+        fctx.save_for_backward(x, v, m)
         fctx.sph = ctx
         return a
 
     @staticmethod
     def backward(fctx, a_bar):
-        x, v, m, rho, rdh = fctx.saved_tensors
-        xb, vb, mb = adjoint_backward(fctx.sph, x, v, m, rho, rdh, a_bar)
+        x, v, m = fctx.saved_tensors
+        xb, vb, mb = adjoint_backward(fctx.sph, x, v, m, a_bar)
         return xb.to(x.dtype), vb.to(v.dtype), mb.to(m.dtype), None
 
 

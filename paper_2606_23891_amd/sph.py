@@ -106,8 +106,7 @@ _SIGS = {
     "sph_offload_step_async": ([vp, vp, vp, vp, vp, i32, vp, sz, vp], i32),
     "sph_adjoint_ws_bytes": ([vp, C.POINTER(sz)], i32),
     "sph_adjoint_forward": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp], i32),
-    "sph_force_adjoint": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz,
-                           vp], i32),
+    "sph_force_adjoint": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp], i32),
     "sph_density_adjoint": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp], i32),
 }
 

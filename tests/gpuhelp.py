@@ -63,6 +63,19 @@ def slot_particles(plan: sph.Plan, t0: int, t1: int) -> np.ndarray:
     return np.concatenate(out) if out else np.zeros(0, np.int64)
 
 
+def bench_tuning(ps, layout_name: str):
+    """the launch parameters the benchmark takes for this workload and store
+    layout on this device (its tuning-cache entry), else the defaults"""
+    import torch
+
+    from paper_2606_23891_amd import tune
+    t = sph.default_tuning()
+    entry = tune.load(tune.device_key(torch.cuda.get_device_properties(0)), tune.signature(ps, layout_name))
+    if entry:
+        tune.apply(t, entry)
+    return t, entry is not None
+
+
 def run_batched_loop(plan: sph.Plan, store: sph.Store, loop: int, tuning=None, counts: bool = False):
     import torch
     pack, res = sph.cell_buffers(plan, loop)
@@ -98,20 +111,25 @@ def scaled_error(gpu: np.ndarray, ref: np.ndarray, S: np.ndarray, P=None) -> flo
     return float(e.max()) if e.size else 0.0
 
 
-def oracle_loop(ps_fields: dict, loop: int, prev: dict, rows=None, epsx=None) -> dict:
+def oracle_loop(ps_fields: dict, loop: int, prev: dict, rows=None, epsx=None, grid=False) -> dict:
     f = ps_fields
     if loop == 0:
-        return oracle.density(f["x"], f["mass"], f["h"], rows=rows, epsx=epsx)
+        return oracle.density(f["x"], f["mass"], f["h"], rows=rows, epsx=epsx, grid=grid)
     if loop == 1:
-        return oracle.gradient(f["x"], f["v"], f["mass"], f["h"], f["u"], prev["rho"], rows=rows, epsx=epsx)
+        return oracle.gradient(f["x"], f["v"], f["mass"], f["h"], f["u"], prev["rho"], rows=rows, epsx=epsx,
+                               grid=grid)
     return oracle.force(f["x"], f["v"], f["mass"], f["h"], f["u"], prev["rho"], prev["rho_dh"],
-                        prev["div_v"], prev["rot_v"], f["alpha_v"], f["alpha_d"], rows=rows, epsx=epsx)
+                        prev["div_v"], prev["rot_v"], f["alpha_v"], f["alpha_d"], rows=rows, epsx=epsx,
+                        grid=grid)
 
 
-def compare_loop(loop: int, gpu: dict, ref: dict, rows=None) -> dict:
-    """scaled errors per output (rows: the sampled particles the oracle computed)"""
+def compare_loop(loop: int, gpu: dict, ref: dict, rows=None, plain: bool = False) -> dict:
+    """scaled errors per output (rows: the sampled particles the oracle computed);
+    plain=True leaves out the position scale P: |q_gpu - q_ref| / max(|q_ref|, S)"""
     sel = (lambda a: a) if rows is None else (lambda a: a[rows])
     S, P = ref["S"], ref["P"]
+    if plain:
+        P = np.zeros_like(P)
     errs = {}
     if loop == 0:
         errs["rho"] = scaled_error(sel(gpu["rho"]), ref["rho"], S[:, 0], P[:, 0])

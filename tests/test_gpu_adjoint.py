@@ -3,12 +3,11 @@ against FP64 central finite differences of the oracle's loss on 64 sampled
 coordinates and against the FP64 torch reference gradient, on the 32^3
 jittered Gresho lattice.
 
-e = |g - g_ref| / max(|g_ref|, FLOOR * rms(g_ref over that input kind)) <= 1e-4
-with FLOOR = 1e-2: the backward kernels run in FP32, and a component that is
-small against its input kind's rms is a sum of per-pair FP32 terms that cancel;
-an FP32 emulation of these kernels reaches 4e-5 at this floor and 2e-4 at
-1e-3 (on 0.07 % of the components).  The norm-wise error and the 1e-3-floor
-figure are logged beside it."""
+e = |g - g_ref| / max(|g_ref|, 1e-3 * rms(g_ref over that input kind)) <= 1e-4.
+The kernels compute in FP64 (components small against their kind's rms are
+sums of nearly cancelling pair terms); v.grad and m.grad come back in the
+float32 of v and m, one rounding of the final value.  The norm-wise error is
+logged beside it."""
 import numpy as np
 import pytest
 
@@ -20,7 +19,7 @@ from gpuhelp import log
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
-FLOOR = 1e-2
+FLOOR = 1e-3
 
 
 def _setup(n_side=32):
@@ -74,8 +73,7 @@ def test_adjoint_against_reference_and_fd():
     log(f"vs reference gradient: x {ex:.2e} v {ev:.2e} m {em:.2e}")
     for k, g_, r_ in (("x", gx, rx), ("v", gv, rv), ("m", gm, rm)):
         log(f"  {k}: normwise {np.linalg.norm(g_ - r_) / np.linalg.norm(r_):.2e}, "
-            f"at floor 1e-3 max {_err(g_, r_, sc[k], 1e-3).max():.2e} "
-            f"({(_err(g_, r_, sc[k], 1e-3) > TOL).mean():.1e} of components above 1e-4)")
+            f"at floor 1e-6 max {_err(g_, r_, sc[k], 1e-6).max():.2e}")
     assert max(ex, ev, em) <= TOL, (ex, ev, em)
     # 64 coordinates: 32 positions, 16 velocities, 16 masses (seed 4)
     rng = np.random.default_rng(4)
@@ -96,8 +94,9 @@ def test_adjoint_against_reference_and_fd():
         worst = max(worst, e)
         assert e <= TOL, (kind, k, c, g, fdv, e)
     log(f"vs finite differences: worst {worst:.2e}")
-    # exact invariances of L hold for the FP32 adjoint up to rounding
+    # exact invariances of L hold for the adjoint up to rounding (v.grad and
+    # m.grad carry the float32 rounding of v and m)
     m = f["mass"].astype(np.float64)
-    assert np.all(np.abs(gx.sum(0)) <= 1e-4 * np.abs(gx).sum(0))
-    assert np.all(np.abs(gv.sum(0)) <= 1e-4 * np.abs(gv).sum(0))
-    assert abs((m * gm).sum()) <= 1e-4 * np.abs(m * gm).sum()
+    assert np.all(np.abs(gx.sum(0)) <= 1e-10 * np.abs(gx).sum(0))
+    assert np.all(np.abs(gv.sum(0)) <= 1e-6 * np.abs(gv).sum(0))
+    assert abs((m * gm).sum()) <= 1e-6 * np.abs(m * gm).sum()

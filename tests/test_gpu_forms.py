@@ -228,3 +228,57 @@ def test_layout_choice_and_conversion():
     for k in ps.fields:
         assert dst.get(k).tobytes() == src.get(k).tobytes(), k
     plan.close()
+
+
+def _host_oracle_view(host: "sph.Store", lay: int, n: int):
+    """the bytes of a pinned host store read back through the oracle's own
+    layout tables"""
+    hv = oracle.HostStore(lay, n)
+    for dst, src, b in zip(hv.subs, host.subs, hv.sub_bytes):
+        dst[:] = src[: n * b].numpy()
+    return hv
+
+
+@pytest.mark.parametrize("layout", ["AOS", "SAOS_SHARED", "SOA"])
+def test_offload_forms_against_oracle(layout):
+    """after the offload step and the pipelined offload step, the host store
+    (read through the oracle's layout tables) holds the loops' outputs within
+    the parity tolerance of the oracle (each loop fed the previous loop's
+    outputs as the host store holds them), and every field no loop writes
+    exactly as it was"""
+    import torch
+
+    from gpuhelp import compare_loop, oracle_loop
+    ps = inputs.make_config(1, n_side=32)
+    lay = sph.LAYOUTS.index(layout)
+    f = dict(ps.fields)
+    extra = inputs.random_fields(ps.n, 25, x=f["x"])
+    for k in ("time_bin", "id", "cold", "a", "u_dt", "lap_u", "v_sig", "wcount"):
+        f[k] = extra[k]
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    ws = torch.zeros(sph.sph_batched_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    eps = oracle.pack_resolution(ps.cells)
+    written = {"rho", "rho_dh", "wcount", "div_v", "rot_v", "lap_u", "v_sig", "a", "u_dt"}
+    for form in ("offload", "offload_async"):
+        log(f"{form} {layout} against the oracle")
+        host = _filled_host_store(lay, f, ps.n)
+        dev = sph.Store(lay, ps.n)
+        if form == "offload":
+            sph.sph_offload_step(plan, host, dev, ws)
+        else:
+            sph.sph_offload_step_async(plan, host, dev, ws, nbundle=3)
+        torch.cuda.synchronize()
+        hv = _host_oracle_view(host, lay, ps.n)
+        prev = {}
+        for loop in range(3):
+            got = {k: hv.get(k) for k in LOOP_OUT[loop]}
+            ref = oracle_loop(ps.fields, loop, prev, epsx=eps, grid=True)
+            errs = compare_loop(loop, got, ref)
+            log(f"{form} loop {loop}: worst {max(errs.values()):.2e}")
+            assert max(errs.values()) <= 1e-5, (form, loop, errs)
+            for k in LOOP_OUT[loop]:
+                prev[k] = got[k].astype(np.float64)
+        for k in sph.FIELDS:
+            if k not in written:
+                assert hv.get(k).tobytes() == np.ascontiguousarray(f[k]).astype(hv.get(k).dtype).tobytes(), (form, k)
+    plan.close()

@@ -1,53 +1,67 @@
-"""Full-size workloads in the launch configuration the benchmark times
-(batched form, default tuning, kernels without pair counts; the counting
-kernels are checked too): sampled particles against the oracle, each loop
-fed the GPU's previous-loop outputs.  256^3 Gresho on 32^3 cells and the 188^3
-clustered set on its octree."""
+"""Full-size workloads in the launch configuration the benchmark times: the
+batched form with the benchmark's tuning-cache entry for the workload and the
+SAOS_SHARED store (else the defaults, logged), the kernels without pair
+counts; the counting kernels are checked too.  Sampled particles are compared
+with the oracle (candidate-grid mode, bit for bit its brute force), each loop
+fed the GPU's previous-loop outputs: 256^3 Gresho on 32^3 cells and the 188^3
+clustered set on its octree.  Besides the tolerance of the parity tests, the
+plain scaled error |q_gpu - q_ref| / max(|q_ref|, S) is logged."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2606_23891_amd import inputs, sph
 
-from gpuhelp import LOOP_OUT, compare_loop, device_store, log, oracle_loop, outputs, run_batched_loop
+from gpuhelp import (LOOP_OUT, bench_tuning, compare_loop, device_store, log, oracle_loop, outputs,
+                     run_batched_loop)
 
 pytestmark = pytest.mark.gpu
 
 
-def _run(k, nrows, layout, convert_to=None):
+def _run(k, nrows, layout_name, convert_to=None):
     log(f"building workload {k}")
     ps = inputs.make_config(k)
     log(f"n={ps.n} cells={len(ps.cells)} tasks={len(ps.tasks)} {inputs.cell_stats(ps.cells)}")
+    tuning, cached = bench_tuning(ps, layout_name)
+    log(f"tuning ({'benchmark cache entry' if cached else 'defaults'}): windows {list(tuning.window)} "
+        f"queue {tuning.queue} blocks/CU {tuning.blocks_per_cu} per loop {list(tuning.blocks_per_loop)}")
     plan = sph.Plan(ps.cells, ps.tasks, ps.n)
-    st = device_store(ps, layout)
+    st = device_store(ps, sph.LAYOUTS.index(layout_name))
     rng = np.random.default_rng(11)
     rows = np.sort(rng.choice(ps.n, nrows, replace=False))
     # the largest cells and the smallest supports are where errors concentrate
-    big = int(np.argmax(ps.cells["count"]))
-    rows = np.unique(np.r_[rows, ps.cells["first"][big] + np.arange(min(16, ps.cells["count"][big])),
-                           np.argsort(ps.fields["h"])[:16]])
+    big = np.argsort(ps.cells["count"])[-4:]
+    extra = [ps.cells["first"][b] + np.arange(min(64, ps.cells["count"][b])) for b in big]
+    rows = np.unique(np.r_[rows, np.concatenate(extra), np.argsort(ps.fields["h"])[:64],
+                           np.argsort(ps.fields["h"])[-64:]])
     eps = oracle.pack_resolution(ps.cells)
     prev = {}
     for loop in range(3):
-        cnt = run_batched_loop(plan, st, loop, counts=True)
+        cnt = run_batched_loop(plan, st, loop, tuning=tuning, counts=True)
         gcnt = outputs(st, loop)
-        run_batched_loop(plan, st, loop)  # without counts, as the benchmark times it
+        run_batched_loop(plan, st, loop, tuning=tuning)  # without counts, as the benchmark times it
         g = outputs(st, loop)
         log(f"loop {loop}: oracle on {rows.size} rows")
-        ref = oracle_loop(ps.fields, loop, prev, rows=rows, epsx=eps)
+        ref = oracle_loop(ps.fields, loop, prev, rows=rows, epsx=eps, grid=True)
         errs = compare_loop(loop, g, ref, rows=rows)
-        for k, e in compare_loop(loop, gcnt, ref, rows=rows).items():
-            errs[k] = max(errs[k], e)
+        for kk, e in compare_loop(loop, gcnt, ref, rows=rows).items():
+            errs[kk] = max(errs[kk], e)
+        plain = compare_loop(loop, g, ref, rows=rows, plain=True)
         log(f"loop {loop}: worst {max(errs.values()):.2e} {errs}")
+        log(f"loop {loop}: plain scaled error, worst {max(plain.values()):.2e} {plain}")
         assert max(errs.values()) <= 1e-5, errs
+        if loop == 0 and k == 2:
+            # the density's sums do not cancel: on the lattice even the plain
+            # scaled error stays within the bar
+            assert max(plain.values()) <= 1e-5, plain
         dc = np.abs(cnt[rows].astype(np.int64) - ref["count"])
         assert np.all(dc <= ref["band"]), (loop, int(dc.max()))
         for kk in LOOP_OUT[loop]:
             prev[kk] = g[kk].astype(np.float64)
     if convert_to is not None:
         # the whole store, outputs included, rewritten into another layout
-        log(f"convert {sph.LAYOUTS[layout]} -> {sph.LAYOUTS[convert_to]} n={ps.n}")
-        dst = sph.Store(convert_to, ps.n)
+        log(f"convert {layout_name} -> {convert_to} n={ps.n}")
+        dst = sph.Store(sph.LAYOUTS.index(convert_to), ps.n)
         sph.sph_store_convert(st, dst)
         for name in sph.FIELDS:
             assert st.get(name).tobytes() == dst.get(name).tobytes(), name
@@ -55,8 +69,8 @@ def _run(k, nrows, layout, convert_to=None):
 
 
 def test_gresho256_sampled():
-    _run(2, 96, sph.LAYOUTS.index("SAOS_SHARED"), convert_to=sph.LAYOUTS.index("SOA"))
+    _run(2, 262144, "SAOS_SHARED", convert_to="SOA")
 
 
 def test_clustered188_sampled():
-    _run(3, 96, sph.LAYOUTS.index("SOA"))
+    _run(3, 16384, "SAOS_SHARED")

@@ -74,7 +74,7 @@ def test_pack_bitexact(sets, layout):
         plan.close()
 
 
-@pytest.mark.parametrize("layout", [0, 1, 4, 7, 8])
+@pytest.mark.parametrize("layout", range(9))
 def test_unpack_bitexact(sets, layout):
     import torch
     rng = np.random.default_rng(3)
@@ -101,7 +101,7 @@ def test_unpack_bitexact(sets, layout):
         plan.close()
 
 
-@pytest.mark.parametrize("layout", [0, 2, 6, 8])
+@pytest.mark.parametrize("layout", range(9))
 def test_cells_pack_unpack_bitexact(sets, layout):
     import torch
     rng = np.random.default_rng(5)
@@ -236,14 +236,14 @@ def test_store_convert_bitexact():
         sph.sph_store_convert(src, src)
 
 
-def _check_loops(ps, layout, mode, rows=None, bundle=1):
+def _check_loops(ps, layout, mode, rows=None, bundle=1, tuning=None):
     """density -> gradient -> force on the GPU; each loop compared with the oracle
     fed the GPU's own previous-loop outputs (loop isolation)."""
     plan = sph.Plan(ps.cells, ps.tasks, ps.n)
     st = device_store(ps, layout)
     prev = {}
     worst = {}
-    t = None
+    t = tuning
     if mode == "batched_xcd":
         t = sph.default_tuning()
         t.queue = 2
@@ -262,10 +262,12 @@ def _check_loops(ps, layout, mode, rows=None, bundle=1):
         gcnt = outputs(st, loop)
         run(loop, False)
         g = outputs(st, loop)
-        ref = oracle_loop(ps.fields, loop, prev, rows=rows, epsx=oracle.pack_resolution(ps.cells))
+        ref = oracle_loop(ps.fields, loop, prev, rows=rows, epsx=oracle.pack_resolution(ps.cells), grid=True)
         errs = compare_loop(loop, g, ref, rows=rows)
         for k, e in compare_loop(loop, gcnt, ref, rows=rows).items():
             errs[k] = max(errs[k], e)
+        plain = compare_loop(loop, g, ref, rows=rows, plain=True)
+        log(f"loop {loop}: plain scaled error, worst {max(plain.values()):.2e}")
         worst.update(errs)
         gc = cnt if rows is None else cnt[rows]
         # counts agree except for pairs within 1e-6 H of the support edge
@@ -352,3 +354,71 @@ def test_batched_work_distribution_bitwise():
     plan.close()
     for o in outs[1:]:
         assert o == outs[0]
+
+
+def _chain_ref(ps, eps):
+    """the oracle's own FP64 chain: density, then gradient with its own rho,
+    then force with its own rho, rho_dh, D and R"""
+    f = ps.fields
+    d = oracle.density(f["x"], f["mass"], f["h"], epsx=eps, grid=True)
+    g = oracle.gradient(f["x"], f["v"], f["mass"], f["h"], f["u"], d["rho"], epsx=eps, grid=True)
+    fo = oracle.force(f["x"], f["v"], f["mass"], f["h"], f["u"], d["rho"], d["rho_dh"], g["div_v"], g["rot_v"],
+                      f["alpha_v"], f["alpha_d"], epsx=eps, grid=True)
+    return [d, g, fo]
+
+
+@pytest.mark.parametrize("k,n_side,loops", [(0, None, 1), (1, 32, 3), (4, 32, 3)])
+def test_full_fp64_chain(k, n_side, loops):
+    """the whole step on the GPU (batched, one call) against the oracle's own
+    FP64 chain, where every loop reads the oracle's previous-loop outputs
+    rather than the GPU's: the 16^3 lattice (density only, its workload), the
+    32^3 Gresho lattice and the 32^3 adjoint lattice"""
+    import torch
+    ps = inputs.make_config(k, n_side=n_side) if n_side else inputs.make_config(k)
+    eps = oracle.pack_resolution(ps.cells)
+    refs = _chain_ref(ps, eps)
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    st = device_store(ps, sph.LAYOUTS.index("SAOS_SHARED"))
+    ws = torch.zeros(sph.sph_batched_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    sph.sph_step_batched(plan, st, ws)
+    torch.cuda.synchronize()
+    for loop in range(loops):
+        errs = compare_loop(loop, outputs(st, loop), refs[loop])
+        plain = compare_loop(loop, outputs(st, loop), refs[loop], plain=True)
+        log(f"chain cfg{k} loop {loop}: worst {max(errs.values()):.2e} {errs}")
+        log(f"chain cfg{k} loop {loop}: plain scaled error, worst {max(plain.values()):.2e} {plain}")
+        assert max(errs.values()) <= TOL, (loop, errs)
+        if loop == 0:
+            assert max(plain.values()) <= TOL, plain
+    plan.close()
+
+
+def _bench_entries():
+    """every tuning-cache entry of this device (the launch parameters the
+    benchmark runs with on its workloads)"""
+    import json
+    import os
+
+    import torch
+
+    from paper_2606_23891_amd import tune
+    data = json.load(open(tune.CACHE)) if os.path.exists(tune.CACHE) else {}
+    return data.get(tune.device_key(torch.cuda.get_device_properties(0)), {})
+
+
+@pytest.mark.parametrize("which", ["lattice", "grid512", "octree"])
+def test_loops_benchmark_tunings(which):
+    """the kernel variants and launch parameters of every benchmark tuning
+    entry (windows, work queues, waves per CU) on the small sets, against the
+    oracle"""
+    ps = {"lattice": lambda: inputs.make_config(4, n_side=16),
+          "grid512": lambda: inputs.make_config(2, n_side=32, grid=4),
+          "octree": lambda: inputs.make_config(3, n_side=24)}[which]()
+    rows = None if ps.n <= 8192 else np.random.default_rng(2).choice(ps.n, 4096, replace=False)
+    entries = _bench_entries()
+    assert entries, "no tuning-cache entry for this device"
+    from paper_2606_23891_amd import tune
+    for sig, entry in entries.items():
+        t = tune.apply(sph.default_tuning(), entry)
+        log(f"tuning {sig}: {entry}")
+        _check_loops(ps, sph.LAYOUTS.index("SAOS_SHARED"), "batched", rows=rows, tuning=t)
