@@ -29,7 +29,8 @@
  *    sph_last_error().
  *  - Plans are library-owned and immutable after creation; one plan may be used
  *    from several threads and streams at once.  No call keeps global mutable
- *    state besides the thread-local error text.
+ *    state besides the thread-local error text and, for
+ *    sph_step_batched_noalloc, one static device scratch array per GPU.
  *  - Floating point: pack and unpack are bit-exact data movement (one FP64
  *    subtraction rounded once to FP32 for positions; FP32 additions in a fixed
  *    order for reductions).  Interaction sums are FP32.
@@ -318,6 +319,21 @@ sph_status sph_unpack_cells(const sph_plan *plan, sph_loop loop, const void *res
 /* density -> gradient -> force, each pack -> interact -> unpack. */
 sph_status sph_step_batched(const sph_plan *plan, const sph_store *store, const sph_params *params,
                             const sph_tuning *tuning, void *ws, size_t ws_bytes, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the step of
+ * sph_step_batched with its workspace taken from a static per-device scratch
+ * array of SPH_NOALLOC_SCRATCH_BYTES inside the library (one copy per GPU the
+ * library runs on, held until the process ends), so the call allocates
+ * nothing.  The caller still provides the plan and the store.  A plan whose
+ * sph_batched_ws_bytes exceeds the scratch size is refused with
+ * SPH_E_CAPACITY before anything is enqueued.  Every call on one GPU shares
+ * that GPU's scratch: calls that overlap on one GPU (other streams, other
+ * threads, graph replays in flight) race and must be ordered by the caller.
+ * The first call on a device looks up that device's scratch address (the
+ * device must be current). */
+#define SPH_NOALLOC_SCRATCH_BYTES (64u << 20)
+sph_status sph_step_batched_noalloc(const sph_plan *plan, const sph_store *store, const sph_params *params,
+                                    const sph_tuning *tuning, void *stream);
 /* Smoothing-length iteration: the per-particle update between the density
  * and gradient loops (Sec. 2.1's linear kernels) that makes every h
  * consistent with its density, rho(h) h^3 = m eta^3 (h = eta (m/rho)^(1/3);

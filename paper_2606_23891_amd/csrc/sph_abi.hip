@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "sph_internal.hpp"
@@ -849,6 +850,35 @@ static sph_status step_batched(const sph_plan *p, const sph_store *store, const 
 }
 
 // ---------------------------------------------------------------------------
+// allocation-free batched step: the workspace lives in a file-scope device
+// array, one copy per GPU the library runs on, held until the process ends
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[SPH_NOALLOC_SCRATCH_BYTES];
+
+// device address of this GPU's copy of `scratch`, looked up once per device
+// with that device current (in host code the array's name is not a device
+// address)
+static sph_status scratch_address(void **out)
+{
+    constexpr int kMaxDev = 64;
+    static void *addr[kMaxDev] = {};
+    static std::mutex mu;
+    int dev = -1;
+    SPH_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) return fail(SPH_E_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(SPH_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        addr[dev] = ptr;
+    }
+    *out = addr[dev];
+    return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
 // smoothing-length iteration
 // ---------------------------------------------------------------------------
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
@@ -1031,6 +1061,22 @@ sph_status sph_step_batched(const sph_plan *p, const sph_store *store, const sph
                             const sph_tuning *tn, void *ws, size_t ws_bytes, void *stream)
 {
     return step_batched(p, store, prm, tn, ws, ws_bytes, (hipStream_t)stream);
+}
+
+sph_status sph_step_batched_noalloc(const sph_plan *p, const sph_store *store, const sph_params *prm,
+                                    const sph_tuning *tn, void *stream)
+{
+    if (!p) return fail(SPH_E_ARG, "plan is null");
+    size_t need = 0;
+    sph_batched_ws_bytes(p, &need);
+    if (need > (size_t)SPH_NOALLOC_SCRATCH_BYTES)
+        return fail(SPH_E_CAPACITY, "the step needs " + std::to_string(need) + " bytes of workspace, beyond the " +
+                                        std::to_string((size_t)SPH_NOALLOC_SCRATCH_BYTES) +
+                                        "-byte static scratch: use sph_step_batched with a workspace");
+    void *ws = nullptr;
+    sph_status s = scratch_address(&ws);
+    if (s) return s;
+    return step_batched(p, store, prm, tn, ws, (size_t)SPH_NOALLOC_SCRATCH_BYTES, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------

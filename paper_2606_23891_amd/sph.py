@@ -90,6 +90,7 @@ _SIGS = {
     "sph_interact_cells": ([vp, i32, vp, sz, vp, vp, vp, sz, vp, vp, sz, vp], i32),
     "sph_unpack_cells": ([vp, i32, vp, sz, vp, vp, vp], i32),
     "sph_step_batched": ([vp, vp, vp, vp, vp, sz, vp], i32),
+    "sph_step_batched_noalloc": ([vp, vp, vp, vp, vp], i32),
     "sph_integrate_ws_bytes": ([vp, C.POINTER(sz)], i32),
     "sph_kick": ([vp, C.c_float, vp], i32),
     "sph_drift": ([vp, vp, C.c_double, vp, sz, C.POINTER(C.c_double), C.POINTER(C.c_float), vp], i32),
@@ -485,6 +486,15 @@ def sph_step_batched(plan, store, ws, params=None, tuning=None, stream=None):
     p = params if params is not None else default_params()
     _check(lib().sph_step_batched(_h(plan), _s(store), C.byref(p), C.byref(tuning) if tuning else None,
                                   _ptr(ws), _nbytes(ws), _stream(stream)), "sph_step_batched")
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # SPH_NOALLOC_SCRATCH_BYTES of sph.h
+
+
+def sph_step_batched_noalloc(plan, store, params=None, tuning=None, stream=None):
+    p = params if params is not None else default_params()
+    _check(lib().sph_step_batched_noalloc(_h(plan), _s(store), C.byref(p), C.byref(tuning) if tuning else None,
+                                          _stream(stream)), "sph_step_batched_noalloc")
 
 
 def sph_offload_bytes(layout: int, loop: int, n: int):
