@@ -230,6 +230,16 @@ sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task 
                            int32_t ntask, int64_t n, sph_plan **out);
 void sph_plan_destroy(sph_plan *plan);
 sph_status sph_plan_get_info(const sph_plan *plan, sph_plan_info *info);
+/* Reach of every cell (reach: host array of ncell doubles): the smallest gap,
+ * minimum image in the unit box, between the cell's cube and the cube of a
+ * non-empty cell it shares no task with, at most 1/2 (and at most 1/G where
+ * the plan buckets cells on a G^3 grid no finer than the widest cell).  Any
+ * particle of the cell, while inside its cube, finds every neighbour within
+ * this distance through the cell's tasks (Sec. 2.2): the smoothing-length
+ * step holds each support to it, and the kick-drift-kick step checks that
+ * supports plus drift stay within it.  On a uniform grid with self and 26
+ * neighbour tasks it is the cell width. */
+sph_status sph_plan_cell_reach(const sph_plan *plan, double *reach);
 /* Slots of tasks [t0, t1) and the bytes a pack / result buffer for that range
  * needs (planes hold P = nslot rounded up to 64 slots; the pack buffer also
  * carries 32 bytes of tile bounds per 64-slot chunk after the planes). */

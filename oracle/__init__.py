@@ -65,6 +65,7 @@ def lib():
                               vp]
     L.or_force.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, d, d, i64, vp, vp,
                            vp, vp, vp, vp, vp, vp, vp]
+    L.or_cell_reach.argtypes = [i32, vp, vp, vp, i32, vp, vp, vp]
     L.or_grid_build.argtypes = [i64, vp, d]
     L.or_grid_build.restype = vp
     L.or_grid_free.argtypes = [vp]
@@ -196,16 +197,40 @@ def balsara(h, u, rho, D, R, alpha_v, gamma=GAMMA_AD, eps=BALSARA_EPS) -> np.nda
 GAMMA_K = np.sqrt(10.0 / 3.0)   # support H over smoothing length h (cubic spline)
 
 
-def h_newton_step(h, m, rho, rho_dh, cell_width, eta, tol):
+def cell_reach(cells, tasks) -> np.ndarray:
+    """Per cell, the smallest gap (minimum image) between its cube and the
+    cube of a non-empty cell that shares no task with it, at most 1/2: the
+    distance within which every neighbour of the cell's particles lies in a
+    cell joined to it by a task (Sec. 2.2).  Brute force over cell pairs."""
+    L = lib()
+    nc, nt = len(cells), len(tasks)
+    loc = _c(cells["loc"], np.float64); width = _c(cells["width"], np.float64)
+    count = _c(cells["count"], np.int32)
+    ci = _c(tasks["ci"], np.int32); cj = _c(tasks["cj"], np.int32)
+    out = np.zeros(nc)
+    L.or_cell_reach(nc, _p(loc), _p(width), _p(count), nt, _p(ci), _p(cj), _p(out))
+    return out
+
+
+def particle_reach(cells, tasks, n) -> np.ndarray:
+    """the reach of every particle's cell (cells hold consecutive particle ranges)"""
+    r = cell_reach(cells, tasks)
+    out = np.zeros(n)
+    for c in range(len(cells)):
+        out[cells["first"][c]:cells["first"][c] + cells["count"][c]] = r[c]
+    return out
+
+
+def h_newton_step(h, m, rho, rho_dh, reach, eta, tol):
     """One smoothing-length update per particle, in FP64 (h itself is a float32
     field).  Root sought: f(h) = rho(h) h^3 - m eta^3 = 0, i.e. h = eta (m /
     rho)^(1/3).  Newton: dh = -f / f' with f' = h^3 rho' + 3 h^2 rho, which is
     dh = -h (rho - n) / (3 rho + h rho') for n = m eta^3 / h^3; where that
     denominator is not positive, the fixed-point step to eta (m / rho)^(1/3).
     |dh| <= tol h: converged, h kept; otherwise h + dh clipped to [h/2, 2h].
-    Either way h is then held to gamma_K h <= the cell width (so a particle
-    above it moves even when converged).  Returns (new h as float32, moved
-    mask)."""
+    Either way h is then held to gamma_K h <= the reach of the particle's cell
+    (cell_reach: the support its cell's tasks cover; a particle above it
+    moves even when converged).  Returns (new h as float32, moved mask)."""
     h64 = np.asarray(h, np.float64)
     rho = np.asarray(rho, np.float64)
     n = np.asarray(m, np.float64) * eta ** 3 / h64 ** 3
@@ -216,7 +241,7 @@ def h_newton_step(h, m, rho, rho_dh, cell_width, eta, tol):
     dh = np.where(den > 0.0, newton, fixed)
     conv = np.abs(dh) <= tol * h64
     hn = np.where(conv, h64, np.clip(h64 + dh, 0.5 * h64, 2.0 * h64))
-    hn = np.minimum(hn, np.asarray(cell_width, np.float64) / GAMMA_K)
+    hn = np.minimum(hn, np.asarray(reach, np.float64) / GAMMA_K)
     hn32 = hn.astype(np.float32)
     moved = hn32 != np.asarray(h, np.float32)
     out = np.asarray(h, np.float32).copy()
@@ -224,7 +249,7 @@ def h_newton_step(h, m, rho, rho_dh, cell_width, eta, tol):
     return out, moved
 
 
-def h_iterate(x, m, h, cell_width, eta=1.2348, tol=1e-4, max_iter=30) -> Dict[str, np.ndarray]:
+def h_iterate(x, m, h, reach, eta=1.2348, tol=1e-4, max_iter=30) -> Dict[str, np.ndarray]:
     """The smoothing-length iteration: the FP64 brute-force density of the
     particles whose h moved (all on the first pass), then one h_newton_step
     for them, until none moves or max_iter passes.  Returns the final h, the
@@ -232,7 +257,7 @@ def h_iterate(x, m, h, cell_width, eta=1.2348, tol=1e-4, max_iter=30) -> Dict[st
     still moved in the last pass."""
     h = np.asarray(h, np.float32).copy()
     n = h.size
-    width = np.asarray(cell_width, np.float64)
+    width = np.asarray(reach, np.float64)
     rho, rdh, wc = np.zeros(n), np.zeros(n), np.zeros(n)
     rows = np.arange(n)
     passes, still = 0, 0

@@ -203,6 +203,53 @@ static int64_t *cand_buffer(const or_grid *g)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Reach of every cell (the reading of Sec. 2.2's "neighbours lie in cells   */
+/* that share a task"): the smallest distance, minimum image in the unit     */
+/* box, between the cell's cube and the cube of any non-empty cell with no   */
+/* task joining the two; at most 1/2.  Brute force over all cell pairs.      */
+/* ------------------------------------------------------------------------ */
+void or_cell_reach(int32_t ncell, const double *loc, const double *width, const int32_t *count,
+                   int32_t ntask, const int32_t *ci, const int32_t *cj, double *reach)
+{
+    /* the cells each cell shares a task with, as lists */
+    int64_t *off = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    for (int32_t t = 0; t < ntask; t++) { off[ci[t] + 1]++; off[cj[t] + 1]++; }
+    for (int32_t c = 0; c < ncell; c++) off[c + 1] += off[c];
+    int32_t *lst = (int32_t *)malloc(sizeof(int32_t) * (size_t)(off[ncell] > 0 ? off[ncell] : 1));
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ncell > 0 ? ncell : 1));
+    for (int32_t c = 0; c < ncell; c++) pos[c] = off[c];
+    for (int32_t t = 0; t < ntask; t++) { lst[pos[ci[t]]++] = cj[t]; lst[pos[cj[t]]++] = ci[t]; }
+#pragma omp parallel
+    {
+        unsigned char *partner = (unsigned char *)calloc((size_t)(ncell > 0 ? ncell : 1), 1);
+#pragma omp for schedule(dynamic, 64)
+        for (int32_t c = 0; c < ncell; c++) {
+            for (int64_t e = off[c]; e < off[c + 1]; e++) partner[lst[e]] = 1;
+            double best = 0.5;
+            for (int32_t d = 0; d < ncell; d++) {
+                if (d == c || partner[d] || count[d] == 0) continue;
+                double g2 = 0.0;
+                for (int k = 0; k < 3; k++) {
+                    double a = loc[3 * c + k] + 0.5 * width[c];
+                    double b = loc[3 * d + k] + 0.5 * width[d];
+                    double sep = mi(b - a);
+                    double g = fabs(sep) - 0.5 * (width[c] + width[d]);
+                    if (g > 0.0) g2 += g * g;
+                }
+                double gap = sqrt(g2);
+                if (gap < best) best = gap;
+            }
+            reach[c] = best;
+            for (int64_t e = off[c]; e < off[c + 1]; e++) partner[lst[e]] = 0;
+        }
+        free(partner);
+    }
+    free(pos);
+    free(lst);
+    free(off);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Density loop: over all j including i with r < H_i                         */
 /*   rho_i = sum m_j W(r, h_i);  rho_dh_i = sum m_j dW/dh(r, h_i);            */
 /*   wcount_i = sum W(r, h_i).                                               */

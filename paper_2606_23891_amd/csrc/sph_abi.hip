@@ -324,6 +324,83 @@ sph_status sph_store_convert(const sph_store *src, const sph_store *dst, void *s
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
+// Reach of every cell: the smallest gap (minimum image in the unit box)
+// between its cube and the cube of a non-empty cell it shares no task with,
+// at most 1/2.  Cells are bucketed by centre on a grid of G^3 buckets no
+// narrower than the widest cell; a cell outside the 5^3 buckets around a
+// cell's own is at least 1/G away from it, so the search stops there and the
+// reach is at most 1/G (with G <= 5 every cell is visited).
+static void compute_reach(const sph_cell *cells, int32_t nc, const sph_task *tasks, int32_t ntask,
+                          std::vector<double> &reach)
+{
+    reach.assign(nc, 0.5);
+    if (nc == 0) return;
+    std::vector<int32_t> off(nc + 1, 0);
+    for (int32_t t = 0; t < ntask; ++t) {
+        off[tasks[t].ci + 1]++;
+        if (tasks[t].cj != tasks[t].ci) off[tasks[t].cj + 1]++;
+    }
+    for (int32_t c = 0; c < nc; ++c) off[c + 1] += off[c];
+    std::vector<int32_t> part(off[nc]);
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (int32_t t = 0; t < ntask; ++t) {
+        part[fill[tasks[t].ci]++] = tasks[t].cj;
+        if (tasks[t].cj != tasks[t].ci) part[fill[tasks[t].cj]++] = tasks[t].ci;
+    }
+    for (int32_t c = 0; c < nc; ++c) std::sort(part.begin() + off[c], part.begin() + off[c + 1]);
+    double wmax = 0.0;
+    for (int32_t c = 0; c < nc; ++c) wmax = std::max(wmax, cells[c].width);
+    int64_t G = wmax > 0.0 ? (int64_t)std::floor(1.0 / wmax) : 1;
+    G = std::max<int64_t>(1, std::min<int64_t>(G, 128));
+    const bool all = G <= 5;
+    const double cap = all ? 0.5 : std::min(0.5, 1.0 / (double)G);
+    auto centre = [&](int32_t c, int d) {
+        const double x = cells[c].loc[d] + 0.5 * cells[c].width;
+        return x - std::floor(x);
+    };
+    auto bucket = [&](double x) { return std::min<int64_t>(G - 1, (int64_t)(x * (double)G)); };
+    std::vector<int64_t> bstart((size_t)(G * G * G) + 1, 0);
+    std::vector<int64_t> bof(nc);
+    for (int32_t c = 0; c < nc; ++c) {
+        bof[c] = (bucket(centre(c, 2)) * G + bucket(centre(c, 1))) * G + bucket(centre(c, 0));
+        bstart[bof[c] + 1]++;
+    }
+    for (int64_t b = 0; b < G * G * G; ++b) bstart[b + 1] += bstart[b];
+    std::vector<int32_t> bcell(nc);
+    {
+        std::vector<int64_t> bf(bstart.begin(), bstart.end() - 1);
+        for (int32_t c = 0; c < nc; ++c) bcell[bf[bof[c]]++] = c;
+    }
+    auto visit = [&](int32_t c, int32_t d, double &best) {
+        if (d == c || cells[d].count == 0) return;
+        if (std::binary_search(part.begin() + off[c], part.begin() + off[c + 1], d)) return;
+        double g2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            double dx = (cells[d].loc[k] + 0.5 * cells[d].width) - (cells[c].loc[k] + 0.5 * cells[c].width);
+            dx -= std::round(dx);
+            const double g = std::fabs(dx) - 0.5 * (cells[c].width + cells[d].width);
+            if (g > 0.0) g2 += g * g;
+        }
+        best = std::min(best, std::sqrt(g2));
+    };
+    for (int32_t c = 0; c < nc; ++c) {
+        if (cells[c].count == 0) continue;
+        double best = cap;
+        if (all) {
+            for (int32_t d = 0; d < nc; ++d) visit(c, d, best);
+        } else {
+            const int64_t bx = bof[c] % G, by = (bof[c] / G) % G, bz = bof[c] / (G * G);
+            for (int64_t dz = -2; dz <= 2; ++dz)
+                for (int64_t dy = -2; dy <= 2; ++dy)
+                    for (int64_t dx = -2; dx <= 2; ++dx) {
+                        const int64_t b = (((bz + dz + G) % G) * G + (by + dy + G) % G) * G + (bx + dx + G) % G;
+                        for (int64_t q = bstart[b]; q < bstart[b + 1]; ++q) visit(c, bcell[q], best);
+                    }
+        }
+        reach[c] = best;
+    }
+}
+
 sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task *tasks, int32_t ntask,
                            int64_t n, sph_plan **out)
 {
@@ -525,6 +602,8 @@ sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task 
                              [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
     }
 
+    compute_reach(cells, ncell, tasks, ntask, p->reach);
+
     sph_status st;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
@@ -538,7 +617,7 @@ sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task 
     if ((st = upload(&p->d_cells, p->cells)) || (st = upload(&p->d_tasks, p->tasks)) ||
         (st = upload(&p->d_chunks, ch)) || (st = upload(&p->d_tiles, tiles)) || (st = upload(&p->d_cellr, cr)) ||
         (st = upload(&p->d_nbr, nbr)) || (st = upload(&p->d_nbr_off, nbr_off)) || (st = upload(&p->d_items, items)) || (st = upload(&p->d_items_x, items_x)) ||
-        (st = upload(&p->d_jt_off, jt_off)) || (st = upload(&p->d_jt, jt))) {
+        (st = upload(&p->d_jt_off, jt_off)) || (st = upload(&p->d_jt, jt)) || (st = upload(&p->d_reach, p->reach))) {
         sph_plan_destroy(p);
         return st;
     }
@@ -551,7 +630,8 @@ void sph_plan_destroy(sph_plan *p)
     if (!p) return;
     (void)hipSetDevice(p->device);
     void *ptrs[] = {p->d_cells, p->d_tasks, p->d_chunks, p->d_tiles, p->d_cellr, p->d_nbr,
-                    p->d_nbr_off, p->d_items, p->d_items_x, p->d_jt_off, p->d_jt, p->d_csr_off, p->d_csr};
+                    p->d_nbr_off, p->d_items, p->d_items_x, p->d_jt_off, p->d_jt, p->d_csr_off, p->d_csr,
+                    p->d_reach};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (p->off_h2d) (void)hipStreamDestroy(p->off_h2d);
@@ -571,6 +651,13 @@ sph_status sph_plan_get_info(const sph_plan *p, sph_plan_info *info)
     info->max_cell = p->max_cell;
     info->max_nbr = p->max_nbr;
     info->batched_ok = p->batched_ok ? 1 : 0;
+    return SPH_OK;
+}
+
+sph_status sph_plan_cell_reach(const sph_plan *p, double *reach)
+{
+    if (!p || (!reach && p->ncell > 0)) return fail(SPH_E_ARG, "null argument");
+    std::copy(p->reach.begin(), p->reach.end(), reach);
     return SPH_OK;
 }
 
@@ -1044,10 +1131,11 @@ sph_status sph_step_kdk(const sph_plan *p, const sph_store *store, const sph_par
     if ((s = launch_drift(p, store, (double)dt, iws, st, true, half))) return s;
     double r[2];
     if ((s = read_fold(p, iws, r, st))) return s;
-    // every pair within a support must still meet in adjacent cells:
-    // H_max + 2 (largest distance outside a cell) <= the narrowest cell
+    // every pair within a support must still meet in cells that share a task:
+    // H_max + 2 (largest distance outside a cell) <= the smallest reach
     double wmin = __builtin_huge_val();
-    for (const sph_cell &c : p->cells) wmin = std::min(wmin, c.width);
+    for (int32_t c = 0; c < p->ncell; ++c)
+        if (p->cells[c].count > 0) wmin = std::min(wmin, p->reach[c]);
     if ((double)kGammaK * r[1] + 2.0 * r[0] > wmin) {
         if (rebuild) *rebuild = 1;
         return fail(SPH_E_PLAN, "particles drifted beyond the plan's reach: rebuild the plan, then run the "

@@ -135,6 +135,11 @@ struct sph_plan {
     sph::JTile *d_jt = nullptr;      // flattened j-tiles of every cell's neighbours
     int32_t max_jt = 0;
     std::vector<int32_t> tile_off;   // per cell: its first tile (ncell + 1 entries)
+    // per cell: the distance from its cube within which every non-empty cell
+    // shares a task with it (a support up to this wide finds all its
+    // neighbours through the cell's tasks)
+    std::vector<double> reach;
+    double *d_reach = nullptr;
     // copy streams of the pipelined offload step, created on its first call
     std::mutex off_mu;
     hipStream_t off_h2d = nullptr, off_d2h = nullptr;

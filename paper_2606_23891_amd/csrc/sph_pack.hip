@@ -672,7 +672,7 @@ static sph_status convert_l(int ld, const StoreArg &src, const StoreArg &dst, in
 struct HIterArgs {
     StoreArg store;
     const Chunk *tiles;
-    const sph_cell *cells;
+    const double *reach;  // per cell: the support its tasks cover
     int64_t ntile;
     float eta3;        // eta^3
     float tol;         // converged when |dh| <= tol h
@@ -685,7 +685,8 @@ struct HIterArgs {
 // not positive the step is the fixed-point one, h eta-scaled to the current
 // density.  A particle whose step is within tol h keeps its h (and with it the
 // density just computed); any other takes h + dh limited to [h/2, 2h].  Every
-// h, moved or not, is then held to a support no wider than its cell.
+// h, moved or not, is then held to a support no wider than its cell's reach
+// (the distance within which the cell's tasks cover every other cell).
 template <int L>
 __global__ __launch_bounds__(256) void k_h_newton(HIterArgs a)
 {
@@ -706,7 +707,7 @@ __global__ __launch_bounds__(256) void k_h_newton(HIterArgs a)
         const float dh = den > 0.0f ? -h * (rho - n) / den : h * (cbrtf(n / rho) - 1.0f);
         float hn = h;
         if (!(fabsf(dh) <= a.tol * h)) hn = fminf(fmaxf(h + dh, 0.5f * h), 2.0f * h);
-        hn = fminf(hn, (float)(a.cells[ch.cell].width / (double)kGammaK));
+        hn = fminf(hn, (float)(a.reach[ch.cell] / (double)kGammaK));
         if (hn != h) {
             st<L, FH, 0, float>(a.store, p, hn);
             moved = true;
@@ -1108,7 +1109,7 @@ sph_status launch_h_newton(const sph_plan *p, const sph_store *s, float eta, flo
     HIterArgs a{};
     a.store = store_arg(s);
     a.tiles = p->d_tiles;
-    a.cells = p->d_cells;
+    a.reach = p->d_reach;
     a.ntile = p->ntile;
     a.eta3 = eta * eta * eta;
     a.tol = tol;

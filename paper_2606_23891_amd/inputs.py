@@ -255,16 +255,23 @@ def uniform_grid(fields: Dict[str, np.ndarray], nc: int):
     return fields, cells, tasks
 
 
-def octree(fields: Dict[str, np.ndarray], top: int = 32, max_count: int = 2000):
-    """Octree leaves under a top-level top^3 grid, split while count > max_count
-    and half the width still covers the largest support radius in the cell.
-    Pair tasks join leaves whose boxes are closer than the larger of their
-    largest support radii (Sec. 2.2: all neighbours lie in adjacent cells)."""
+def octree(fields: Dict[str, np.ndarray], top: int = 32, max_count: int = 2000, min_count: int = 10):
+    """Octree leaves under a top-level top^3 grid (cells at least as wide as
+    the largest support), split while they hold more than max_count particles
+    -- also below the largest support radius in the leaf, as SWIFT's cells of a
+    clustered set are.  A leaf with fewer than min_count particles is merged
+    with the leaf next to it in store order (the smaller of the two, within
+    the same top-level cell and while the sum stays within max_count); the
+    merged cell is the smallest octree cube holding both, so it may overlap
+    other cells, which the pair criterion below handles like any other gap 0.
+    Pair tasks join every two cells whose boxes are closer than the larger of
+    their largest support radii (Sec. 2.2: every neighbour of a particle then
+    lies in a cell that shares a task with its own)."""
     fields, keys = _sort_morton(fields)
     hsup = SUPPORT_PER_H * fields["h"].astype(np.float64)
     assert hsup.max() < 1.0 / top, "top-level cells must be wider than the largest support"
     ltop = int(np.log2(top))
-    leaves = []  # (level, key prefix, first, count, Hmax)
+    leaves = []  # [level, key prefix, first, count]
     stack = []
     tkey = (keys >> np.uint64(3 * (MORTON_BITS - ltop))).astype(np.int64)
     tcounts = np.bincount(tkey, minlength=top ** 3)
@@ -274,9 +281,7 @@ def octree(fields: Dict[str, np.ndarray], top: int = 32, max_count: int = 2000):
             stack.append((ltop, k, int(tfirst[k]), int(tcounts[k])))
     while stack:
         lvl, pre, f, c = stack.pop()
-        hmax = float(hsup[f:f + c].max())
-        width = 1.0 / (1 << lvl)
-        if c > max_count and width / 2 >= hmax and lvl < MORTON_BITS:
+        if c > max_count and lvl < MORTON_BITS:
             sub = (keys[f:f + c] >> np.uint64(3 * (MORTON_BITS - lvl - 1))).astype(np.int64)
             for ch in range(7, -1, -1):
                 cpre = (pre << 3) | ch
@@ -285,8 +290,45 @@ def octree(fields: Dict[str, np.ndarray], top: int = 32, max_count: int = 2000):
                 if hi > lo:
                     stack.append((lvl + 1, cpre, f + lo, hi - lo))
         else:
-            leaves.append((lvl, pre, f, c, hmax))
+            leaves.append([lvl, pre, f, c])
     leaves.sort(key=lambda t: t[2])
+
+    def common(a, b):
+        """the smallest octree cube (level, prefix) holding cubes a and b"""
+        la, pa, lb, pb = a[0], a[1], b[0], b[1]
+        lvl = min(la, lb)
+        pa >>= 3 * (la - lvl)
+        pb >>= 3 * (lb - lvl)
+        while pa != pb:
+            pa >>= 3
+            pb >>= 3
+            lvl -= 1
+        return lvl, pa
+
+    merged = True
+    while merged:
+        merged = False
+        k = 0
+        while k < len(leaves):
+            if leaves[k][3] >= min_count:
+                k += 1
+                continue
+            best = None
+            for nb in (k - 1, k + 1):
+                if 0 <= nb < len(leaves) and leaves[nb][3] + leaves[k][3] <= max_count:
+                    lvl, pre = common(leaves[k], leaves[nb])
+                    if lvl >= ltop and (best is None or leaves[nb][3] < leaves[best][3]):
+                        best = nb
+            if best is None:
+                k += 1
+                continue
+            a_, b_ = sorted((k, best))
+            lvl, pre = common(leaves[a_], leaves[b_])
+            leaves[a_] = [lvl, pre, leaves[a_][2], leaves[a_][3] + leaves[b_][3]]
+            del leaves[b_]
+            merged = True
+            k = a_
+    leaves = [(l[0], l[1], l[2], l[3], float(hsup[l[2]:l[2] + l[3]].max())) for l in leaves]
     nl = len(leaves)
     lvl = np.array([t[0] for t in leaves])
     pre = np.array([t[1] for t in leaves], dtype=np.int64)
@@ -363,7 +405,7 @@ def make_config(k: int, *, jitter: float = 0.1, grid: Optional[int] = None,
     0: 16^3 jittered lattice, zero velocity, u = 1, 4^3 cells.
     1: 64^3 Gresho vortex, 16^3 cells, random switches.
     2: 256^3 Gresho vortex, 32^3 cells (grid=64 gives the 64-per-cell variant).
-    3: 188^3 clustered set on an octree (leaf counts about 10..2000).
+    3: 188^3 clustered set on an octree (10..2000 particles per cell).
     4: 32^3 Gresho vortex on a jittered lattice, 8^3 cells (adjoint workload).
     ``n_side`` shrinks a workload for quick tests.
     """

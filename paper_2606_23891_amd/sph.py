@@ -75,6 +75,7 @@ _SIGS = {
     "sph_plan_destroy": ([vp], None),
     "sph_plan_get_info": ([vp, vp], i32),
     "sph_plan_buffer_bytes": ([vp, i32, i32, i32, C.POINTER(i64), C.POINTER(sz), C.POINTER(sz)], i32),
+    "sph_plan_cell_reach": ([vp, vp], i32),
     "sph_zero_outputs": ([vp, i32, vp, vp], i32),
     "sph_pack": ([vp, i32, vp, i32, i32, vp, sz, vp], i32),
     "sph_density": ([vp, vp, sz, i32, i32, vp, vp, sz, vp, vp], i32),
@@ -270,6 +271,12 @@ def _aligned_view(t, nbytes: int):
     return t[off:off + nbytes]
 
 
+def sph_plan_cell_reach(plan) -> np.ndarray:
+    out = np.zeros(len(plan.cells), np.float64)
+    _check(lib().sph_plan_cell_reach(_h(plan), out.ctypes.data if out.size else None), "sph_plan_cell_reach")
+    return out
+
+
 class Plan:
     """Cells and tasks of one step, uploaded once."""
 
@@ -285,6 +292,9 @@ class Plan:
 
     def buffer_bytes(self, loop: int, t0: int, t1: int):
         return sph_plan_buffer_bytes(self, loop, t0, t1)
+
+    def cell_reach(self) -> np.ndarray:
+        return sph_plan_cell_reach(self)
 
     def close(self):
         if self.ptr:

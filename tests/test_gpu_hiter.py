@@ -24,8 +24,9 @@ def _perturbed(ps, seed):
     return h
 
 
-def _cell_width(ps):
-    return np.repeat(np.asarray(ps.cells["width"], np.float64), np.asarray(ps.cells["count"]))
+def _reach(ps):
+    """the oracle's reach of every particle's cell (the support its tasks cover)"""
+    return oracle.particle_reach(ps.cells, ps.tasks, ps.n)
 
 
 @pytest.mark.parametrize("name,cfg", [("lattice16", dict(k=0, n_side=16, grid=4)),
@@ -42,7 +43,7 @@ def test_h_iteration_matches_oracle(name, cfg):
     torch.cuda.synchronize()
     hg = st.get("h")
     log(f"{name}: GPU passes {passes}, unconverged {still}")
-    ref = oracle.h_iterate(ps.fields["x"], ps.fields["mass"], h0, _cell_width(ps), eta=ETA, tol=TOL)
+    ref = oracle.h_iterate(ps.fields["x"], ps.fields["mass"], h0, _reach(ps), eta=ETA, tol=TOL)
     log(f"{name}: oracle passes {ref['passes']}, unconverged {ref['unconverged']}")
     assert still == 0 and ref["unconverged"] == 0
     assert passes >= 2
@@ -71,7 +72,7 @@ def test_h_iteration_pass_limit_and_arguments():
     log("h iteration, one pass")
     passes, still = sph.sph_h_iterate(plan, st, ws, eta=ETA, tol=TOL, max_iter=1)
     torch.cuda.synchronize()
-    ref = oracle.h_iterate(ps.fields["x"], ps.fields["mass"], h0, _cell_width(ps), eta=ETA, tol=TOL, max_iter=1)
+    ref = oracle.h_iterate(ps.fields["x"], ps.fields["mass"], h0, _reach(ps), eta=ETA, tol=TOL, max_iter=1)
     assert passes == 1 and still > 0
     # one pass: the first density is of h0 on both sides, so the stepped h agree to FP32 step rounding
     assert np.max(np.abs(st.get("h") - ref["h"]) / ref["h"]) <= 1e-5
@@ -86,33 +87,55 @@ def test_h_iteration_pass_limit_and_arguments():
     plan.close()
 
 
+def test_plan_reach_matches_oracle():
+    """the plan's per-cell reach (bucketed search) against the oracle's brute
+    force over all cell pairs: a uniform grid (the cell width), the clustered
+    set's octree with six cell widths, and a sparse grid with empty cells"""
+    for name, ps in (("grid8", inputs.make_config(1, n_side=32, grid=8)),
+                     ("octree64", inputs.make_config(3, n_side=64)),
+                     ("octree24", inputs.make_config(3, n_side=24))):
+        plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+        got = plan.cell_reach()
+        ref = oracle.cell_reach(ps.cells, ps.tasks)
+        log(f"reach {name}: cells {len(ps.cells)}, reach/width {np.min(got / ps.cells['width']):.3f}.."
+            f"{np.max(got / ps.cells['width']):.3f}")
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-15)
+        plan.close()
+
+
 def test_h_iteration_octree_with_cell_caps():
-    """the clustered set's cells with eta = 3: supports of several hundred
-    neighbours, so the dense regions reach the cap gamma_K h <= cell width and
-    stay there; GPU and oracle apply the same limits, so the final h agree and
-    the stored densities are those of the final h"""
+    """the clustered set's octree at 64^3 (cells of six widths, supports
+    beyond the smaller cells) with eta = 3: supports of several hundred
+    neighbours, so the dense regions reach the cap gamma_K h <= the reach of
+    their cell and stay there; GPU and oracle apply the same limits, so the
+    final h agree, and the stored densities are those of the final h, checked
+    against the oracle's density on every particle"""
     import torch
-    ps = inputs.make_config(3, n_side=24)
+    ps = inputs.make_config(3, n_side=64)
     eta = 3.0   # supports of several hundred neighbours: the dense regions reach the cap
     h0 = (_perturbed(ps, 7) * np.float32(eta / ETA)).astype(np.float32)
+    reach = _reach(ps)
+    h0 = np.minimum(h0, (reach / oracle.GAMMA_K).astype(np.float32))
     plan = sph.Plan(ps.cells, ps.tasks, ps.n)
     st = device_store(ps, sph.LAYOUTS.index("SOA"), extra={"h": h0})
     ws = torch.zeros(sph.sph_h_iterate_ws_bytes(plan), dtype=torch.uint8, device="cuda")
-    log(f"h iteration octree n={ps.n} cells={len(ps.cells)}")
+    log(f"h iteration octree n={ps.n} cells={len(ps.cells)} widths {np.unique(ps.cells['width']).size}")
     passes, still = sph.sph_h_iterate(plan, st, ws, eta=eta, tol=TOL, max_iter=40)
     torch.cuda.synchronize()
     hg = st.get("h")
-    width = _cell_width(ps)
-    ref = oracle.h_iterate(ps.fields["x"], ps.fields["mass"], h0, width, eta=eta, tol=TOL, max_iter=40)
+    ref = oracle.h_iterate(ps.fields["x"], ps.fields["mass"], h0, reach, eta=eta, tol=TOL, max_iter=40)
+    capped = hg.astype(np.float64) * oracle.GAMMA_K >= reach * (1 - 1e-6)
     log(f"octree: GPU passes {passes} left {still}; oracle passes {ref['passes']} left {ref['unconverged']}; "
-        f"capped {int(np.sum(hg >= (width / oracle.GAMMA_K).astype(np.float32)))}")
+        f"capped {int(capped.sum())}, in cells narrower than their support "
+        f"{int(np.sum(oracle.GAMMA_K * hg > np.repeat(ps.cells['width'], ps.cells['count'])))}")
     assert still == 0 and ref["unconverged"] == 0
     hr = ref["h"].astype(np.float64)
     assert np.max(np.abs(hg - hr) / hr) <= 3 * TOL
-    capped = hg.astype(np.float64) * oracle.GAMMA_K >= width * (1 - 1e-6)
     assert capped.sum() > 100
-    assert np.all(oracle.GAMMA_K * hg.astype(np.float64) <= width * (1 + 1e-6))
-    ref_d = oracle.density(ps.fields["x"], ps.fields["mass"], hg, epsx=oracle.pack_resolution(ps.cells))
+    assert np.all(oracle.GAMMA_K * hg.astype(np.float64) <= reach * (1 + 1e-6))
+    ref_d = oracle.density(ps.fields["x"], ps.fields["mass"], hg, epsx=oracle.pack_resolution(ps.cells),
+                           grid=True)
     errs = compare_loop(0, outputs(st, 0), ref_d)
+    log(f"octree: density at final h, worst {max(errs.values()):.2e}")
     assert max(errs.values()) <= 1e-5, errs
     plan.close()

@@ -297,8 +297,13 @@ def test_loops_multitile_cells(mode):
 
 @pytest.mark.parametrize("mode", ["per_task", "batched", "batched_xcd"])
 def test_loops_octree_uneven(mode):
-    ps = inputs.make_config(3, n_side=24)
-    _check_loops(ps, 4, mode, bundle=16)
+    """the clustered set's octree at 64^3: cells of six widths holding 10 to
+    2000 particles, supports wider than the smaller cells, tasks between cells
+    that are not adjacent"""
+    ps = inputs.make_config(3, n_side=64)
+    assert np.unique(ps.cells["width"]).size > 1
+    rows = np.random.default_rng(4).choice(ps.n, 8192, replace=False)
+    _check_loops(ps, 4, mode, rows=rows, bundle=64)
 
 
 def _coincident_set(seed=5):

@@ -4,6 +4,7 @@ and the neighbour search through tasks is complete (checked by brute force)."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_2606_23891_amd import inputs
 
 
@@ -80,3 +81,43 @@ def test_gresho_profile():
         vv, uu = inputs.gresho_profile(xx)
         dp = (uu[1] - uu[0]) * (2.0 / 3.0) / (2 * e)
         np.testing.assert_allclose(dp, np.hypot(*vv[2, :2]) ** 2 / r0, rtol=1e-6)
+
+
+def test_clustered_cells_within_counts():
+    """the clustered workload's octree (at 64^3): every cell holds 10 to 2000
+    particles, supports span close to the factor of 100 the full workload is
+    clamped to, and cells narrower than their largest support exist (the
+    octree splits on counts alone)"""
+    ps = inputs.make_config(3, n_side=64)
+    c = ps.cells["count"]
+    assert c.min() >= 10 and c.max() <= 2000, inputs.cell_stats(ps.cells)
+    h = ps.fields["h"]
+    assert 50.0 <= float(h.max() / h.min()) <= 100.0 * (1 + 1e-6)
+    H = inputs.SUPPORT_PER_H * h.astype(np.float64)
+    hmax = np.maximum.reduceat(H, ps.cells["first"])
+    assert np.any(hmax > ps.cells["width"])
+
+
+def test_cell_reach_definition():
+    """the oracle's cell reach: the cell width on a uniform grid with 26
+    neighbour tasks; on the clustered octree, every particle within the reach
+    of another's cell sits in a cell that shares a task with it (checked by
+    brute force over sampled particles)"""
+    ps = inputs.make_config(0)
+    r = oracle.cell_reach(ps.cells, ps.tasks)
+    np.testing.assert_array_equal(r, ps.cells["width"])
+    ps = inputs.make_config(3, n_side=48)
+    r = oracle.cell_reach(ps.cells, ps.tasks)
+    x = ps.fields["x"]
+    cell_of = np.repeat(np.arange(len(ps.cells)), ps.cells["count"])
+    part = {(int(a), int(b)) for a, b in zip(ps.tasks["ci"], ps.tasks["cj"])}
+    part |= {(b, a) for a, b in part}
+    rng = np.random.default_rng(3)
+    for i in rng.choice(ps.n, 400, replace=False):
+        d = x - x[i]
+        d -= np.round(d)
+        near = np.flatnonzero(np.sqrt((d * d).sum(1)) < r[cell_of[i]])
+        for j in near:
+            ci, cj = int(cell_of[i]), int(cell_of[j])
+            assert ci == cj or (ci, cj) in part, (i, j)
+    assert np.any(r < 0.5)
