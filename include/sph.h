@@ -68,7 +68,11 @@ typedef enum sph_layout {
     SPH_SAOS_FORCE_TYPE = 6,  /* SAOS_FORCE split again by data type               */
     SPH_SAOS_SHARED_TYPE = 7, /* SAOS_SHARED split again by data type              */
     SPH_SOA = 8,              /* one array per scalar component                    */
-    SPH_NLAYOUTS = 9
+    SPH_SAOS_SHARED_REPL = 9, /* SAOS_SHARED with the position replicated into   */
+                              /* every substruct a loop packs from (Sec. 5's data */
+                              /* replication): {x m h} {x v u rho} {x rho_dh D R  */
+                              /* alpha_v alpha_d} {outputs} {cold}                */
+    SPH_NLAYOUTS = 10
 } sph_layout;
 
 typedef enum sph_loop { SPH_DENSITY = 0, SPH_GRADIENT = 1, SPH_FORCE = 2 } sph_loop;
@@ -169,7 +173,15 @@ const char *sph_last_error(void);
 sph_status sph_layout_info(sph_layout layout, int32_t *nsub, size_t *sub_bytes);
 
 /* Where component `comp` of `field` lives: substruct index, byte offset in the
- * record and record stride (the getter/setter mapping of Algorithm 1). */
+ * record and record stride (the getter/setter mapping of Algorithm 1).  For
+ * a layout that replicates x this is the primary copy (the first in member
+ * order), which every read takes; every write of x (sph_store_put, the
+ * drift, sph_store_convert) writes all copies, and sph_x_replicas lists the
+ * others. */
+/* Copies of x beyond the primary one: *count of them, replica r in substruct
+ * sub[r] at byte offset offset[r] of the record (component c 8 bytes further);
+ * sub and offset hold at least 3 entries. */
+sph_status sph_x_replicas(sph_layout layout, int32_t *count, int32_t *sub, size_t *offset);
 sph_status sph_field_location(sph_layout layout, sph_field field, int32_t comp, int32_t *sub,
                               size_t *offset, size_t *stride);
 

@@ -21,7 +21,7 @@ SO = os.path.join(HERE, "liboracle.so")
 
 LOOPS = {"density": 0, "gradient": 1, "force": 2}
 LAYOUTS = ["AOS", "AOS_RANDOM", "SAOS_GRAD", "SAOS_FORCE", "SAOS_SHARED", "SAOS_GRAD_TYPE",
-           "SAOS_FORCE_TYPE", "SAOS_SHARED_TYPE", "SOA"]
+           "SAOS_FORCE_TYPE", "SAOS_SHARED_TYPE", "SOA", "SAOS_SHARED_REPL"]
 FIELD_IDS = {"x": 0, "v": 1, "a": 2, "mass": 3, "h": 4, "u": 5, "u_dt": 6, "rho": 7, "rho_dh": 8,
              "wcount": 9, "div_v": 10, "rot_v": 11, "lap_u": 12, "v_sig": 13, "alpha_v": 14,
              "alpha_d": 15, "time_bin": 16, "id": 17, "cold": 18}
@@ -71,6 +71,7 @@ def lib():
     L.or_grid_free.argtypes = [vp]
     L.or_balsara.argtypes = [i64, vp, vp, vp, vp, vp, vp, d, d, vp]
     L.or_layout_info.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(sz)]
+    L.or_x_copies.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(sz)]
     L.or_field_location.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(sz),
                                     C.POINTER(sz)]
     L.or_store_put.argtypes = [C.c_int, i64, vp, C.c_int, vp]
@@ -342,6 +343,17 @@ def full_chain(f: Dict[str, np.ndarray]) -> Dict[str, np.ndarray]:
 # --------------------------------------------------------------------------
 # layouts, store, pack / unpack
 # --------------------------------------------------------------------------
+def x_copies(layout: int):
+    """[(substruct, byte offset of x[0])] of the copies of x after the one that is read"""
+    L = lib()
+    n = C.c_int()
+    sb = (C.c_int * 4)()
+    of = (C.c_size_t * 4)()
+    if L.or_x_copies(layout, C.byref(n), sb, of):
+        raise ValueError(layout)
+    return [(sb[r], of[r]) for r in range(n.value)]
+
+
 def layout_info(layout: int):
     L = lib()
     ns = C.c_int()

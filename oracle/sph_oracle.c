@@ -550,7 +550,9 @@ void or_force(int64_t n, const double *x, const float *v, const float *m, const 
 /* Particle layouts (Sec. 3.1), the oracle's own tables.                    */
 /* A layout is a list of substructs; each substruct is a list of members     */
 /* placed in order at their natural alignment, the record padded to 8 bytes. */
-/* SoA is one array per scalar component.                                    */
+/* SoA is one array per scalar component.  A layout may list x again in      */
+/* later substructs (Sec. 5, data replication): the first copy is the one    */
+/* read, and writing x writes every copy.                                    */
 /* ======================================================================== */
 enum { F_X, F_V, F_A, F_MASS, F_H, F_U, F_UDT, F_RHO, F_RHODH, F_WCOUNT, F_DIV, F_ROT,
        F_LAP, F_VSIG, F_AV, F_AD, F_TBIN, F_ID, F_COLD, NF };
@@ -559,7 +561,7 @@ static const int f_ncomp[NF] = {3, 3, 3, 1, 1, 1, 1, 1, 1, 1, 1, 3, 1, 1, 1, 1, 
 static const int f_csize[NF] = {8, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 1, 8, 8};
 
 enum { L_AOS, L_AOS_RANDOM, L_SAOS_GRAD, L_SAOS_FORCE, L_SAOS_SHARED, L_SAOS_GRAD_TYPE,
-       L_SAOS_FORCE_TYPE, L_SAOS_SHARED_TYPE, L_SOA, NL };
+       L_SAOS_FORCE_TYPE, L_SAOS_SHARED_TYPE, L_SOA, L_SAOS_SHARED_REPL, NL };
 
 #define END (-1)
 #define NEXT (-2)
@@ -593,14 +595,23 @@ static const int lay_shared_t[] = {F_X, NEXT, F_MASS, F_H, NEXT,
                                    F_RHODH, F_DIV, F_ROT, F_AV, F_AD, NEXT,
                                    F_A, F_UDT, F_WCOUNT, F_LAP, F_VSIG, NEXT,
                                    F_TBIN, F_ID, NEXT, F_COLD, END};
+/* pack-shared with the position in every substruct a loop packs from */
+static const int lay_shared_repl[] = {F_X, F_MASS, F_H, NEXT,
+                                      F_X, F_V, F_U, F_RHO, NEXT,
+                                      F_X, F_RHODH, F_DIV, F_ROT, F_AV, F_AD, NEXT,
+                                      F_A, F_UDT, F_WCOUNT, F_LAP, F_VSIG, NEXT,
+                                      F_TBIN, F_ID, F_COLD, END};
 static const int *const lay_lists[NL] = {lay_aos, lay_rand, lay_grad, lay_force, lay_shared,
-                                         lay_grad_t, lay_force_t, lay_shared_t, NULL};
+                                         lay_grad_t, lay_force_t, lay_shared_t, NULL, lay_shared_repl};
 
 typedef struct {
     int nsub;
     size_t sub_bytes[32];
-    int sub_of[NF][5];     /* per field component */
+    int sub_of[NF][5];     /* per field component: the copy that is read */
     size_t off_of[NF][5];
+    int nxcopy;            /* further copies of x */
+    int xcopy_sub[4];
+    size_t xcopy_off[4];   /* offset of x[0]; x[c] 8 bytes further */
 } or_layout;
 
 static int build_layout(int L, or_layout *o)
@@ -625,7 +636,7 @@ static int build_layout(int L, or_layout *o)
         return 0;
     }
     const int *lst = lay_lists[L];
-    int s = 0;
+    int s = 0, seen_x = 0;
     size_t off = 0;
     for (int k = 0;; k++) {
         int f = lst[k];
@@ -638,9 +649,16 @@ static int build_layout(int L, or_layout *o)
         }
         size_t align = f_csize[f] < 8 ? (size_t)f_csize[f] : 8;
         off = (off + align - 1) / align * align;
-        for (int c = 0; c < f_ncomp[f]; c++) {
-            o->sub_of[f][c] = s;
-            o->off_of[f][c] = off + (size_t)c * f_csize[f];
+        if (f == F_X && seen_x) { /* a further copy of the position */
+            o->xcopy_sub[o->nxcopy] = s;
+            o->xcopy_off[o->nxcopy] = off;
+            o->nxcopy++;
+        } else {
+            for (int c = 0; c < f_ncomp[f]; c++) {
+                o->sub_of[f][c] = s;
+                o->off_of[f][c] = off + (size_t)c * f_csize[f];
+            }
+            if (f == F_X) seen_x = 1;
         }
         off += (size_t)f_ncomp[f] * f_csize[f];
     }
@@ -654,6 +672,15 @@ int or_layout_info(int L, int *nsub, size_t *sub_bytes)
     if (build_layout(L, &o)) return -1;
     *nsub = o.nsub;
     for (int s = 0; s < o.nsub; s++) sub_bytes[s] = o.sub_bytes[s];
+    return 0;
+}
+
+int or_x_copies(int L, int *count, int *sub, size_t *off)
+{
+    or_layout o;
+    if (build_layout(L, &o)) return -1;
+    *count = o.nxcopy;
+    for (int r = 0; r < o.nxcopy; r++) { sub[r] = o.xcopy_sub[r]; off[r] = o.xcopy_off[r]; }
     return 0;
 }
 
@@ -681,8 +708,14 @@ int or_store_put(int L, int64_t n, void *const *subs, int f, const void *src)
     const unsigned char *s = (const unsigned char *)src;
     size_t cs = f_csize[f];
     for (int64_t p = 0; p < n; p++)
-        for (int c = 0; c < f_ncomp[f]; c++)
+        for (int c = 0; c < f_ncomp[f]; c++) {
             memcpy(loc_ptr(&o, subs, f, c, p), s + ((size_t)p * f_ncomp[f] + c) * cs, cs);
+            if (f == F_X)
+                for (int r = 0; r < o.nxcopy; r++)
+                    memcpy((unsigned char *)subs[o.xcopy_sub[r]] + (size_t)p * o.sub_bytes[o.xcopy_sub[r]] +
+                               o.xcopy_off[r] + 8 * (size_t)c,
+                           s + ((size_t)p * f_ncomp[f] + c) * cs, cs);
+        }
     return 0;
 }
 

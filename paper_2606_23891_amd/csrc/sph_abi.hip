@@ -72,6 +72,8 @@ struct FieldDesc {
     CompDesc c[6];
     int ncomp;
     int csize;
+    int nrep;                        // replicas of x written beside the primary copy
+    CompDesc rep[kMaxXRep][3];
 };
 
 static FieldDesc field_desc(const sph_store *s, int f)
@@ -85,6 +87,13 @@ static FieldDesc field_desc(const sph_store *s, int f)
         fd.c[c].base = (char *)s->sub[sb] + d.off[f][c];
         fd.c[c].stride = d.sub_bytes[sb];
     }
+    fd.nrep = f == FX ? d.nxrep : 0;
+    for (int r = 0; r < fd.nrep; ++r)
+        for (int c = 0; c < 3; ++c) {
+            const int sb = d.xrep_sub[r];
+            fd.rep[r][c].base = (char *)s->sub[sb] + d.xrep_off[r] + 8 * c;
+            fd.rep[r][c].stride = d.sub_bytes[sb];
+        }
     return fd;
 }
 
@@ -101,6 +110,8 @@ __global__ void k_field_copy(FieldDesc d, int64_t n, const char *src, char *dst,
         if (b == 8) *(uint64_t *)sp = *(const uint64_t *)q;
         else if (b == 4) *(uint32_t *)sp = *(const uint32_t *)q;
         else *sp = *q;
+        for (int r = 0; r < d.nrep; ++r)  // replicated positions (8-byte components)
+            *(uint64_t *)(d.rep[r][c].base + p * d.rep[r][c].stride) = *(const uint64_t *)q;
     } else {
         char *q = dst + i * b;
         if (b == 8) *(uint64_t *)q = *(const uint64_t *)sp;
@@ -237,6 +248,19 @@ sph_status sph_field_location(sph_layout layout, sph_field field, int32_t comp, 
     *sub = d.sub[field][comp];
     *offset = (size_t)d.off[field][comp];
     *stride = (size_t)d.sub_bytes[*sub];
+    return SPH_OK;
+}
+
+sph_status sph_x_replicas(sph_layout layout, int32_t *count, int32_t *sub, size_t *offset)
+{
+    if ((int)layout < 0 || (int)layout >= kNLayouts) return fail(SPH_E_LAYOUT, "unknown layout");
+    if (!count || !sub || !offset) return fail(SPH_E_ARG, "null output");
+    const LayoutDesc &d = kLayouts[layout];
+    *count = d.nxrep;
+    for (int r = 0; r < d.nxrep; ++r) {
+        sub[r] = d.xrep_sub[r];
+        offset[r] = (size_t)d.xrep_off[r];
+    }
     return SPH_OK;
 }
 

@@ -58,6 +58,15 @@ template <int L, int F, int C, typename T>
 __device__ __forceinline__ void st(const StoreArg &s, int64_t p, T v)
 {
     *reinterpret_cast<T *>(field_ptr<L, F, C>(s, p)) = v;
+    if constexpr (F == FX) {
+        // replicated positions: every copy holds the same bits
+        static_for<0, kLayouts[L].nxrep>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            constexpr int sb = kLayouts[L].xrep_sub[r];
+            char *base = (char *)__builtin_assume_aligned(s.sub[sb], 256);
+            *reinterpret_cast<T *>(base + p * kLayouts[L].sub_bytes[sb] + kLayouts[L].xrep_off[r] + 8 * C) = v;
+        });
+    }
 }
 
 struct PackArgs {
@@ -447,6 +456,7 @@ int fission_passes(int layout, int loop, int schedule, bool unpack, uint32_t *ma
     case 6: return passes_l<6>(loop, schedule, unpack, masks);
     case 7: return passes_l<7>(loop, schedule, unpack, masks);
     case 8: return passes_l<8>(loop, schedule, unpack, masks);
+    case 9: return passes_l<9>(loop, schedule, unpack, masks);
     default: return 0;
     }
 }
@@ -537,7 +547,7 @@ __device__ __forceinline__ void read_record(const StoreArg &st, int64_t p, uint3
             constexpr int F = decltype(fc)::value;
             static_for<0, kNComp[F]>([&](auto cc) {
                 constexpr int C = decltype(cc)::value;
-                if constexpr (kLayouts[L].sub[F][C] == S) v[word_of(F, C)] = *(const uint8_t *)base;
+                if constexpr (has_member(kLayouts[L], F, C, S)) v[word_of(F, C)] = *(const uint8_t *)base;
             });
         });
     } else {
@@ -563,8 +573,8 @@ __device__ __forceinline__ void read_record(const StoreArg &st, int64_t p, uint3
             constexpr int F = decltype(fc)::value;
             static_for<0, kNComp[F]>([&](auto cc) {
                 constexpr int C = decltype(cc)::value;
-                if constexpr (kLayouts[L].sub[F][C] == S) {
-                    constexpr int off = kLayouts[L].off[F][C], k = word_of(F, C);
+                if constexpr (has_member(kLayouts[L], F, C, S)) {
+                    constexpr int off = member_off(kLayouts[L], F, C, S), k = word_of(F, C);
                     if constexpr (kCompBytes[F] == 8) {
                         v[k] = w[off / 4];
                         v[k + 1] = w[off / 4 + 1];
@@ -591,7 +601,7 @@ __device__ __forceinline__ void write_record(const StoreArg &st, int64_t p, cons
             constexpr int F = decltype(fc)::value;
             static_for<0, kNComp[F]>([&](auto cc) {
                 constexpr int C = decltype(cc)::value;
-                if constexpr (kLayouts[L].sub[F][C] == S) *(uint8_t *)base = (uint8_t)v[word_of(F, C)];
+                if constexpr (has_member(kLayouts[L], F, C, S)) *(uint8_t *)base = (uint8_t)v[word_of(F, C)];
             });
         });
     } else {
@@ -602,8 +612,8 @@ __device__ __forceinline__ void write_record(const StoreArg &st, int64_t p, cons
             constexpr int F = decltype(fc)::value;
             static_for<0, kNComp[F]>([&](auto cc) {
                 constexpr int C = decltype(cc)::value;
-                if constexpr (kLayouts[L].sub[F][C] == S) {
-                    constexpr int off = kLayouts[L].off[F][C], k = word_of(F, C);
+                if constexpr (has_member(kLayouts[L], F, C, S)) {
+                    constexpr int off = member_off(kLayouts[L], F, C, S), k = word_of(F, C);
                     if constexpr (kCompBytes[F] == 8) {
                         w[off / 4] = v[k];
                         w[off / 4 + 1] = v[k + 1];
@@ -660,6 +670,7 @@ static sph_status convert_l(int ld, const StoreArg &src, const StoreArg &dst, in
     case 6: return convert_ll<LS, 6>(src, dst, n, st);
     case 7: return convert_ll<LS, 7>(src, dst, n, st);
     case 8: return convert_ll<LS, 8>(src, dst, n, st);
+    case 9: return convert_ll<LS, 9>(src, dst, n, st);
     default: return fail(SPH_E_LAYOUT, "unknown layout");
     }
 }
@@ -1000,7 +1011,7 @@ static sph_status cfl_l(const CflArgs &a, hipStream_t st)
     case 2: return fn<2>(__VA_ARGS__); case 3: return fn<3>(__VA_ARGS__);            \
     case 4: return fn<4>(__VA_ARGS__); case 5: return fn<5>(__VA_ARGS__);            \
     case 6: return fn<6>(__VA_ARGS__); case 7: return fn<7>(__VA_ARGS__);            \
-    case 8: return fn<8>(__VA_ARGS__);                                              \
+    case 8: return fn<8>(__VA_ARGS__); case 9: return fn<9>(__VA_ARGS__);            \
     default: return fail(SPH_E_LAYOUT, "unknown layout");                           \
     }
 
@@ -1178,6 +1189,7 @@ sph_status launch_drift(const sph_plan *p, const sph_store *s, double dt, void *
     case 6: r = drift_l<6>(a, st); break;
     case 7: r = drift_l<7>(a, st); break;
     case 8: r = drift_l<8>(a, st); break;
+    case 9: r = drift_l<9>(a, st); break;
     default: return fail(SPH_E_LAYOUT, "unknown layout");
     }
     if (r) return r;
@@ -1205,6 +1217,7 @@ sph_status launch_cfl(const sph_plan *p, const sph_store *s, float cfl, void *ws
     case 6: r = cfl_l<6>(a, st); break;
     case 7: r = cfl_l<7>(a, st); break;
     case 8: r = cfl_l<8>(a, st); break;
+    case 9: r = cfl_l<9>(a, st); break;
     default: return fail(SPH_E_LAYOUT, "unknown layout");
     }
     if (r) return r;

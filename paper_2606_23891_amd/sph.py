@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libsph.so")
 DENSITY, GRADIENT, FORCE = 0, 1, 2
 LOOPS = (DENSITY, GRADIENT, FORCE)
 LAYOUTS = ["AOS", "AOS_RANDOM", "SAOS_GRAD", "SAOS_FORCE", "SAOS_SHARED", "SAOS_GRAD_TYPE",
-           "SAOS_FORCE_TYPE", "SAOS_SHARED_TYPE", "SOA"]
+           "SAOS_FORCE_TYPE", "SAOS_SHARED_TYPE", "SOA", "SAOS_SHARED_REPL"]
 FIELDS = ["x", "v", "a", "mass", "h", "u", "u_dt", "rho", "rho_dh", "wcount", "div_v", "rot_v",
           "lap_u", "v_sig", "alpha_v", "alpha_d", "time_bin", "id", "cold"]
 FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
@@ -64,6 +64,7 @@ _SIGS = {
     "sph_last_error": ([], C.c_char_p),
     "sph_layout_info": ([i32, C.POINTER(i32), C.POINTER(sz)], i32),
     "sph_field_location": ([i32, i32, i32, C.POINTER(i32), C.POINTER(sz), C.POINTER(sz)], i32),
+    "sph_x_replicas": ([i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(sz)], i32),
     "sph_field_info": ([i32, C.POINTER(i32), C.POINTER(i32)], i32),
     "sph_pack_layout": ([i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)], i32),
     "sph_fission_passes": ([i32, i32, i32, C.POINTER(i32), C.POINTER(C.c_uint32), C.POINTER(i32),
@@ -180,6 +181,15 @@ def sph_field_location(layout: int, field: int, comp: int):
     _check(lib().sph_field_location(layout, field, comp, C.byref(s), C.byref(o), C.byref(st)),
            "sph_field_location")
     return s.value, o.value, st.value
+
+
+def sph_x_replicas(layout: int):
+    """[(substruct, byte offset of component 0)] of the copies of x beyond the primary one"""
+    n = i32()
+    sb = (i32 * 3)()
+    of = (sz * 3)()
+    _check(lib().sph_x_replicas(layout, C.byref(n), sb, of), "sph_x_replicas")
+    return [(sb[r], of[r]) for r in range(n.value)]
 
 
 def sph_field_info(field: int):

@@ -29,9 +29,10 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(sph._SIGS), set(names) ^ set(sph._SIGS)
 
 
-@pytest.mark.parametrize("layout", range(9))
+@pytest.mark.parametrize("layout", range(10))
 def test_layout_tables_match_oracle(layout):
     assert sph.sph_layout_info(layout) == oracle.layout_info(layout)
+    assert sph.sph_x_replicas(layout) == oracle.x_copies(layout)
     for name, fid in sph.FIELD_ID.items():
         nc, cb = sph.sph_field_info(fid)
         assert (nc, cb) == (oracle.FIELD_TYPES[name][1], np.dtype(oracle.FIELD_TYPES[name][0]).itemsize)
@@ -57,7 +58,7 @@ _RESULTS = [[("rho", 0), ("rho_dh", 0), ("wcount", 0)],
             [("a", 0), ("a", 1), ("a", 2), ("u_dt", 0)]]
 
 
-@pytest.mark.parametrize("layout", range(9))
+@pytest.mark.parametrize("layout", range(10))
 def test_fission_passes_partition_by_schedule_key(layout):
     """every schedule's pass masks partition the loop's members, members of a
     pass share the schedule's key (none / substruct / field / component type /
@@ -121,7 +122,7 @@ def test_validation_errors_before_any_launch():
     # unknown layout / loop
     nsub = C.c_int32()
     sb = (C.c_size_t * 32)()
-    assert L.sph_layout_info(9, C.byref(nsub), sb) == -2
+    assert L.sph_layout_info(10, C.byref(nsub), sb) == -2
     assert L.sph_pack_layout(3, C.byref(nsub), (C.c_int32 * 5)(), C.byref(nsub)) == -1
     # plan validation
     ps = inputs.make_config(0, n_side=8, grid=4)

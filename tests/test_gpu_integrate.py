@@ -29,7 +29,7 @@ def _setup(seed=21, layout="SAOS_SHARED"):
     return ps, f, plan, st, ws
 
 
-@pytest.mark.parametrize("layout", ["AOS", "SAOS_SHARED", "SOA"])
+@pytest.mark.parametrize("layout", ["AOS", "SAOS_SHARED", "SOA", "SAOS_SHARED_REPL"])
 def test_kick_drift_cfl_bitexact(layout):
     import torch
     ps, f, plan, st, ws = _setup(layout=layout)
@@ -43,6 +43,11 @@ def test_kick_drift_cfl_bitexact(layout):
     assert st.get("x").tobytes() == xn.tobytes()
     assert mo == out.max()
     assert mh == f["h"].max()
+    # the whole store, every copy of a replicated position included, as the
+    # oracle's store of the kicked and drifted fields
+    host = oracle.HostStore(sph.LAYOUTS.index(layout), ps.n)
+    host.put_all(dict(f, v=v, u=u, x=xn))
+    assert st.raw() == host.raw()
     dt = sph.sph_cfl_dt(plan, st, ws, cfl=0.2)
     assert np.float32(dt) == oracle.cfl_dt(f["h"], f["v_sig"], 0.2)
     torch.cuda.synchronize()

@@ -31,7 +31,7 @@ def sets():
     return _small_sets()
 
 
-@pytest.mark.parametrize("layout", range(9))
+@pytest.mark.parametrize("layout", range(10))
 def test_store_bytes_match_oracle(layout):
     ps = inputs.make_config(0, n_side=8, grid=4)
     f = inputs.random_fields(ps.n, 7, x=ps.fields["x"])
@@ -49,7 +49,7 @@ def _ranges(ntask):
     return [(0, ntask), (0, 1), (ntask // 2, ntask // 2 + 1), (3, min(ntask, 40)), (ntask - 1, ntask), (5, 5)]
 
 
-@pytest.mark.parametrize("layout", range(9))
+@pytest.mark.parametrize("layout", range(10))
 def test_pack_bitexact(sets, layout):
     import torch
     for name, ps in sets.items():
@@ -74,7 +74,7 @@ def test_pack_bitexact(sets, layout):
         plan.close()
 
 
-@pytest.mark.parametrize("layout", range(9))
+@pytest.mark.parametrize("layout", range(10))
 def test_unpack_bitexact(sets, layout):
     import torch
     rng = np.random.default_rng(3)
@@ -101,7 +101,7 @@ def test_unpack_bitexact(sets, layout):
         plan.close()
 
 
-@pytest.mark.parametrize("layout", range(9))
+@pytest.mark.parametrize("layout", range(10))
 def test_cells_pack_unpack_bitexact(sets, layout):
     import torch
     rng = np.random.default_rng(5)
@@ -132,7 +132,7 @@ def test_cells_pack_unpack_bitexact(sets, layout):
         plan.close()
 
 
-@pytest.mark.parametrize("layout", [0, 1, 4, 7, 8])
+@pytest.mark.parametrize("layout", [0, 1, 4, 7, 8, 9])
 def test_fission_schedules_bitexact(sets, layout):
     """every loop-fission schedule of the batched pack and unpack writes the
     same bytes as the fused kernels (pack buffers pre-filled with a pattern,
@@ -211,16 +211,16 @@ def test_store_convert_bitexact():
     x = inputs.random_fields(n, 29)["x"]
     f = inputs.random_fields(n, 31, x=x)
     refs = {}
-    for ld in range(9):
+    for ld in range(10):
         host = oracle.HostStore(ld, n, fill=0)
         host.put_all(f)
         refs[ld] = host.raw()
-    for ls in range(9):
+    for ls in range(10):
         src = sph.Store(ls, n)
         for t in src.subs:
             t.fill_(0x5A)
         src.put_all(f)
-        for ld in range(9):
+        for ld in range(10):
             log(f"convert {sph.LAYOUTS[ls]} -> {sph.LAYOUTS[ld]} n={n}")
             dst = sph.Store(ld, n)
             for t in dst.subs:

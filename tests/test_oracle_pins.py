@@ -249,7 +249,7 @@ def _classes(layout):
     return out
 
 
-@pytest.mark.parametrize("layout", range(9))
+@pytest.mark.parametrize("layout", range(10))
 def test_layout_tables_are_consistent(layout):
     sb = oracle.layout_info(layout)
     used = [np.zeros(b, bool) for b in sb]
@@ -299,7 +299,7 @@ def _store_and_fields(layout, n=300, seed=3, x=None):
     return st, f
 
 
-@pytest.mark.parametrize("layout", range(9))
+@pytest.mark.parametrize("layout", range(10))
 def test_store_roundtrip(layout):
     st, f = _store_and_fields(layout)
     for k, v in f.items():
@@ -316,7 +316,7 @@ def test_pack_identical_across_layouts(loop):
     ps = _tiny_set()
     f = inputs.random_fields(ps.n, 5, x=ps.fields["x"])
     bufs = []
-    for lay in range(9):
+    for lay in range(10):
         st = oracle.HostStore(lay, ps.n, fill=0x5A)
         st.put_all(f)
         bufs.append(oracle.pack(st, loop, ps.cells, ps.tasks, 0, len(ps.tasks)))
