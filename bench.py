@@ -1,10 +1,11 @@
 """Benchmark of the SPH pack / interact / unpack hot path on one MI355X.
 
-One step = density -> gradient -> force, each as pack -> interaction ->
-unpack, over the whole synthetic workload (inputs resident in HBM).  The
-timed region runs the batched form stage by stage on one stream with HIP
-events between the stages, so every kernel's average duration is measured
-inside the timed region.  Reported beside it: the same step replayed as one
+One step = density -> gradient -> force, each as pack -> interaction, then
+one write-back of every output (the unpacks folded into one pass at the end
+of the step), over the whole synthetic workload (inputs resident in HBM).
+The timed region runs the batched step stage by stage on one stream with HIP
+events between the seven stages, so every kernel's average duration is
+measured inside the timed region.  Reported beside it: the same step replayed as one
 captured HIP graph, the per-task form (one launch per task and stage, the
 paper's offload cycle with single-task bundles), and the CPU oracle timed on
 a bounded sample of the same workload.
@@ -30,13 +31,23 @@ METRIC = "pair interactions/s + pack/unpack GB/s (batched vs per-task, FP32 @1e-
 # FP32 operations the pair body of each loop executes per interacting pair
 # (add, mul, min/max, sqrt, rsqrt, rcp = 1; fma = 2; the candidate test excluded)
 PAIR_FLOPS = {0: 32, 1: 55, 2: 81}
-# algorithmic HBM bytes per particle: fields read from the store + packed record
-# written (+ 32 bytes of tile bounds per 64 particles); unpack: result read +
-# outputs written
+# the same per-pair work as fixed beforehand from the SPH formulas (a textbook
+# count of the terms, independent of this implementation's folding)
+PAIR_FLOPS_FORMULA = {0: 18, 1: 50, 2: 110}
+# algorithmic HBM bytes per particle, per-loop form: fields read from the
+# store + packed record written (+ 32 bytes of tile bounds per 64 particles);
+# unpack: result read + outputs written
 PACK_BYTES = {0: 32 + 20 + 0.5, 1: 52 + 40 + 0.5, 2: 80 + 68 + 0.5}
 UNPACK_BYTES = {0: 12 + 12, 1: 24 + 24, 2: 16 + 16}
-# interaction kernel: its packed records read once + its result planes written
-INTERACT_BYTES = {0: 20 + 0.5 + 12, 1: 40 + 0.5 + 24, 2: 68 + 0.5 + 16}
+# staged step: the gradient / force packs read the fields earlier loops of the
+# step produce from its result planes (4 / 24 bytes) instead of the store, and
+# write the derived planes of the pair term (16 / 32 bytes); one write-back
+# reads every result (52 bytes) and writes every output (52 bytes)
+STEP_PACK_BYTES = {0: 32 + 20 + 0.5, 1: 48 + 4 + 40 + 0.5 + 16, 2: 56 + 24 + 68 + 0.5 + 32}
+WRITEBACK_BYTES = 52 + 52
+# interaction kernel: its packed records and derived planes read once + its
+# result planes written
+INTERACT_BYTES = {0: 20 + 0.5 + 12, 1: 40 + 16 + 0.5 + 24, 2: 68 + 32 + 0.5 + 16}
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 LOOP_NAME = {0: "density", 1: "gradient", 2: "force"}
@@ -90,32 +101,32 @@ TRAFFIC_SUMMARY = "hbm_traffic_gresho256.md"
 
 
 def stage_kernels(stage, layout, tuning):
-    """the kernels a batched stage launches (demangled names; the queue reset
-    of the interaction stages, a one-thread kernel, is left out)"""
+    """the kernels a stage of the staged batched step launches (demangled
+    names; the queue reset of the interaction stages, a one-thread kernel, is
+    left out)"""
+    if stage == "writeback":
+        return [f"void sph::k_writeback<{layout}>(sph::UnpackArgs)"]
     for L, nm in LOOP_NAME.items():
-        split = getattr(tuning, "pack_schedule", 0) != 0
         if stage == f"pack_{nm}":
-            if split:
-                return [f"void sph::k_pack_pass<{layout}, {L}>(sph::PackArgs, unsigned int)"]
-            return [f"void sph::k_pack<{layout}, {L}>(sph::PackArgs)"]
-        if stage == f"unpack_{nm}":
-            return [f"void sph::k_unpack_chunks<{layout}, {L}, true, {'true' if split else 'false'}>(sph::UnpackArgs)"]
+            return [f"void sph::k_pack<{layout}, {L}, true>(sph::PackArgs)"]
         if stage == nm:
-            k = [f"void sph::k_interact<{L}, 1, {tuning.window[L]}, false>(sph::InteractArgs)"]
-            return ([f"void sph::k_prep<{L}>(sph::PrepArgs)"] if L >= 1 else []) + k
+            return [f"void sph::k_interact<{L}, 1, {tuning.window[L]}, false>(sph::InteractArgs)"]
     raise KeyError(stage)
 
 
 def stage_bytes(stage, n):
-    """algorithmic HBM bytes of one launch of a batched stage"""
+    """algorithmic HBM bytes of one launch of a stage of the staged step"""
+    if stage == "writeback":
+        return WRITEBACK_BYTES * n
     for L, nm in LOOP_NAME.items():
         if stage == f"pack_{nm}":
-            return PACK_BYTES[L] * n
-        if stage == f"unpack_{nm}":
-            return UNPACK_BYTES[L] * n
+            return STEP_PACK_BYTES[L] * n
         if stage == nm:
             return INTERACT_BYTES[L] * n
     raise KeyError(stage)
+
+
+STAGES = ["pack_density", "density", "pack_gradient", "gradient", "pack_force", "force", "writeback"]
 
 
 def workload_name(k, ps):
@@ -164,23 +175,27 @@ def main():
     elif a.tuning != "default":
         tune.apply(tuning, json.load(open(a.tuning)))
         tuned_from = a.tuning
+    if tuning.pack_schedule != 0:
+        log("the staged step packs each loop in one kernel: the tuning's loop-fission schedule is not used")
+        tuning.pack_schedule = 0
     log(f"tuning ({tuned_from}): blocks/CU {tuning.blocks_per_cu} per loop {list(tuning.blocks_per_loop)} "
         f"windows {list(tuning.window)} queue {tuning.queue} pack waves {tuning.pack_waves}")
     params = sph.default_params()
     stream = torch.cuda.current_stream()
     bufs = {L: sph.cell_buffers(plan, L) for L in range(3)}
     ws = sph.interact_ws(plan)
+    sws = torch.zeros(sph.sph_batched_ws_bytes(plan), dtype=torch.uint8, device="cuda")
 
-    def stage(L, s):
-        pack, res = bufs[L]
-        if s == 0:
-            sph.sph_pack_cells(plan, L, store, pack, tuning)
-        elif s == 1:
-            sph.sph_interact_cells(plan, L, pack, res, ws, params=params, tuning=tuning)
+    def stage(i):
+        # the staged step: pack and interactions per loop, one write-back
+        if i == 6:
+            sph.sph_step_writeback(plan, store, sws, tuning=tuning)
+        elif i % 2 == 0:
+            sph.sph_step_pack(plan, i // 2, store, sws, params=params, tuning=tuning)
         else:
-            sph.sph_unpack_cells(plan, L, res, store, tuning)
+            sph.sph_step_interact(plan, i // 2, sws, params=params, tuning=tuning)
 
-    # interaction counts (untimed)
+    # interaction counts (untimed, per-loop form with the counting kernels)
     pairs = {}
     cnt = torch.zeros(ps.n, dtype=torch.int32, device="cuda")
     for L in range(3):
@@ -192,33 +207,31 @@ def main():
         pairs[L] = int(cnt.to(torch.int64).sum().item())
     total_pairs = sum(pairs.values())
     log(f"interacting pairs per step: {pairs}")
+    del bufs, ws
+    torch.cuda.empty_cache()
 
     for _ in range(a.warmup):
-        for L in range(3):
-            for s in range(3):
-                stage(L, s)
+        for i in range(7):
+            stage(i)
     torch.cuda.synchronize()
 
-    # timed region: K steps, events between all 9 stages
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(10)] for _ in range(a.steps)]
+    # timed region: K steps, events between all 7 stages
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(8)] for _ in range(a.steps)]
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     for k in range(a.steps):
         ev[k][0].record(stream)
-        i = 1
-        for L in range(3):
-            for s in range(3):
-                stage(L, s)
-                ev[k][i].record(stream)
-                i += 1
+        for i in range(7):
+            stage(i)
+            ev[k][i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    stage_ms = np.zeros(9)
+    stage_ms = np.zeros(7)
     step_ms = []
     for k in range(a.steps):
-        for i in range(9):
+        for i in range(7):
             stage_ms[i] += ev[k][i].elapsed_time(ev[k][i + 1])
-        step_ms.append(ev[k][0].elapsed_time(ev[k][9]))
+        step_ms.append(ev[k][0].elapsed_time(ev[k][7]))
     stage_ms /= a.steps
     ms_per_step = float(np.mean(step_ms))
     value = total_pairs / (ms_per_step * 1e-3)
@@ -226,26 +239,35 @@ def main():
 
     stages = {}
     n = ps.n
-    for L in range(3):
-        p_ms, i_ms, u_ms = stage_ms[3 * L:3 * L + 3]
-        stages[f"pack_{LOOP_NAME[L]}"] = {"ms": p_ms, "GB/s": PACK_BYTES[L] * n / (p_ms * 1e-3) / 1e9}
-        stages[f"{LOOP_NAME[L]}"] = {"ms": i_ms, "pairs": pairs[L],
-                                     "TFLOP/s": PAIR_FLOPS[L] * pairs[L] / (i_ms * 1e-3) / 1e12,
-                                     "pairs/s": pairs[L] / (i_ms * 1e-3)}
-        stages[f"unpack_{LOOP_NAME[L]}"] = {"ms": u_ms, "GB/s": UNPACK_BYTES[L] * n / (u_ms * 1e-3) / 1e9}
-    pu_bytes = sum((PACK_BYTES[L] + UNPACK_BYTES[L]) * n for L in range(3))
-    pu_ms = sum(stage_ms[3 * L] + stage_ms[3 * L + 2] for L in range(3))
+    for i, nm in enumerate(STAGES):
+        ms = float(stage_ms[i])
+        if nm in LOOP_NAME.values():
+            L = [k for k, v in LOOP_NAME.items() if v == nm][0]
+            stages[nm] = {"ms": ms, "pairs": pairs[L],
+                          "TFLOP/s": PAIR_FLOPS[L] * pairs[L] / (ms * 1e-3) / 1e12,
+                          "TFLOP/s_formula_count": PAIR_FLOPS_FORMULA[L] * pairs[L] / (ms * 1e-3) / 1e12,
+                          "pairs/s": pairs[L] / (ms * 1e-3),
+                          "GB/s": stage_bytes(nm, n) / (ms * 1e-3) / 1e9}
+        else:
+            stages[nm] = {"ms": ms, "GB/s": stage_bytes(nm, n) / (ms * 1e-3) / 1e9}
+    pu = [k for k in STAGES if k.startswith("pack_") or k == "writeback"]
+    pu_bytes = sum(stage_bytes(k, n) for k in pu)
+    pu_ms = sum(stages[k]["ms"] for k in pu)
     pack_unpack_gbs = pu_bytes / (pu_ms * 1e-3) / 1e9
 
     # dominant kernel and its roofline
     names = list(stages)
     dom = names[int(np.argmax([stages[k]["ms"] for k in names]))]
-    if "GB/s" in stages[dom]:
+    if "TFLOP/s" not in stages[dom]:
         roof = {"kernel": dom, "bound": "hbm", "achieved": stages[dom]["GB/s"], "peak": PEAK_HBM_GBS,
                 "unit": "GB/s"}
     else:
         roof = {"kernel": dom, "bound": "alu", "achieved": stages[dom]["TFLOP/s"], "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s"}
+                "unit": "TFLOP/s", "flops_per_pair": PAIR_FLOPS[names.index(dom) // 2],
+                "achieved_formula_count": stages[dom]["TFLOP/s_formula_count"],
+                "flops_per_pair_formula_count": PAIR_FLOPS_FORMULA[names.index(dom) // 2],
+                "kernel_ms": stages[dom]["ms"]}
+        roof["frac_formula_count"] = roof["achieved_formula_count"] / roof["peak"]
     roof["frac"] = roof["achieved"] / roof["peak"]
     # HBM bytes per launch of that kernel from the committed counter summary of
     # this workload, if it was taken from the current kernel sources
@@ -264,7 +286,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "pair interactions/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": workload_name(a.config, ps), "layout": a.layout, "form": "batched",
+        "config": {"workload": workload_name(a.config, ps), "layout": a.layout, "form": "batched, staged",
                    "pairs_per_step": total_pairs, "device": tune.device_key(dev), "cu": dev.multi_processor_count,
                    "tuning": {"source": tuned_from, "blocks_per_cu": tuning.blocks_per_cu,
                               "blocks_per_loop": list(tuning.blocks_per_loop),
@@ -293,7 +315,7 @@ def main():
 
     # the same step as one captured graph
     if not a.no_graph:
-        wsb = torch.zeros(sph.sph_batched_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+        wsb = sws
         g = sph.Graph(plan, store, wsb, params=params, tuning=tuning)
         g.launch(stream)
         torch.cuda.synchronize()
@@ -375,7 +397,7 @@ def main():
 
     # the CPU oracle on a bounded sample of the same workload
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(ps, store, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(ps, store, a.cpu_seconds, a.layout)
 
     print(json.dumps(out), flush=True)
 
@@ -684,9 +706,13 @@ def offload_sweep(ps, plan, names, tuning, reps=2):
     return res
 
 
-def cpu_baseline(ps, store, budget_s):
-    """Oracle (FP64 brute force over all N, OpenMP) on sampled rows, all three
-    loops; unit scaled to interacting pairs per second."""
+def cpu_baseline(ps, store, budget_s, layout_name):
+    """The oracle timed on the host: its interaction loops (FP64, OpenMP, the
+    candidate-grid mode: every particle within the largest support visited,
+    the same sums as its brute force) on sampled rows, all three loops, in
+    interacting pairs per second; beside it the oracle's plain-C pack and
+    unpack (per-loop form, one host thread) of the workload's first cells in
+    GB/s of the same algorithmic bytes as the device figures."""
     import oracle
 
     f = ps.fields
@@ -699,7 +725,7 @@ def cpu_baseline(ps, store, budget_s):
     # grow the sample until one run takes at least half the budget (the oracle
     # converts its whole input on every call, so short runs are overhead) and
     # report that run
-    nrow = 32
+    nrow = 1024
     while True:
         rows = rng.choice(ps.n, nrow, replace=False)
         t0 = time.perf_counter()
@@ -708,17 +734,50 @@ def cpu_baseline(ps, store, budget_s):
         if dt >= 0.5 * budget_s or nrow >= ps.n:
             break
         nrow = int(min(ps.n, nrow * min(8.0, max(2.0, 0.8 * budget_s / dt))))
-    return {"value": c / dt, "unit": "pair interactions/s", "cores": cores, "kind": "oracle",
-            "sample": f"{nrow} random particles of the workload, density+gradient+force, each summed by "
-                      f"brute force over all {ps.n} particles in FP64 ({dt:.1f} s)",
+    out = {"value": c / dt, "unit": "pair interactions/s", "cores": cores, "kind": "oracle",
+           "sample": f"{nrow} random particles of the workload, density+gradient+force, each summed over the "
+                     f"particles of the oracle's candidate grid (FP64; the same sums as its brute force over "
+                     f"all {ps.n}) ({dt:.1f} s)",
+           "seconds": dt}
+    out["host_pack_unpack"] = _oracle_pack_unpack(oracle, ps, sph_layout_index(layout_name))
+    return out
+
+
+def sph_layout_index(name):
+    import oracle
+    return oracle.LAYOUTS.index(name)
+
+
+def _oracle_pack_unpack(oracle, ps, layout, target=1 << 20):
+    """the oracle's pack and unpack of every loop (per-loop form: pack, then
+    unpack of a result buffer) over the first cells holding about `target`
+    particles, one host thread"""
+    csum = np.cumsum(ps.cells["count"])
+    k = int(min(len(csum), np.searchsorted(csum, target) + 1))
+    n_sub = int(csum[k - 1])
+    cells = np.ascontiguousarray(ps.cells[:k])
+    host = oracle.HostStore(layout, n_sub)
+    host.put_all({name: np.ascontiguousarray(v[:n_sub]) for name, v in ps.fields.items()})
+    rng = np.random.default_rng(1)
+    res = {L: rng.uniform(-1, 1, (oracle.RESULT_PLANES[L], oracle.round_slots(n_sub))).astype(np.float32)
+           for L in range(3)}
+    t0 = time.perf_counter()
+    for L in range(3):
+        oracle.pack_cells(host, L, cells)
+        oracle.unpack_cells(host, L, res[L])
+    dt = time.perf_counter() - t0
+    nbytes = sum((PACK_BYTES[L] + UNPACK_BYTES[L]) * n_sub for L in range(3))
+    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"pack + unpack of the three loops over the first {k} cells ({n_sub} particles) of the "
+                      f"workload, {oracle.LAYOUTS[layout]} store, per-loop form ({dt:.2f} s)",
             "seconds": dt}
 
 
 def _oracle_rows(oracle, f, rho, rdh, D, R, rows):
-    d = oracle.density(f["x"], f["mass"], f["h"], rows=rows)
-    g = oracle.gradient(f["x"], f["v"], f["mass"], f["h"], f["u"], rho, rows=rows)
+    d = oracle.density(f["x"], f["mass"], f["h"], rows=rows, grid=True)
+    g = oracle.gradient(f["x"], f["v"], f["mass"], f["h"], f["u"], rho, rows=rows, grid=True)
     fo = oracle.force(f["x"], f["v"], f["mass"], f["h"], f["u"], rho, rdh, D, R, f["alpha_v"], f["alpha_d"],
-                      rows=rows)
+                      rows=rows, grid=True)
     return int(d["count"].sum() + g["count"].sum() + fo["count"].sum())
 
 

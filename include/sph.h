@@ -338,9 +338,30 @@ sph_status sph_interact_cells(const sph_plan *plan, sph_loop loop, const void *p
 /* out = +0.0f + result (V: the larger of +0.0f and the result). */
 sph_status sph_unpack_cells(const sph_plan *plan, sph_loop loop, const void *res_buf, size_t res_bytes,
                             const sph_store *store, const sph_tuning *tuning, void *stream);
-/* density -> gradient -> force, each pack -> interact -> unpack. */
+/* density -> gradient -> force over the whole store, in stages: pack the
+ * density record, density, pack the gradient record (rho taken from the
+ * density results), gradient, pack the force record (rho, rho_dh, D, R from
+ * the earlier results, the force pair term's derived per-particle planes
+ * written beside it), force, then one write-back of every output into the
+ * store -- the unpacks of Sec. 2.3 folded into one pass at the end of the
+ * step.  The store ends bit for bit as after pack -> interact -> unpack per
+ * loop (sph_pack_cells / sph_interact_cells / sph_unpack_cells).  With a
+ * loop-fission pack schedule (tuning->pack_schedule != 0) every loop is
+ * unpacked into the store before the next packs from it.  ws: device memory
+ * of sph_batched_ws_bytes, 256-byte aligned, caller-owned, overwritten. */
 sph_status sph_step_batched(const sph_plan *plan, const sph_store *store, const sph_params *params,
                             const sph_tuning *tuning, void *ws, size_t ws_bytes, void *stream);
+/* The stages of sph_step_batched, one call each (same ws; the step's result
+ * planes and pack buffer live in it): sph_step_pack for density, gradient,
+ * force in turn, each followed by sph_step_interact of the same loop, then
+ * sph_step_writeback.  Results between the calls exist only in ws. */
+sph_status sph_step_pack(const sph_plan *plan, sph_loop loop, const sph_store *store,
+                         const sph_params *params, const sph_tuning *tuning, void *ws, size_t ws_bytes,
+                         void *stream);
+sph_status sph_step_interact(const sph_plan *plan, sph_loop loop, const sph_params *params,
+                             const sph_tuning *tuning, void *ws, size_t ws_bytes, void *stream);
+sph_status sph_step_writeback(const sph_plan *plan, const sph_store *store, const sph_tuning *tuning,
+                              void *ws, size_t ws_bytes, void *stream);
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the step of
  * sph_step_batched with its workspace taken from a static per-device scratch

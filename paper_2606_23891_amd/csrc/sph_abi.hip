@@ -866,12 +866,32 @@ static sph_status batched_checks(const sph_plan *p, int loop)
     return SPH_OK;
 }
 
+// workspace of the staged step: the interaction workspace (queue counters and
+// derived planes) of the force loop, the largest pack buffer, then the result
+// planes of all three loops
+struct StepWs {
+    char *q;      // interaction workspace
+    char *pack;   // pack buffer
+    float *res;   // kStepPlanes planes of round_slots(n) floats
+};
+static size_t step_ws_bytes(const sph_plan *p)
+{
+    return interact_ws_bytes_for(2, p->n) + pack_bytes_for(2, p->n, p->ntile) +
+           (size_t)round_slots(p->n) * 4 * kStepPlanes;
+}
+static StepWs step_ws(const sph_plan *p, void *ws)
+{
+    StepWs w;
+    w.q = (char *)ws;
+    w.pack = w.q + interact_ws_bytes_for(2, p->n);
+    w.res = (float *)(w.pack + pack_bytes_for(2, p->n, p->ntile));
+    return w;
+}
+
 sph_status sph_batched_ws_bytes(const sph_plan *p, size_t *bytes)
 {
     if (!p || !bytes) return fail(SPH_E_ARG, "null argument");
-    // interaction workspace (queue + derived planes) of the force loop, the
-    // largest pack buffer and the largest result buffer
-    *bytes = interact_ws_bytes_for(2, p->n) + pack_bytes_for(2, p->n, p->ntile) + result_bytes_for(1, p->n);
+    *bytes = step_ws_bytes(p);
     return SPH_OK;
 }
 
@@ -946,17 +966,44 @@ static sph_status step_batched(const sph_plan *p, const sph_store *store, const 
     sph_tuning def;
     sph_tuning_default(&def);
     if (!tn) tn = &def;
-    char *base = (char *)ws;
-    void *q = base;  // queue counter, then the derived planes
-    void *pack = base + interact_ws_bytes_for(2, p->n);
-    void *res = (char *)pack + pack_bytes_for(2, p->n, p->ntile);
+    const StepWs w = step_ws(p, ws);
+    if (tn->pack_schedule != 0) {
+        // loop-fission schedules: each loop's own unpack into the store, then
+        // the next loop packs from it
+        for (int loop = 0; loop < 3; ++loop) {
+            if ((s = launch_pack(p, loop, store, true, 0, 0, w.pack, tn->pack_waves, st, tn->pack_schedule)))
+                return s;
+            if ((s = launch_interact(p, loop, true, 0, p->ntask, w.pack, prm, tn, w.res, nullptr, w.q, st)))
+                return s;
+            if ((s = launch_unpack(const_cast<sph_plan *>(p), loop, w.res, true, 0, 0, store, tn->pack_waves, st,
+                                   tn->pack_schedule)))
+                return s;
+        }
+        return SPH_OK;
+    }
+    // staged: outputs stay in the step's result planes, later packs read them
+    // there, and one write-back stores them all
     for (int loop = 0; loop < 3; ++loop) {
-        if ((s = launch_pack(p, loop, store, true, 0, 0, pack, tn->pack_waves, st, tn->pack_schedule))) return s;
-        if ((s = launch_interact(p, loop, true, 0, p->ntask, pack, prm, tn, res, nullptr, q, st))) return s;
-        if ((s = launch_unpack(const_cast<sph_plan *>(p), loop, res, true, 0, 0, store, tn->pack_waves, st,
-                               tn->pack_schedule)))
+        if ((s = launch_pack_step(p, loop, store, w.res, w.pack, (float *)(w.q + kQueueBytes), prm, tn->pack_waves,
+                                  st)))
+            return s;
+        if ((s = launch_interact(p, loop, true, 0, p->ntask, w.pack, prm, tn,
+                                 w.res + (size_t)kStepPlane0[loop] * round_slots(p->n), nullptr, w.q, st, nullptr,
+                                 -1, true)))
             return s;
     }
+    return launch_writeback(p, store, w.res, tn->pack_waves, st);
+}
+
+static sph_status step_stage_checks(const sph_plan *p, const sph_store *store, const sph_tuning *tn, void *ws,
+                                    size_t ws_bytes)
+{
+    sph_status s;
+    if ((s = batched_checks(p, 0)) || (store && (s = check_store(store))) || (s = check_tuning(tn))) return s;
+    if (store && store->n != p->n) return fail(SPH_E_ARG, "store size differs from the plan's");
+    if (!ws || !aligned256(ws)) return fail(SPH_E_ARG, "workspace null or misaligned");
+    if (ws_bytes < step_ws_bytes(p))
+        return fail(SPH_E_CAPACITY, "workspace needs " + std::to_string(step_ws_bytes(p)) + " bytes");
     return SPH_OK;
 }
 
@@ -1138,18 +1185,18 @@ sph_status sph_step_kdk(const sph_plan *p, const sph_store *store, const sph_par
                         float dt, void *ws, size_t ws_bytes, int32_t *rebuild, void *stream)
 {
     sph_status s;
-    size_t step_ws = 0;
-    sph_batched_ws_bytes(p, &step_ws);
-    step_ws = (step_ws + 255) / 256 * 256;
+    size_t step_bytes = 0;
+    sph_batched_ws_bytes(p, &step_bytes);
+    step_bytes = (step_bytes + 255) / 256 * 256;
     if (!p) return fail(SPH_E_ARG, "plan is null");
-    if (ws_bytes < step_ws) return fail(SPH_E_CAPACITY, "workspace too small");
-    if ((s = integrate_checks(p, store, (char *)ws + step_ws, ws_bytes - step_ws))) return s;
+    if (ws_bytes < step_bytes) return fail(SPH_E_CAPACITY, "workspace too small");
+    if ((s = integrate_checks(p, store, (char *)ws + step_bytes, ws_bytes - step_bytes))) return s;
     if (!prm) return fail(SPH_E_ARG, "params is null");
     if (!std::isfinite(dt) || !(dt >= 0.0f)) return fail(SPH_E_ARG, "dt must be finite and non-negative");
     if (rebuild) *rebuild = 0;
     if (p->n == 0) return SPH_OK;
     const hipStream_t st = (hipStream_t)stream;
-    void *iws = (char *)ws + step_ws;
+    void *iws = (char *)ws + step_bytes;
     const float half = 0.5f * dt;
     // the first half kick and the drift in one pass over the particles
     if ((s = launch_drift(p, store, (double)dt, iws, st, true, half))) return s;
@@ -1165,7 +1212,7 @@ sph_status sph_step_kdk(const sph_plan *p, const sph_store *store, const sph_par
         return fail(SPH_E_PLAN, "particles drifted beyond the plan's reach: rebuild the plan, then run the "
                                 "loops and the second half kick");
     }
-    if ((s = step_batched(p, store, prm, tn, ws, step_ws, st))) return s;
+    if ((s = step_batched(p, store, prm, tn, ws, step_bytes, st))) return s;
     return launch_kick(store, half, st);
 }
 
@@ -1173,6 +1220,43 @@ sph_status sph_step_batched(const sph_plan *p, const sph_store *store, const sph
                             const sph_tuning *tn, void *ws, size_t ws_bytes, void *stream)
 {
     return step_batched(p, store, prm, tn, ws, ws_bytes, (hipStream_t)stream);
+}
+
+sph_status sph_step_pack(const sph_plan *p, sph_loop loop, const sph_store *store, const sph_params *prm,
+                         const sph_tuning *tn, void *ws, size_t ws_bytes, void *stream)
+{
+    sph_status s;
+    if ((s = check_loop(loop)) || (s = step_stage_checks(p, store, tn, ws, ws_bytes))) return s;
+    if (!prm) return fail(SPH_E_ARG, "params is null");
+    if (p->n == 0) return SPH_OK;
+    const StepWs w = step_ws(p, ws);
+    return launch_pack_step(p, loop, store, w.res, w.pack, (float *)(w.q + kQueueBytes), prm, tn ? tn->pack_waves : 4,
+                            (hipStream_t)stream);
+}
+
+sph_status sph_step_interact(const sph_plan *p, sph_loop loop, const sph_params *prm, const sph_tuning *tn,
+                             void *ws, size_t ws_bytes, void *stream)
+{
+    sph_status s;
+    if ((s = check_loop(loop)) || (s = step_stage_checks(p, nullptr, tn, ws, ws_bytes))) return s;
+    if (!prm) return fail(SPH_E_ARG, "params is null");
+    if (p->n == 0) return SPH_OK;
+    sph_tuning def;
+    sph_tuning_default(&def);
+    const StepWs w = step_ws(p, ws);
+    return launch_interact(p, loop, true, 0, p->ntask, w.pack, prm, tn ? tn : &def,
+                           w.res + (size_t)kStepPlane0[loop] * round_slots(p->n), nullptr, w.q, (hipStream_t)stream,
+                           nullptr, -1, true);
+}
+
+sph_status sph_step_writeback(const sph_plan *p, const sph_store *store, const sph_tuning *tn, void *ws,
+                              size_t ws_bytes, void *stream)
+{
+    sph_status s;
+    if ((s = step_stage_checks(p, store, tn, ws, ws_bytes))) return s;
+    if (!store) return fail(SPH_E_ARG, "store is null");
+    if (p->n == 0) return SPH_OK;
+    return launch_writeback(p, store, step_ws(p, ws).res, tn ? tn->pack_waves : 4, (hipStream_t)stream);
 }
 
 sph_status sph_step_batched_noalloc(const sph_plan *p, const sph_store *store, const sph_params *prm,

@@ -187,51 +187,6 @@ struct Acc {
     int32_t n;
 };
 
-// Per-particle quantities the pair terms need beyond the packed fields: for
-// the gradient loop {u, m/rho, c}; for the force loop the factors of the pair
-// term with its constants folded in (see derive_force).  The batched form
-// computes them once per particle (k_prep) into derived planes; the per-task
-// form computes them when it stages a particle.
-__device__ __forceinline__ float4 derive_gradient(const float4 &p1, const float2 &p2, float g)
-{
-    return make_float4(p2.x, p1.w / p2.y, sqrtf(g * (g - 1.0f) * p2.x), 0.f);
-}
-
-struct ForceDerived {
-    float4 q0, q1;
-};
-
-// The force pair term needs, per particle, K = H^-5 (8/pi) (the spline's
-// normalisation), A = P / (Omega rho^2) with P = (gamma - 1) rho u and the
-// grad-h factor Omega = 1 + (h/3rho) drho/dh, the sound speed c, the
-// Balsara-limited viscosity alpha~ = alpha_v |div v| / (|div v| + |curl v| +
-// eps c / h), alpha_d, rho and u.  Half the spline factor w'(q)/q K is what the
-// pair term uses (the average of i's and j's), and with t = 1 - q it is
-//   t > 1/2:  K (9 q - 6)     = kD + nkB t,   kD = 3K, nkB = -9K
-//   t <= 1/2: -3 K t^2 H / r  = kA t^2 / r,   kA = -3 K H
-// (the spline is C1 at q = 1/2, so either side may take the boundary).  The
-// pair sums take A2 = 2A against the halved factor, atq = -alpha~/4 and
-// adh = alpha_d / 2 as the halves of the pair averages, and rh = rho / 2.
-// Planes: q0 = {1/H, K, A2, c}, q1 = {atq, adh, rh, u}; kA, nkB, kD and H^2
-// follow from K and h where a particle is loaded (spline_consts).
-__device__ __forceinline__ ForceDerived derive_force(const float4 &p0, const float4 &p2, const float4 &p3, float ad,
-                                                     float g, float eps)
-{
-    const float h = p0.w, u = p2.x, rho = p2.y, rdh = p2.z, D = p2.w;
-    const float H = kGammaK * h, ih = 1.0f / H;
-    const float A = (g - 1.0f) * u / (rho + h * rdh * (1.0f / 3.0f));  // P / (Omega rho^2)
-    const float c = sqrtf(g * (g - 1.0f) * u);
-    const float irho = 1.0f / rho;
-    const float div = fabsf(D * irho);
-    const float curl = sqrtf(p3.x * p3.x + p3.y * p3.y + p3.z * p3.z) * irho;
-    const float at = p3.w * div / (div + curl + eps * c / h);
-    const float K = kC3 * ih * ih * ih * ih * ih;
-    ForceDerived f;
-    f.q0 = make_float4(ih, K, 2.0f * A, c);
-    f.q1 = make_float4(-0.25f * at, 0.5f * ad, 0.5f * rho, u);
-    return f;
-}
-
 // the spline constants of derive_force from K and h: {kA, nkB, kD, H}
 __device__ __forceinline__ float4 spline_consts(float K, float h)
 {
@@ -1050,7 +1005,7 @@ static sph_status launch_win(const InteractArgs &a, int win, unsigned grid, hipS
 
 sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, int32_t t1, const void *pack,
                            const sph_params *prm, const sph_tuning *tn, void *res, int32_t *counts, void *ws,
-                           hipStream_t st, const int32_t *items, int64_t nitems)
+                           hipStream_t st, const int32_t *items, int64_t nitems, bool prepped)
 {
     InteractArgs a{};
     a.pack = (const char *)pack;
@@ -1112,7 +1067,9 @@ sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, 
             hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, a.queue);
             SPH_CHECK_LAUNCH("queue reset launch");
         }
-        if (loop >= 1) {
+        if (loop >= 1 && prepped) {
+            a.q = (float *)((char *)ws + kQueueBytes);  // written by the step's pack
+        } else if (loop >= 1) {
             PrepArgs pa{a.pack, a.P, p->n, (float *)((char *)ws + kQueueBytes), a.gam, a.eps};
             a.q = pa.q;
             const unsigned pg = (unsigned)((p->n + 255) / 256);

@@ -200,6 +200,10 @@ inline size_t result_bytes_for(int loop, int64_t nslot)
 // derived per-particle planes of the gradient (1 float4) or force (2 float4 +
 // 1 float2) loop
 constexpr size_t kQueueBytes = 256;
+// result planes of a whole staged step (every loop's outputs, in plane
+// order): density 0..2, gradient 3..8, force 9..12
+constexpr int kStepPlanes = 13;
+constexpr int kStepPlane0[3] = {0, 3, 9};
 static_assert(kQueues * kQueueStride * sizeof(int32_t) <= kQueueBytes, "queue counters");
 constexpr int kDerivedFloats[3] = {0, 4, 8};
 inline size_t interact_ws_bytes_for(int loop, int64_t n)
@@ -207,11 +211,68 @@ inline size_t interact_ws_bytes_for(int loop, int64_t n)
     return kQueueBytes + (size_t)round_slots(n) * 4 * kDerivedFloats[loop];
 }
 
+// Per-particle quantities the pair terms need beyond the packed fields: for
+// the gradient loop {u, m/rho, c}; for the force loop the factors of the pair
+// term with its constants folded in (see derive_force).  The batched form
+// computes them once per particle into derived planes (k_prep, or the pack of
+// the staged step); the per-task form computes them when it stages a
+// particle.  Contraction is off inside, so every compile unit (the pack's is
+// built without contraction) computes the same bits.
+__device__ __forceinline__ float4 derive_gradient(const float4 &p1, const float2 &p2, float g)
+{
+#pragma clang fp contract(off)
+    return make_float4(p2.x, p1.w / p2.y, sqrtf(g * (g - 1.0f) * p2.x), 0.f);
+}
+
+struct ForceDerived {
+    float4 q0, q1;
+};
+
+// The force pair term needs, per particle, K = H^-5 (8/pi) (the spline's
+// normalisation), A = P / (Omega rho^2) with P = (gamma - 1) rho u and the
+// grad-h factor Omega = 1 + (h/3rho) drho/dh, the sound speed c, the
+// Balsara-limited viscosity alpha~ = alpha_v |div v| / (|div v| + |curl v| +
+// eps c / h), alpha_d, rho and u.  Half the spline factor w'(q)/q K is what the
+// pair term uses (the average of i's and j's), and with t = 1 - q it is
+//   t > 1/2:  K (9 q - 6)     = kD + nkB t,   kD = 3K, nkB = -9K
+//   t <= 1/2: -3 K t^2 H / r  = kA t^2 / r,   kA = -3 K H
+// (the spline is C1 at q = 1/2, so either side may take the boundary).  The
+// pair sums take A2 = 2A against the halved factor, atq = -alpha~/4 and
+// adh = alpha_d / 2 as the halves of the pair averages, and rh = rho / 2.
+// Planes: q0 = {1/H, K, A2, c}, q1 = {atq, adh, rh, u}; kA, nkB, kD and H^2
+// follow from K and h where a particle is loaded (spline_consts).
+__device__ __forceinline__ ForceDerived derive_force(const float4 &p0, const float4 &p2, const float4 &p3, float ad,
+                                                     float g, float eps)
+{
+#pragma clang fp contract(off)
+    const float h = p0.w, u = p2.x, rho = p2.y, rdh = p2.z, D = p2.w;
+    const float H = kGammaK * h, ih = 1.0f / H;
+    const float A = (g - 1.0f) * u / (rho + h * rdh * (1.0f / 3.0f));  // P / (Omega rho^2)
+    const float c = sqrtf(g * (g - 1.0f) * u);
+    const float irho = 1.0f / rho;
+    const float div = fabsf(D * irho);
+    const float curl = sqrtf(p3.x * p3.x + p3.y * p3.y + p3.z * p3.z) * irho;
+    const float at = p3.w * div / (div + curl + eps * c / h);
+    const float K = kC3 * ih * ih * ih * ih * ih;
+    ForceDerived f;
+    f.q0 = make_float4(ih, K, 2.0f * A, c);
+    f.q1 = make_float4(-0.25f * at, 0.5f * ad, 0.5f * rho, u);
+    return f;
+}
+
 // ---------------------------------------------------------------------------
 // launchers implemented in the .hip files
 // ---------------------------------------------------------------------------
 // schedule: the loop fission of sph_tuning.pack_schedule (batched form only;
 // per-task ranges always use the fused kernels)
+// pack of loop `loop` inside a staged step: the earlier loops' outputs are
+// taken from the step's result planes (res, P floats each) instead of the
+// store, and (gradient, force) the derived planes are written to `derived`
+sph_status launch_pack_step(const sph_plan *p, int loop, const sph_store *s, const float *res, void *buf,
+                            float *derived, const sph_params *prm, int waves, hipStream_t st);
+// every output of a staged step from its result planes into the store, each
+// output substruct record written whole
+sph_status launch_writeback(const sph_plan *p, const sph_store *s, const float *res, int waves, hipStream_t st);
 sph_status launch_pack(const sph_plan *p, int loop, const sph_store *s, bool cells, int32_t t0, int32_t t1,
                        void *buf, int waves, hipStream_t st, int schedule = 0);
 sph_status launch_unpack(sph_plan *p, int loop, const void *res, bool cells, int32_t t0, int32_t t1,
@@ -252,6 +313,6 @@ sph_status launch_unpack_tiles(const sph_plan *p, int loop, const void *res, int
 sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, int32_t t1,
                            const void *pack, const sph_params *prm, const sph_tuning *tn, void *res,
                            int32_t *counts, void *ws, hipStream_t st, const int32_t *items = nullptr,
-                           int64_t nitems = -1);
+                           int64_t nitems = -1, bool prepped = false);
 
 }  // namespace sph

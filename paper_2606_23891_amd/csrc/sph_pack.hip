@@ -80,6 +80,10 @@ struct PackArgs {
     int64_t P;      // slots per plane
     char *buf;
     float4 *bounds; // 2 per chunk
+    // staged step (batched form): earlier loops' outputs and the derived planes
+    const float *step_res;  // kStepPlanes planes of P floats
+    float *derived;         // gradient: 1 float4 plane; force: 2 float4 planes
+    float gam, eps;
 };
 
 // fields each loop's pack reads (paper Table 1)
@@ -184,7 +188,19 @@ __device__ __forceinline__ void load_sub(const StoreArg &st, int64_t p, PackVals
     }
 }
 
-template <int L, int LOOP>
+// the value an output holds once unpacked from a per-particle result: +0 + r,
+// the signal velocity the larger of +0 and r (the batched unpack's reduction)
+__device__ __forceinline__ float settle(float r, bool vmax)
+{
+    return vmax ? ((r > 0.0f) ? r : 0.0f) : 0.0f + r;
+}
+
+// STEP: the pack of a staged step (batched form only): the fields earlier
+// loops of the step produce are taken, settled, from the step's result planes
+// rather than from the store (which receives them at the step's end), and the
+// derived planes of the gradient / force pair terms are written beside the
+// packed record
+template <int L, int LOOP, bool STEP = false>
 __global__ __launch_bounds__(512) void k_pack(PackArgs a)
 {
     const int lane = threadIdx.x & 63;
@@ -208,6 +224,17 @@ __global__ __launch_bounds__(512) void k_pack(PackArgs a)
     if (valid) {
         PackVals v;
         static_for<0, kLayouts[L].nsub>([&](auto sc) { load_sub<L, LOOP, decltype(sc)::value>(a.store, p, v); });
+        if constexpr (STEP && LOOP >= 1) {
+            const float *r = a.step_res;
+            v.rho = settle(r[p], false);
+            if constexpr (LOOP == 2) {
+                v.rdh = settle(r[P + p], false);
+                v.div = settle(r[3 * P + p], false);
+                v.rot[0] = settle(r[4 * P + p], false);
+                v.rot[1] = settle(r[5 * P + p], false);
+                v.rot[2] = settle(r[6 * P + p], false);
+            }
+        }
         dx = (float)(v.x[0] - o0);
         dy = (float)(v.x[1] - o1);
         dz = (float)(v.x[2] - o2);
@@ -231,6 +258,16 @@ __global__ __launch_bounds__(512) void k_pack(PackArgs a)
                 float *pl4 = (float *)(a.buf + P * 64);
                 pl4[slot] = v.ad;
             }
+        }
+        if constexpr (STEP && LOOP == 1) {
+            ((float4 *)a.derived)[slot] = derive_gradient(make_float4(v.v[0], v.v[1], v.v[2], v.m),
+                                                          make_float2(v.u, v.rho), a.gam);
+        } else if constexpr (STEP && LOOP == 2) {
+            const ForceDerived f = derive_force(make_float4(dx, dy, dz, hh), make_float4(v.u, v.rho, v.rdh, v.div),
+                                                make_float4(v.rot[0], v.rot[1], v.rot[2], v.av), v.ad, a.gam,
+                                                a.eps);
+            ((float4 *)a.derived)[slot] = f.q0;
+            ((float4 *)(a.derived + 4 * P))[slot] = f.q1;
         }
     }
     // chunk bounds by DPP reductions (VALU, no LDS round trips)
@@ -418,6 +455,114 @@ __global__ __launch_bounds__(256) void k_unpack_csr(UnpackArgs a)
             cur = reduce_one<LOOP, k>(cur, a.res[k * a.P + (a.csr[q] - a.slot_lo)]);
         st<L, F, C, float>(a.store, p, cur);
     });
+}
+
+// ---------------------------------------------------------------------------
+// staged step: one write-back of every output at the end of the step
+// ---------------------------------------------------------------------------
+// the output of each step result plane
+constexpr int kStepOutF[kStepPlanes] = {FRHO, FRHODH, FWCOUNT, FDIV, FROT, FROT, FROT, FLAP, FVSIG, FA, FA, FA, FUDT};
+constexpr int kStepOutC[kStepPlanes] = {0, 0, 0, 0, 0, 1, 2, 0, 0, 0, 1, 2, 0};
+constexpr int kStepVsig = 8;
+
+// does byte b of substruct S of layout L hold an output?
+constexpr bool out_byte(int L, int S, int b)
+{
+    for (int q = 0; q < kStepPlanes; ++q) {
+        const int f = kStepOutF[q], c = kStepOutC[q];
+        if (kLayouts[L].sub[f][c] == S && b >= kLayouts[L].off[f][c] && b < kLayouts[L].off[f][c] + 4) return true;
+    }
+    return false;
+}
+constexpr int out_bytes_in(int L, int S, int lo, int len)
+{
+    int k = 0;
+    for (int b = lo; b < lo + len; ++b) k += out_byte(L, S, b) ? 1 : 0;
+    return k;
+}
+
+// One wave per tile, one lane per particle.  Each substruct that holds an
+// output is written in whole records when the record is at most 64 bytes
+// (so consecutive lanes cover whole 32-byte sectors), otherwise in the
+// aligned chunks that hold outputs; a chunk that also holds other members or
+// padding is read first and merged, so those bytes keep their bits.
+template <int L>
+__global__ __launch_bounds__(512) void k_writeback(UnpackArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t c = __builtin_amdgcn_readfirstlane((int)((int64_t)blockIdx.x * (blockDim.x >> 6) +
+                                                           (threadIdx.x >> 6)));
+    if (c >= a.nchunk) return;
+    const Chunk ch = a.chunks[c];
+    if (lane >= ch.n) return;
+    const int64_t p = ch.part0 + lane;
+    static_for<0, kLayouts[L].nsub>([&](auto sc) {
+        constexpr int S = decltype(sc)::value;
+        constexpr int R = kLayouts[L].sub_bytes[S];
+        if constexpr (out_bytes_in(L, S, 0, R) > 0) {
+            constexpr int G = load_width(R, 0);
+            constexpr bool whole = R <= 64;
+            char *base = (char *)__builtin_assume_aligned(a.store.sub[S], 256) + p * R;
+            uint32_t w[R / 4];
+            static_for<0, R / G>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                constexpr int no = out_bytes_in(L, S, k * G, G);
+                if constexpr ((whole || no > 0) && no < G) {
+                    if constexpr (G == 16) {
+                        const uint4 q = *(const uint4 *)(base + 16 * k);
+                        w[4 * k] = q.x;
+                        w[4 * k + 1] = q.y;
+                        w[4 * k + 2] = q.z;
+                        w[4 * k + 3] = q.w;
+                    } else if constexpr (G == 8) {
+                        const uint2 q = *(const uint2 *)(base + 8 * k);
+                        w[2 * k] = q.x;
+                        w[2 * k + 1] = q.y;
+                    } else {
+                        w[k] = *(const uint32_t *)(base + 4 * k);
+                    }
+                }
+            });
+            static_for<0, kStepPlanes>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                constexpr int F = kStepOutF[q], C = kStepOutC[q];
+                if constexpr (kLayouts[L].sub[F][C] == S)
+                    w[kLayouts[L].off[F][C] / 4] = __float_as_uint(settle(a.res[q * a.P + p], q == kStepVsig));
+            });
+            static_for<0, R / G>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                if constexpr (whole || out_bytes_in(L, S, k * G, G) > 0) {
+                    if constexpr (G == 16)
+                        *(uint4 *)(base + 16 * k) = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+                    else if constexpr (G == 8)
+                        *(uint2 *)(base + 8 * k) = make_uint2(w[2 * k], w[2 * k + 1]);
+                    else
+                        *(uint32_t *)(base + 4 * k) = w[k];
+                }
+            });
+        }
+    });
+}
+
+template <int L>
+static sph_status writeback_l(const UnpackArgs &a, int waves, hipStream_t st)
+{
+    const unsigned grid = (unsigned)((a.nchunk + waves - 1) / waves);
+    hipLaunchKernelGGL((k_writeback<L>), dim3(grid), dim3(64 * waves), 0, st, a);
+    SPH_CHECK_LAUNCH("write-back launch");
+    return SPH_OK;
+}
+
+template <int L>
+static sph_status pack_step_l(int loop, const PackArgs &a, int waves, hipStream_t st)
+{
+    const unsigned grid = (unsigned)((a.nchunk + waves - 1) / waves);
+    const dim3 blk(64 * waves);
+    if (loop == 0) hipLaunchKernelGGL((k_pack<L, 0, true>), dim3(grid), blk, 0, st, a);
+    else if (loop == 1) hipLaunchKernelGGL((k_pack<L, 1, true>), dim3(grid), blk, 0, st, a);
+    else hipLaunchKernelGGL((k_pack<L, 2, true>), dim3(grid), blk, 0, st, a);
+    SPH_CHECK_LAUNCH("step pack launch");
+    return SPH_OK;
 }
 
 // the fission groups of a layout's pack (unpack) members under a schedule
@@ -1041,6 +1186,41 @@ sph_status launch_pack(const sph_plan *p, int loop, const sph_store *s, bool cel
     a.bounds = (float4 *)(a.buf + a.P * 4 * kPackFloats[loop]);
     if (a.nchunk == 0) return SPH_OK;
     SPH_BY_LAYOUT(s->layout, pack_l, p, loop, a, waves, schedule, st);
+}
+
+sph_status launch_pack_step(const sph_plan *p, int loop, const sph_store *s, const float *res, void *buf,
+                            float *derived, const sph_params *prm, int waves, hipStream_t st)
+{
+    PackArgs a{};
+    a.store = store_arg(s);
+    a.cells = p->d_cells;
+    a.tasks = p->d_tasks;
+    a.buf = (char *)buf;
+    a.chunks = p->d_tiles;
+    a.chunk_base = 0;
+    a.nchunk = p->ntile;
+    a.slot_base = 0;
+    a.P = round_slots(p->n);
+    a.bounds = (float4 *)(a.buf + a.P * 4 * kPackFloats[loop]);
+    a.step_res = res;
+    a.derived = derived;
+    a.gam = prm->gamma_ad;
+    a.eps = prm->balsara_eps;
+    if (a.nchunk == 0) return SPH_OK;
+    SPH_BY_LAYOUT(s->layout, pack_step_l, loop, a, waves, st);
+}
+
+sph_status launch_writeback(const sph_plan *p, const sph_store *s, const float *res, int waves, hipStream_t st)
+{
+    UnpackArgs a{};
+    a.store = store_arg(s);
+    a.chunks = p->d_tiles;
+    a.nchunk = p->ntile;
+    a.P = round_slots(p->n);
+    a.res = res;
+    a.n = p->n;
+    if (a.nchunk == 0) return SPH_OK;
+    SPH_BY_LAYOUT(s->layout, writeback_l, a, waves, st);
 }
 
 sph_status launch_pack_tiles(const sph_plan *p, int loop, const sph_store *s, int32_t tile0, int32_t tile1,

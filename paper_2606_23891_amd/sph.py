@@ -93,6 +93,9 @@ _SIGS = {
     "sph_unpack_cells": ([vp, i32, vp, sz, vp, vp, vp], i32),
     "sph_step_batched": ([vp, vp, vp, vp, vp, sz, vp], i32),
     "sph_step_batched_noalloc": ([vp, vp, vp, vp, vp], i32),
+    "sph_step_pack": ([vp, i32, vp, vp, vp, vp, sz, vp], i32),
+    "sph_step_interact": ([vp, i32, vp, vp, vp, sz, vp], i32),
+    "sph_step_writeback": ([vp, vp, vp, vp, sz, vp], i32),
     "sph_integrate_ws_bytes": ([vp, C.POINTER(sz)], i32),
     "sph_kick": ([vp, C.c_float, vp], i32),
     "sph_drift": ([vp, vp, C.c_double, vp, sz, C.POINTER(C.c_double), C.POINTER(C.c_float), vp], i32),
@@ -506,6 +509,23 @@ def sph_step_batched(plan, store, ws, params=None, tuning=None, stream=None):
     p = params if params is not None else default_params()
     _check(lib().sph_step_batched(_h(plan), _s(store), C.byref(p), C.byref(tuning) if tuning else None,
                                   _ptr(ws), _nbytes(ws), _stream(stream)), "sph_step_batched")
+
+
+def sph_step_pack(plan, loop, store, ws, params=None, tuning=None, stream=None):
+    p = params if params is not None else default_params()
+    _check(lib().sph_step_pack(_h(plan), loop, _s(store), C.byref(p), C.byref(tuning) if tuning else None,
+                               _ptr(ws), _nbytes(ws), _stream(stream)), "sph_step_pack")
+
+
+def sph_step_interact(plan, loop, ws, params=None, tuning=None, stream=None):
+    p = params if params is not None else default_params()
+    _check(lib().sph_step_interact(_h(plan), loop, C.byref(p), C.byref(tuning) if tuning else None,
+                                   _ptr(ws), _nbytes(ws), _stream(stream)), "sph_step_interact")
+
+
+def sph_step_writeback(plan, store, ws, tuning=None, stream=None):
+    _check(lib().sph_step_writeback(_h(plan), _s(store), C.byref(tuning) if tuning else None, _ptr(ws),
+                                    _nbytes(ws), _stream(stream)), "sph_step_writeback")
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20   # SPH_NOALLOC_SCRATCH_BYTES of sph.h

@@ -282,3 +282,42 @@ def test_offload_forms_against_oracle(layout):
             if k not in written:
                 assert hv.get(k).tobytes() == np.ascontiguousarray(f[k]).astype(hv.get(k).dtype).tobytes(), (form, k)
     plan.close()
+
+
+@pytest.mark.parametrize("layout", range(10))
+def test_staged_step_matches_per_loop_unpack(layout):
+    """the staged step (earlier loops' outputs read from the step's result
+    planes, one write-back at the end) leaves the store byte for byte as the
+    per-loop pack -> interact -> unpack sequence, both as one call and as its
+    seven stage calls; on a 32^3 Gresho lattice with random values in the
+    fields no loop touches (padding included)"""
+    import torch
+    ps = inputs.make_config(1, n_side=32)
+    f = dict(ps.fields)
+    extra = inputs.random_fields(ps.n, 27, x=f["x"])
+    for k in ("time_bin", "id", "cold", "a", "u_dt", "lap_u", "v_sig", "wcount"):
+        f[k] = extra[k]
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    ref = sph.Store(layout, ps.n)
+    for t in ref.subs:
+        t.fill_(0x3C)
+    ref.put_all(f)
+    for L in range(3):
+        run_batched_loop(plan, ref, L)
+    ws = torch.zeros(sph.sph_batched_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    one = sph.Store(layout, ps.n)
+    staged = sph.Store(layout, ps.n)
+    for st in (one, staged):
+        for t in st.subs:
+            t.fill_(0x3C)
+        st.put_all(f)
+    log(f"staged step {sph.LAYOUTS[layout]}")
+    sph.sph_step_batched(plan, one, ws)
+    for L in range(3):
+        sph.sph_step_pack(plan, L, staged, ws)
+        sph.sph_step_interact(plan, L, ws)
+    sph.sph_step_writeback(plan, staged, ws)
+    torch.cuda.synchronize()
+    assert one.raw() == ref.raw()
+    assert staged.raw() == ref.raw()
+    plan.close()

@@ -80,8 +80,8 @@ def test_tuning_cache_keys_and_apply(tmp_path, monkeypatch):
 
 
 def test_bench_stage_kernel_names():
-    """the kernels the benchmark attributes to each stage (its roofline and
-    traffic lookups use these names), fused and under a fission schedule"""
+    """the kernels the benchmark attributes to each stage of the staged step
+    (its roofline and traffic lookups use these names)"""
     import importlib.util
     import sys
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -90,14 +90,14 @@ def test_bench_stage_kernel_names():
     sys.modules["bench_mod"] = bench
     spec.loader.exec_module(bench)
     t = types.SimpleNamespace(window=[256, 128, 128], pack_schedule=0)
-    assert bench.stage_kernels("pack_force", 4, t) == ["void sph::k_pack<4, 2>(sph::PackArgs)"]
-    assert bench.stage_kernels("unpack_density", 4, t) == [
-        "void sph::k_unpack_chunks<4, 0, true, false>(sph::UnpackArgs)"]
-    assert bench.stage_kernels("force", 4, t) == ["void sph::k_prep<2>(sph::PrepArgs)",
-                                                  "void sph::k_interact<2, 1, 128, false>(sph::InteractArgs)"]
+    assert bench.STAGES == ["pack_density", "density", "pack_gradient", "gradient", "pack_force", "force",
+                            "writeback"]
+    assert bench.stage_kernels("pack_force", 4, t) == ["void sph::k_pack<4, 2, true>(sph::PackArgs)"]
+    assert bench.stage_kernels("writeback", 4, t) == ["void sph::k_writeback<4>(sph::UnpackArgs)"]
+    assert bench.stage_kernels("force", 4, t) == ["void sph::k_interact<2, 1, 128, false>(sph::InteractArgs)"]
     assert bench.stage_kernels("density", 8, t) == ["void sph::k_interact<0, 1, 256, false>(sph::InteractArgs)"]
-    t.pack_schedule = 2
-    assert bench.stage_kernels("pack_gradient", 8, t) == [
-        "void sph::k_pack_pass<8, 1>(sph::PackArgs, unsigned int)"]
-    assert bench.stage_kernels("unpack_force", 8, t) == [
-        "void sph::k_unpack_chunks<8, 2, true, true>(sph::UnpackArgs)"]
+    # algorithmic bytes per particle: the staged packs read earlier outputs
+    # from the result planes and write the derived planes
+    assert bench.stage_bytes("pack_force", 1) == 56 + 24 + 68 + 0.5 + 32
+    assert bench.stage_bytes("force", 1) == 68 + 32 + 0.5 + 16
+    assert bench.stage_bytes("writeback", 1) == 104
