@@ -41,10 +41,12 @@ PACK_BYTES = {0: 32 + 20 + 0.5, 1: 52 + 40 + 0.5, 2: 80 + 68 + 0.5}
 UNPACK_BYTES = {0: 12 + 12, 1: 24 + 24, 2: 16 + 16}
 # staged step: the gradient / force packs read the fields earlier loops of the
 # step produce from its result planes (4 / 24 bytes) instead of the store, and
-# write the derived planes of the pair term (16 / 32 bytes); one write-back
-# reads every result (52 bytes) and writes every output (52 bytes)
+# write the derived planes of the pair term (16 / 32 bytes); each of the 13
+# outputs is stored once, 4 bytes, by the stage the library names for the
+# store's layout (a pack that loads the output's record whole, else the
+# write-back, which also reads the output's result, 4 bytes)
 STEP_PACK_BYTES = {0: 32 + 20 + 0.5, 1: 48 + 4 + 40 + 0.5 + 16, 2: 56 + 24 + 68 + 0.5 + 32}
-WRITEBACK_BYTES = 52 + 52
+OUTPUT_BYTES = 4
 # interaction kernel: its packed records and derived planes read once + its
 # result planes written
 INTERACT_BYTES = {0: 20 + 0.5 + 12, 1: 40 + 16 + 0.5 + 24, 2: 68 + 32 + 0.5 + 16}
@@ -114,13 +116,15 @@ def stage_kernels(stage, layout, tuning):
     raise KeyError(stage)
 
 
-def stage_bytes(stage, n):
-    """algorithmic HBM bytes of one launch of a stage of the staged step"""
+def stage_bytes(stage, n, writers):
+    """algorithmic HBM bytes of one launch of a stage of the staged step;
+    writers: the stage storing each output (1, 2: that loop's pack; 3: the
+    write-back), from the library for the store's layout"""
     if stage == "writeback":
-        return WRITEBACK_BYTES * n
+        return 2 * OUTPUT_BYTES * sum(1 for w in writers if w == 3) * n
     for L, nm in LOOP_NAME.items():
         if stage == f"pack_{nm}":
-            return STEP_PACK_BYTES[L] * n
+            return (STEP_PACK_BYTES[L] + OUTPUT_BYTES * sum(1 for w in writers if w == L)) * n
         if stage == nm:
             return INTERACT_BYTES[L] * n
     raise KeyError(stage)
@@ -239,6 +243,7 @@ def main():
 
     stages = {}
     n = ps.n
+    writers = sph.sph_step_output_writers(layout)
     for i, nm in enumerate(STAGES):
         ms = float(stage_ms[i])
         if nm in LOOP_NAME.values():
@@ -247,11 +252,11 @@ def main():
                           "TFLOP/s": PAIR_FLOPS[L] * pairs[L] / (ms * 1e-3) / 1e12,
                           "TFLOP/s_formula_count": PAIR_FLOPS_FORMULA[L] * pairs[L] / (ms * 1e-3) / 1e12,
                           "pairs/s": pairs[L] / (ms * 1e-3),
-                          "GB/s": stage_bytes(nm, n) / (ms * 1e-3) / 1e9}
+                          "GB/s": stage_bytes(nm, n, writers) / (ms * 1e-3) / 1e9}
         else:
-            stages[nm] = {"ms": ms, "GB/s": stage_bytes(nm, n) / (ms * 1e-3) / 1e9}
+            stages[nm] = {"ms": ms, "GB/s": stage_bytes(nm, n, writers) / (ms * 1e-3) / 1e9}
     pu = [k for k in STAGES if k.startswith("pack_") or k == "writeback"]
-    pu_bytes = sum(stage_bytes(k, n) for k in pu)
+    pu_bytes = sum(stage_bytes(k, n, writers) for k in pu)
     pu_ms = sum(stages[k]["ms"] for k in pu)
     pack_unpack_gbs = pu_bytes / (pu_ms * 1e-3) / 1e9
 
@@ -280,7 +285,7 @@ def main():
     roof["traffic"] = (sum(tr["kernels"][k]["bytes"] for k in knames)
                        if tr and all(k in tr["kernels"] for k in knames) else None)
     roof["traffic_unit"] = "bytes per launch of the stage's kernels"
-    roof["algorithmic_bytes"] = stage_bytes(dom, n)
+    roof["algorithmic_bytes"] = stage_bytes(dom, n, writers)
 
     out = {
         "metric": METRIC, "value": value, "unit": "pair interactions/s", "n_gpus": 1, "steps": a.steps,

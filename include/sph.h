@@ -354,7 +354,12 @@ sph_status sph_step_batched(const sph_plan *plan, const sph_store *store, const 
 /* The stages of sph_step_batched, one call each (same ws; the step's result
  * planes and pack buffer live in it): sph_step_pack for density, gradient,
  * force in turn, each followed by sph_step_interact of the same loop, then
- * sph_step_writeback.  Results between the calls exist only in ws. */
+ * sph_step_writeback.  Results between the calls live in ws; a gradient or
+ * force pack that loads a substruct record whole and finds outputs of earlier
+ * loops in it writes the record back with them (SAOS_SHARED: rho with
+ * {v u rho}, rho_dh, D, R with the force-only substruct; SoA: their arrays),
+ * and the write-back stores the rest, so the store is complete only after
+ * sph_step_writeback. */
 sph_status sph_step_pack(const sph_plan *plan, sph_loop loop, const sph_store *store,
                          const sph_params *params, const sph_tuning *tuning, void *ws, size_t ws_bytes,
                          void *stream);
@@ -362,6 +367,10 @@ sph_status sph_step_interact(const sph_plan *plan, sph_loop loop, const sph_para
                              const sph_tuning *tuning, void *ws, size_t ws_bytes, void *stream);
 sph_status sph_step_writeback(const sph_plan *plan, const sph_store *store, const sph_tuning *tuning,
                               void *ws, size_t ws_bytes, void *stream);
+/* Which stage of the staged step stores each output into a store of this
+ * layout: writer[13] in the order rho, rho_dh, wcount, D, R[3], lap_u, v_sig,
+ * a[3], u_dt; 1 or 2 = the gradient or force pack, 3 = the write-back. */
+sph_status sph_step_output_writers(sph_layout layout, int32_t *writer);
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the step of
  * sph_step_batched with its workspace taken from a static per-device scratch

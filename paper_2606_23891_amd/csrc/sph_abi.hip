@@ -1249,6 +1249,13 @@ sph_status sph_step_interact(const sph_plan *p, sph_loop loop, const sph_params 
                            nullptr, -1, true);
 }
 
+sph_status sph_step_output_writers(sph_layout layout, int32_t *writer)
+{
+    if ((int)layout < 0 || (int)layout >= kNLayouts) return fail(SPH_E_LAYOUT, "unknown layout");
+    if (!writer) return fail(SPH_E_ARG, "null output");
+    return step_writers((int)layout, writer);
+}
+
 sph_status sph_step_writeback(const sph_plan *p, const sph_store *store, const sph_tuning *tn, void *ws,
                               size_t ws_bytes, void *stream)
 {

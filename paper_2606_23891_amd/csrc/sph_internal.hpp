@@ -273,6 +273,9 @@ sph_status launch_pack_step(const sph_plan *p, int loop, const sph_store *s, con
 // every output of a staged step from its result planes into the store, each
 // output substruct record written whole
 sph_status launch_writeback(const sph_plan *p, const sph_store *s, const float *res, int waves, hipStream_t st);
+// the stage of the staged step that stores each output (1 or 2: that loop's
+// pack, 3: the write-back), in step result plane order
+sph_status step_writers(int layout, int32_t *writer);
 sph_status launch_pack(const sph_plan *p, int loop, const sph_store *s, bool cells, int32_t t0, int32_t t1,
                        void *buf, int waves, hipStream_t st, int schedule = 0);
 sph_status launch_unpack(sph_plan *p, int loop, const void *res, bool cells, int32_t t0, int32_t t1,

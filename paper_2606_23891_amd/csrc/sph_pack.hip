@@ -120,6 +120,49 @@ constexpr int load_width(int record, int lo)
     return (record % 16 == 0 && lo % 16 == 0) ? 16 : (record % 8 == 0 && lo % 8 == 0) ? 8 : 4;
 }
 
+// ---------------------------------------------------------------------------
+// outputs of a staged step (see the write-back below)
+// ---------------------------------------------------------------------------
+// the output of each step result plane, and the loop producing it
+constexpr int kStepOutF[kStepPlanes] = {FRHO, FRHODH, FWCOUNT, FDIV, FROT, FROT, FROT, FLAP, FVSIG, FA, FA, FA, FUDT};
+constexpr int kStepOutC[kStepPlanes] = {0, 0, 0, 0, 0, 1, 2, 0, 0, 0, 1, 2, 0};
+constexpr int kStepOutLoop[kStepPlanes] = {0, 0, 0, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2};
+constexpr int kStepVsig = 8;
+
+// the value an output holds once unpacked from a per-particle result: +0 + r,
+// the signal velocity the larger of +0 and r (the batched unpack's reduction)
+__device__ __forceinline__ float settle(float r, bool vmax)
+{
+    return vmax ? ((r > 0.0f) ? r : 0.0f) : 0.0f + r;
+}
+
+// does loop LOOP's pack load the whole record of substruct S (its span, widened
+// to the load width, covers the record)?
+constexpr bool full_load(int L, int LOOP, int S)
+{
+    const int lo = span_lo(L, LOOP, S), hi = span_hi(L, LOOP, S);
+    if (lo != 0 || hi <= 0) return false;
+    const int R = kLayouts[L].sub_bytes[S];
+    const int G = load_width(R, 0);
+    return (hi + G - 1) / G * G == R;
+}
+// who stores step output q into the store: the first later pack that loads
+// its substruct whole (it writes the record back with the outputs it holds),
+// else the write-back at the end of the step (3)
+constexpr int step_writer(int L, int q)
+{
+    const int S = kLayouts[L].sub[kStepOutF[q]][kStepOutC[q]];
+    for (int lp = kStepOutLoop[q] + 1; lp <= 2; ++lp)
+        if (full_load(L, lp, S)) return lp;
+    return 3;
+}
+constexpr bool pack_writes_sub(int L, int LOOP, int S)
+{
+    for (int q = 0; q < kStepPlanes; ++q)
+        if (step_writer(L, q) == LOOP && kLayouts[L].sub[kStepOutF[q]][kStepOutC[q]] == S) return true;
+    return false;
+}
+
 // the values a pack reads, by field
 struct PackVals {
     double x[3];
@@ -150,8 +193,13 @@ struct PackVals {
 // field the loop reads out of the loaded words: one pass over each record
 // instead of one narrow load per field (the bytes are the same, the requests
 // a fraction)
-template <int L, int LOOP, int S>
-__device__ __forceinline__ void load_sub(const StoreArg &st, int64_t p, PackVals &v)
+// STEP (staged step): a substruct this pack loads whole and that holds
+// outputs of earlier loops of the step gets those outputs, settled from the
+// step's result planes (P floats each), written into the loaded record, which
+// is stored back whole; the fields are then taken from the patched record.
+template <int L, int LOOP, int S, bool STEP = false>
+__device__ __forceinline__ void load_sub(const StoreArg &st, int64_t p, PackVals &v, const float *res = nullptr,
+                                         int64_t P = 0)
 {
     constexpr int lo = span_lo(L, LOOP, S), hi = span_hi(L, LOOP, S);
     if constexpr (lo < hi) {
@@ -176,6 +224,24 @@ __device__ __forceinline__ void load_sub(const StoreArg &st, int64_t p, PackVals
                 w[k] = *(const uint32_t *)(base + 4 * k);
             }
         });
+        if constexpr (STEP && pack_writes_sub(L, LOOP, S)) {
+            static_for<0, kStepPlanes>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                constexpr int F = kStepOutF[q], C = kStepOutC[q];
+                if constexpr (kStepOutLoop[q] < LOOP && kLayouts[L].sub[F][C] == S)
+                    w[kLayouts[L].off[F][C] / 4] = __float_as_uint(settle(res[q * P + p], q == kStepVsig));
+            });
+            char *wb = (char *)__builtin_assume_aligned(st.sub[S], 256) + p * R;
+            static_for<0, NB / G>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                if constexpr (G == 16)
+                    *(uint4 *)(wb + 16 * k) = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+                else if constexpr (G == 8)
+                    *(uint2 *)(wb + 8 * k) = make_uint2(w[2 * k], w[2 * k + 1]);
+                else
+                    *(uint32_t *)(wb + 4 * k) = w[k];
+            });
+        }
         static_for<0, NFIELD>([&](auto fc) {
             constexpr int F = decltype(fc)::value;
             if constexpr (kPackReads[LOOP][F]) {
@@ -186,13 +252,6 @@ __device__ __forceinline__ void load_sub(const StoreArg &st, int64_t p, PackVals
             }
         });
     }
-}
-
-// the value an output holds once unpacked from a per-particle result: +0 + r,
-// the signal velocity the larger of +0 and r (the batched unpack's reduction)
-__device__ __forceinline__ float settle(float r, bool vmax)
-{
-    return vmax ? ((r > 0.0f) ? r : 0.0f) : 0.0f + r;
 }
 
 // STEP: the pack of a staged step (batched form only): the fields earlier
@@ -223,7 +282,9 @@ __global__ __launch_bounds__(512) void k_pack(PackArgs a)
     float dx = 0.f, dy = 0.f, dz = 0.f, hh = 0.f;
     if (valid) {
         PackVals v;
-        static_for<0, kLayouts[L].nsub>([&](auto sc) { load_sub<L, LOOP, decltype(sc)::value>(a.store, p, v); });
+        static_for<0, kLayouts[L].nsub>([&](auto sc) {
+            load_sub<L, LOOP, decltype(sc)::value, STEP>(a.store, p, v, a.step_res, P);
+        });
         if constexpr (STEP && LOOP >= 1) {
             const float *r = a.step_res;
             v.rho = settle(r[p], false);
@@ -460,17 +521,15 @@ __global__ __launch_bounds__(256) void k_unpack_csr(UnpackArgs a)
 // ---------------------------------------------------------------------------
 // staged step: one write-back of every output at the end of the step
 // ---------------------------------------------------------------------------
-// the output of each step result plane
-constexpr int kStepOutF[kStepPlanes] = {FRHO, FRHODH, FWCOUNT, FDIV, FROT, FROT, FROT, FLAP, FVSIG, FA, FA, FA, FUDT};
-constexpr int kStepOutC[kStepPlanes] = {0, 0, 0, 0, 0, 1, 2, 0, 0, 0, 1, 2, 0};
-constexpr int kStepVsig = 8;
-
-// does byte b of substruct S of layout L hold an output?
+// does byte b of substruct S of layout L hold an output the write-back
+// stores (one that no pack of the step has written already)?
 constexpr bool out_byte(int L, int S, int b)
 {
     for (int q = 0; q < kStepPlanes; ++q) {
         const int f = kStepOutF[q], c = kStepOutC[q];
-        if (kLayouts[L].sub[f][c] == S && b >= kLayouts[L].off[f][c] && b < kLayouts[L].off[f][c] + 4) return true;
+        if (step_writer(L, q) == 3 && kLayouts[L].sub[f][c] == S && b >= kLayouts[L].off[f][c] &&
+            b < kLayouts[L].off[f][c] + 4)
+            return true;
     }
     return false;
 }
@@ -526,7 +585,7 @@ __global__ __launch_bounds__(512) void k_writeback(UnpackArgs a)
             static_for<0, kStepPlanes>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
                 constexpr int F = kStepOutF[q], C = kStepOutC[q];
-                if constexpr (kLayouts[L].sub[F][C] == S)
+                if constexpr (step_writer(L, q) == 3 && kLayouts[L].sub[F][C] == S)
                     w[kLayouts[L].off[F][C] / 4] = __float_as_uint(settle(a.res[q * a.P + p], q == kStepVsig));
             });
             static_for<0, R / G>([&](auto kc) {
@@ -1186,6 +1245,30 @@ sph_status launch_pack(const sph_plan *p, int loop, const sph_store *s, bool cel
     a.bounds = (float4 *)(a.buf + a.P * 4 * kPackFloats[loop]);
     if (a.nchunk == 0) return SPH_OK;
     SPH_BY_LAYOUT(s->layout, pack_l, p, loop, a, waves, schedule, st);
+}
+
+template <int L>
+static void writers_l(int32_t *w)
+{
+    for (int q = 0; q < kStepPlanes; ++q) w[q] = step_writer(L, q);
+}
+
+sph_status step_writers(int layout, int32_t *w)
+{
+    switch (layout) {
+    case 0: writers_l<0>(w); break;
+    case 1: writers_l<1>(w); break;
+    case 2: writers_l<2>(w); break;
+    case 3: writers_l<3>(w); break;
+    case 4: writers_l<4>(w); break;
+    case 5: writers_l<5>(w); break;
+    case 6: writers_l<6>(w); break;
+    case 7: writers_l<7>(w); break;
+    case 8: writers_l<8>(w); break;
+    case 9: writers_l<9>(w); break;
+    default: return fail(SPH_E_LAYOUT, "unknown layout");
+    }
+    return SPH_OK;
 }
 
 sph_status launch_pack_step(const sph_plan *p, int loop, const sph_store *s, const float *res, void *buf,

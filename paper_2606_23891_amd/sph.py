@@ -96,6 +96,7 @@ _SIGS = {
     "sph_step_pack": ([vp, i32, vp, vp, vp, vp, sz, vp], i32),
     "sph_step_interact": ([vp, i32, vp, vp, vp, sz, vp], i32),
     "sph_step_writeback": ([vp, vp, vp, vp, sz, vp], i32),
+    "sph_step_output_writers": ([i32, vp], i32),
     "sph_integrate_ws_bytes": ([vp, C.POINTER(sz)], i32),
     "sph_kick": ([vp, C.c_float, vp], i32),
     "sph_drift": ([vp, vp, C.c_double, vp, sz, C.POINTER(C.c_double), C.POINTER(C.c_float), vp], i32),
@@ -526,6 +527,17 @@ def sph_step_interact(plan, loop, ws, params=None, tuning=None, stream=None):
 def sph_step_writeback(plan, store, ws, tuning=None, stream=None):
     _check(lib().sph_step_writeback(_h(plan), _s(store), C.byref(tuning) if tuning else None, _ptr(ws),
                                     _nbytes(ws), _stream(stream)), "sph_step_writeback")
+
+
+STEP_OUTPUTS = [("rho", 0), ("rho_dh", 0), ("wcount", 0), ("div_v", 0), ("rot_v", 0), ("rot_v", 1),
+                ("rot_v", 2), ("lap_u", 0), ("v_sig", 0), ("a", 0), ("a", 1), ("a", 2), ("u_dt", 0)]
+
+
+def sph_step_output_writers(layout: int):
+    """per step output (STEP_OUTPUTS order): 1 / 2 = stored by that loop's pack, 3 = by the write-back"""
+    w = (i32 * 13)()
+    _check(lib().sph_step_output_writers(layout, w), "sph_step_output_writers")
+    return list(w)
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20   # SPH_NOALLOC_SCRATCH_BYTES of sph.h

@@ -98,6 +98,9 @@ def test_bench_stage_kernel_names():
     assert bench.stage_kernels("density", 8, t) == ["void sph::k_interact<0, 1, 256, false>(sph::InteractArgs)"]
     # algorithmic bytes per particle: the staged packs read earlier outputs
     # from the result planes and write the derived planes
-    assert bench.stage_bytes("pack_force", 1) == 56 + 24 + 68 + 0.5 + 32
-    assert bench.stage_bytes("force", 1) == 68 + 32 + 0.5 + 16
-    assert bench.stage_bytes("writeback", 1) == 104
+    shared = [1, 2, 3, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3]   # SAOS_SHARED: packs store rho, rho_dh, D, R
+    assert bench.stage_bytes("pack_gradient", 1, shared) == 48 + 4 + 40 + 0.5 + 16 + 4
+    assert bench.stage_bytes("pack_force", 1, shared) == 56 + 24 + 68 + 0.5 + 32 + 20
+    assert bench.stage_bytes("force", 1, shared) == 68 + 32 + 0.5 + 16
+    assert bench.stage_bytes("writeback", 1, shared) == 8 * 7
+    assert bench.stage_bytes("writeback", 1, [3] * 13) == 104
