@@ -440,19 +440,59 @@ def _pack_unpack_row(ps, plan, st, bufs, tuning, steps):
     return row
 
 
+def _staged_row(ps, plan, st, sws, tuning, steps):
+    """the staged step's conversions on one store: the three packs (earlier
+    outputs from the step's result planes, derived planes written) and the
+    write-back, the interactions left out (the result planes keep whatever a
+    previous step left there: the timing does not depend on their values)"""
+    import torch
+
+    from paper_2606_23891_amd import sph
+
+    stream = torch.cuda.current_stream()
+    writers = sph.sph_step_output_writers(st.layout)
+    stages = ["pack_density", "pack_gradient", "pack_force", "writeback"]
+
+    def run(i):
+        if i == 3:
+            sph.sph_step_writeback(plan, st, sws, tuning=tuning)
+        else:
+            sph.sph_step_pack(plan, i, st, sws, tuning=tuning)
+
+    for i in range(4):
+        run(i)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    acc = np.zeros(4)
+    for _ in range(steps):
+        ev[0].record(stream)
+        for i in range(4):
+            run(i)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        acc += [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
+    acc /= steps
+    row = {nm: {"ms": round(float(ms), 4), "GB/s": round(stage_bytes(nm, ps.n, writers) / (ms * 1e-3) / 1e9, 1)}
+           for nm, ms in zip(stages, acc)}
+    row["total_ms"] = round(float(acc.sum()), 4)
+    return row
+
+
 def layout_sweep(ps, plan, names, tuning, steps):
-    """pack + unpack time of each loop for every store layout (fresh store each)"""
+    """pack + unpack time of each loop for every store layout (fresh store
+    each), per-loop form, and the staged step's packs + write-back"""
     import torch
 
     from paper_2606_23891_amd import sph
 
     bufs = {L: sph.cell_buffers(plan, L) for L in range(3)}
+    sws = torch.zeros(sph.sph_batched_ws_bytes(plan), dtype=torch.uint8, device="cuda")
     res = {}
     for name in names:
         st = sph.Store(sph.LAYOUTS.index(name), ps.n)
         st.put_all(ps.fields)
         torch.cuda.synchronize()
         row = _pack_unpack_row(ps, plan, st, bufs, tuning, steps)
+        row["staged"] = _staged_row(ps, plan, st, sws, tuning, steps)
         res[name] = row
         log(f"layout {name}: pack+unpack {row['total_ms']:.3f} ms per step")
         del st

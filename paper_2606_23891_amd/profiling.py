@@ -14,6 +14,7 @@ CLI (on the pulled rocprofv3 output directories):
   python -m paper_2606_23891_amd.profiling traffic <fetch_dir> <write_dir> --copy-mib 1024 \
       --workload W --out F --command-fetch C1 --command-write C2
   python -m paper_2606_23891_amd.profiling sq <pmc_dir> [<pmc_dir> ...] --out F --command C
+  python -m paper_2606_23891_amd.profiling layouts <bench_json_line_file> --out F --command C --title T
 """
 from __future__ import annotations
 
@@ -179,6 +180,65 @@ def sq_markdown(dirs, title: str, commands, match: str = "sph::") -> str:
     return "\n".join(lines)
 
 
+def layouts_markdown(bench_out: str, title: str, command: str) -> str:
+    """the per-layout pack / unpack table, the offload table and the conversion
+    table of one bench.py run (its JSON line)"""
+    with open(bench_out) as f:
+        d = json.loads([ln for ln in f.read().splitlines() if ln.strip().startswith("{")][-1])
+    lines = [f"# {title}", "", "Command (one MI355X, repository root):", "", "```", command, "```", ""]
+    if "layouts" in d:
+        lines += ["Per-loop form (each loop packed, then unpacked into the store), batched, tuned launch "
+                  "parameters; HIP-event averages per layout.  GB/s are algorithmic bytes (fields the loop "
+                  "needs + packed record; results + outputs), so AoS is charged only for the bytes it needs.", "",
+                  "| layout | pack d | unpack d | pack g | unpack g | pack f | unpack f | total ms | vs AoS |",
+                  "|---|---|---|---|---|---|---|---|---|"]
+        for name, r in d["layouts"].items():
+            cells = []
+            for loop in ("density", "gradient", "force"):
+                x = r[loop]
+                cells.append(f"{x['pack_ms']:.3f} ms ({x['pack_GB/s']:.0f} GB/s)")
+                cells.append(f"{x['unpack_ms']:.3f} ms ({x['unpack_GB/s']:.0f} GB/s)")
+            lines.append(f"| {name} | " + " | ".join(cells) + f" | {r['total_ms']:.3f} | {r.get('vs_AOS', 0):.3f} |")
+        lines.append("")
+        if any("staged" in r for r in d["layouts"].values()):
+            lines += ["Staged step (the form the benchmark's step runs): the three packs, each taking the "
+                      "step's earlier outputs from its result planes, writing the derived planes and, where it "
+                      "loads an output's record whole, storing that output; then the write-back of the rest.  "
+                      "GB/s on the same algorithmic bytes as the step's stages.", "",
+                      "| layout | pack d | pack g | pack f | write-back | total ms |", "|---|---|---|---|---|---|"]
+            for name, r in d["layouts"].items():
+                g = r.get("staged")
+                if not g:
+                    continue
+                cells = [f"{g[k]['ms']:.3f} ms ({g[k]['GB/s']:.0f} GB/s)"
+                         for k in ("pack_density", "pack_gradient", "pack_force", "writeback")]
+                lines.append(f"| {name} | " + " | ".join(cells) + f" | {g['total_ms']:.3f} |")
+            lines.append("")
+    if "offload" in d:
+        lines += ["Offload form (host store in pinned memory; per loop, H2D of the substructs the loop reads or "
+                  "partially writes, batched compute, D2H of the substructs holding its outputs); pipelined: "
+                  "`sph_offload_step_async` with 4 and 16 bundles of cells, every input substruct sent once per "
+                  "step:", "",
+                  "| layout | ms/step | H2D GB | D2H GB | link GB/s | pipelined, 4 bundles | pipelined, 16 bundles |",
+                  "|---|---|---|---|---|---|---|"]
+        for name, r in d["offload"].items():
+            if not isinstance(r, dict):
+                continue
+            lines.append(f"| {name} | {r['ms_per_step']:.1f} | {r['h2d_GB']:.2f} | {r['d2h_GB']:.2f} | "
+                         f"{r['link_GB/s']:.1f} | {r['async4_ms_per_step']:.1f} | {r['async16_ms_per_step']:.1f} |")
+        if "pinned_copy_h2d_GB/s" in d["offload"]:
+            lines += ["", f"Pinned hipMemcpy H2D: {d['offload']['pinned_copy_h2d_GB/s']} GB/s."]
+        lines.append("")
+    if "convert" in d:
+        lines += ["Whole-store layout conversion (`sph_store_convert`; bytes = every record of both stores once):",
+                  "", "| conversion | ms | GB moved | GB/s |", "|---|---|---|---|"]
+        for name, r in d["convert"].items():
+            lines.append(f"| {name.replace('->', '→')} | {r['ms']:.3f} | {r['bytes'] / 1e9:.2f} | {r['GB/s']:.0f} |")
+        lines.append("")
+    lines += [f"Same run: staged batched step {d['ms_per_step']:.2f} ms ({d['value']:.3e} pairs/s).", ""]
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -202,6 +262,11 @@ def main():
     q.add_argument("--out", required=True)
     q.add_argument("--title", required=True)
     q.add_argument("--command", action="append", required=True)
+    y = sub.add_parser("layouts")
+    y.add_argument("bench_out")
+    y.add_argument("--out", required=True)
+    y.add_argument("--title", required=True)
+    y.add_argument("--command", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
         txt = stats_markdown(a.csv, a.title, a.command, a.note)
@@ -209,6 +274,8 @@ def main():
         algo = json.load(open(a.algo)) if a.algo else None
         txt = traffic_markdown(traffic(a.fetch_dir, a.write_dir, a.copy_mib << 20), a.workload,
                                a.command_fetch, a.command_write, algo)
+    elif a.cmd == "layouts":
+        txt = layouts_markdown(a.bench_out, a.title, a.command)
     else:
         txt = sq_markdown(a.dirs, a.title, a.command)
     with open(a.out, "w") as f:
