@@ -62,8 +62,8 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2, help="workload 1..3 (2: 256^3 Gresho)")
     ap.add_argument("--grid", type=int, default=None, help="cells per side (uniform workloads)")
     ap.add_argument("--n-side", type=int, default=None)
@@ -289,7 +289,8 @@ def main():
 
     out = {
         "metric": METRIC, "value": value, "unit": "pair interactions/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "warmup": a.warmup, "ms_per_step": ms_per_step, "ms_per_step_median": float(np.median(step_ms)),
+        "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": workload_name(a.config, ps), "layout": a.layout, "form": "batched, staged",
                    "pairs_per_step": total_pairs, "device": tune.device_key(dev), "cu": dev.multi_processor_count,

@@ -1,7 +1,10 @@
 """Hand-written adjoint kernels (through the C-ABI and the autograd Function)
 against FP64 central finite differences of the oracle's loss on 64 sampled
 coordinates and against the FP64 torch reference gradient, on the 32^3
-jittered Gresho lattice.
+jittered Gresho lattice (8^3 cells of 64: one tile per cell, each tile's
+neighbour walk shared by four waves), and against the reference gradient
+alone on 4^3 cells of 512 (eight tiles per cell) and 16^3 cells of 8 (tiles of
+8 particles, one wave per tile).
 
 e = |g - g_ref| / max(|g_ref|, 1e-3 * rms(g_ref over that input kind)) <= 1e-4.
 The kernels compute in FP64 (components small against their kind's rms are
@@ -22,8 +25,8 @@ TOL = 1e-4
 FLOOR = 1e-3
 
 
-def _setup(n_side=32):
-    ps = inputs.make_config(4, n_side=n_side)
+def _setup(n_side=32, grid=None):
+    ps = inputs.make_config(4, n_side=n_side, grid=grid)
     f = ps.fields
     d = oracle.density(f["x"], f["mass"], f["h"])
     g = oracle.gradient(f["x"], f["v"], f["mass"], f["h"], f["u"], d["rho"])
@@ -100,3 +103,20 @@ def test_adjoint_against_reference_and_fd():
     assert np.all(np.abs(gx.sum(0)) <= 1e-10 * np.abs(gx).sum(0))
     assert np.all(np.abs(gv.sum(0)) <= 1e-6 * np.abs(gv).sum(0))
     assert abs((m * gm).sum()) <= 1e-6 * np.abs(m * gm).sum()
+
+
+@pytest.mark.parametrize("grid", [4, 16])
+def test_adjoint_cell_grids(grid):
+    ps, atilde = _setup(grid=grid)
+    f = ps.fields
+    log(f"adjoint n={ps.n} grid {grid}^3: {inputs.cell_stats(ps.cells)}")
+    L, a, gx, gv, gm = _gpu_grad(ps, atilde)
+    Lr, ar, rx, rv, rm = adjoint_ref.reference_gradient(f, atilde.astype(np.float64))
+    assert L == pytest.approx(Lr, rel=1e-4)
+    ea = _err(a, ar, float(np.sqrt((ar ** 2).mean()))).max()
+    sc = {k: float(np.sqrt((r ** 2).mean())) for k, r in (("x", rx), ("v", rv), ("m", rm))}
+    ex = _err(gx, rx, sc["x"]).max()
+    ev = _err(gv, rv, sc["v"]).max()
+    em = _err(gm, rm, sc["m"]).max()
+    log(f"grid {grid}: a {ea:.2e}; gradient x {ex:.2e} v {ev:.2e} m {em:.2e}")
+    assert max(ea, ex, ev, em) <= TOL, (ea, ex, ev, em)
