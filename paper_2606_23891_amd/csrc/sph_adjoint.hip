@@ -75,30 +75,32 @@ __device__ __forceinline__ void spl64(double q, double &w, double &dw, double &d
     }
 }
 
-// F = (1/r) dW/dr = C3 H^-5 w'(q)/q and dF/dr = C3 H^-6 (q w'' - w')/q^2, both 0 beyond H
-__device__ __forceinline__ void kern_F64(double r, double H, double &F, double &Fp)
+// F = (1/r) dW/dr = C3 H^-5 w'(q)/q and dF/dr = C3 H^-6 (q w'' - w')/q^2, both 0
+// beyond H; from r, 1/r (0 at r = 0, where only the inner piece is reached),
+// H and 1/H, with 1/q = H/r, so no division
+__device__ __forceinline__ void kern_F64(double r, double ir, double H, double iH, double &F, double &Fp)
 {
     if (!(r < H)) {
         F = 0.0;
         Fp = 0.0;
         return;
     }
-    const double iH = 1.0 / H, q = r * iH;
-    const double K5 = kC3_64 * iH * iH * iH * iH * iH;
+    const double q = r * iH, iH2 = iH * iH;
+    const double K5 = kC3_64 * iH2 * iH2 * iH;
     if (q < 0.5) {
         F = K5 * (-12.0 + 18.0 * q);
         Fp = K5 * iH * 18.0;
     } else {
         const double t = 1.0 - q;
-        F = K5 * (-6.0 * t * t / q);
-        Fp = K5 * iH * 6.0 * t * (1.0 + q) / (q * q);
+        F = K5 * (-6.0 * t * t * H * ir);
+        Fp = K5 * 6.0 * t * (1.0 + q) * H * ir * ir;
     }
 }
 
 // per-particle quantities of the force loop, from the workspace's float64
 // density of the same positions
 struct Q64 {
-    double H, A, c, rho, om, u, at, ad;  // om = rho + h rho_dh / 3
+    double H, iH, A, Aom, c, rho, om, u, at, ad;  // om = rho + h rho_dh / 3, Aom = A / om
 };
 
 __device__ __forceinline__ Q64 q64(const AdjArgs &a, int64_t i)
@@ -108,10 +110,12 @@ __device__ __forceinline__ Q64 q64(const AdjArgs &a, int64_t i)
     const float4 ua = a.ua[i];
     const double g = a.gam;
     p.H = kGammaK64 * h;
+    p.iH = 1.0 / p.H;
     p.rho = a.rho64[2 * i];
     p.om = p.rho + h * a.rho64[2 * i + 1] / 3.0;
     p.u = ua.x;
     p.A = (g - 1.0) * p.u / p.om;
+    p.Aom = p.A / p.om;
     p.c = sqrt(g * (g - 1.0) * p.u);
     p.at = ua.y;
     p.ad = ua.z;
@@ -135,17 +139,17 @@ struct AdjKind<0> {
     static constexpr bool MIXED = false;
 };
 template <>
-struct AdjKind<1> {  // x y | z H | A c | rho u | at ad | m vx | vy vz | j -
+struct AdjKind<1> {  // x y | z H | A c | rho u | at ad | m vx | vy vz | j 1/H
     static constexpr int NF = 16, WIN = 64, NACC = 4;
     static constexpr bool MIXED = true;
 };
 template <>
-struct AdjKind<2> {  // x y | z H | A c | rho at | m vx | vy vz | abx aby | abz j
-    static constexpr int NF = 16, WIN = 64, NACC = 9;
+struct AdjKind<2> {  // x y | z H | A c | rho at | m vx | vy vz | abx aby | abz j | 1/H -
+    static constexpr int NF = 18, WIN = 64, NACC = 9;
     static constexpr bool MIXED = true;
 };
 template <>
-struct AdjKind<3> {  // x y | z H | m rhobar | rhodhbar -
+struct AdjKind<3> {  // x y | z H | m rhobar | rhodhbar 1/H
     static constexpr int NF = 8, WIN = 128, NACC = 4;
     static constexpr bool MIXED = true;
 };
@@ -164,7 +168,7 @@ struct AdjIO {
 
 // the lane's particle
 struct IAdj {
-    double x, y, z, H, H2;
+    double x, y, z, H, H2, iH;
     Q64 P;
     double vx, vy, vz, abx, aby, abz, hk, mk, rbk, dbk;
 };
@@ -178,6 +182,7 @@ __device__ __forceinline__ void adj_load_i(const AdjArgs &a, const AdjIO &io, in
     const float2 hm = a.hm[k];
     I.H = kGammaK64 * (double)hm.x;
     I.H2 = I.H * I.H;
+    I.iH = 1.0 / I.H;
     I.hk = hm.x;
     I.mk = hm.y;
     if constexpr (KIND == 1 || KIND == 2) {
@@ -215,18 +220,19 @@ __device__ __forceinline__ void adj_stage(const AdjArgs &a, const AdjIO &io, int
             r[4] = make_double2(Q.at, Q.ad);
             r[5] = make_double2(mj, (double)v.x);
             r[6] = make_double2((double)v.y, (double)v.z);
-            r[7] = make_double2((double)j, 0.0);
+            r[7] = make_double2((double)j, Q.iH);
         } else {
             r[3] = make_double2(Q.rho, Q.at);
             r[4] = make_double2(mj, (double)v.x);
             r[5] = make_double2((double)v.y, (double)v.z);
             r[6] = make_double2(io.abar[3 * j], io.abar[3 * j + 1]);
             r[7] = make_double2(io.abar[3 * j + 2], (double)j);
+            r[8] = make_double2(Q.iH, 0.0);
         }
     }
     if constexpr (KIND == 3) {
         r[2] = make_double2(mj, io.rbar[j]);
-        r[3] = make_double2(io.dbar[j], 0.0);
+        r[3] = make_double2(io.dbar[j], 1.0 / Hj);
     }
 }
 
@@ -248,33 +254,34 @@ __device__ __forceinline__ void adj_pair(const AdjArgs &a, const IAdj &I, int64_
     double rx, ry, rz;
     const double r2 = adj_r2(I, rec, rx, ry, rz);
     if constexpr (KIND == 0) {
-        const double q = sqrt(r2) / I.H;
+        const double q = sqrt(r2) * I.iH;
         double w, dw, d2w;
         spl64(q, w, dw, d2w);
         const double mj = rec[1].y;
         s[0] += mj * w;
         s[1] += mj * (3.0 * w + q * dw);
     } else if constexpr (KIND == 1) {
-        const double2 c2 = rec[2], c3 = rec[3], c4 = rec[4], c5 = rec[5], c6 = rec[6];
-        if (rec[7].x == (double)k) return;  // j == k
+        const double2 c2 = rec[2], c3 = rec[3], c4 = rec[4], c5 = rec[5], c6 = rec[6], c7 = rec[7];
+        if (c7.x == (double)k) return;  // j == k
         const Q64 &P = I.P;
         const double QH = rec[1].y, QA = c2.x, Qc = c2.y, Qrho = c3.x, Qu = c3.y, Qat = c4.x, Qad = c4.y;
         const double mj = c5.x;
         const double r = sqrt(r2);
+        const double ir = r > 0.0 ? 1.0 / r : 0.0;
         double Fk, Fkp, Fj, Fjp;
-        kern_F64(r, P.H, Fk, Fkp);
-        kern_F64(r, QH, Fj, Fjp);
+        kern_F64(r, ir, P.H, P.iH, Fk, Fkp);
+        kern_F64(r, ir, QH, c7.y, Fj, Fjp);
         const double Fb = 0.5 * (Fk + Fj);
         const double vx = I.vx - c5.y, vy = I.vy - c6.x, vz = I.vz - c6.y;
         const double dot = vx * rx + vy * ry + vz * rz;
-        const double mu = (r > 0.0 && dot < 0.0) ? dot / r : 0.0;
-        const double rb = 0.5 * (P.rho + Qrho);
-        const double Pi = -0.5 * 0.5 * (P.at + Qat) * (P.c + Qc - a.beta * mu) * mu / rb;
+        const double mu = dot < 0.0 ? dot * ir : 0.0;
+        const double irb = 2.0 / (P.rho + Qrho);  // 1 / rho_ij
+        const double Pi = -0.5 * 0.5 * (P.at + Qat) * (P.c + Qc - a.beta * mu) * mu * irb;
         const double S = P.A * Fk + QA * Fj + Pi * Fb;
         s[0] -= mj * S * rx;
         s[1] -= mj * S * ry;
         s[2] -= mj * S * rz;
-        s[3] += mj * (P.A * Fk * dot + 0.5 * Pi * Fb * dot + 0.5 * (P.ad + Qad) * fabs(dot) * (P.u - Qu) * Fb / rb);
+        s[3] += mj * (P.A * Fk * dot + 0.5 * Pi * Fb * dot + 0.5 * (P.ad + Qad) * fabs(dot) * (P.u - Qu) * Fb * irb);
     } else if constexpr (KIND == 2) {
         const double2 c2 = rec[2], c3 = rec[3], c4 = rec[4], c5 = rec[5], c6 = rec[6], c7 = rec[7];
         if (c7.y == (double)k) return;  // j == k
@@ -285,17 +292,17 @@ __device__ __forceinline__ void adj_pair(const AdjArgs &a, const IAdj &I, int64_
         const double ir = r > 0.0 ? 1.0 / r : 0.0;
         const double ex = rx * ir, ey = ry * ir, ez = rz * ir;
         double Fk, Fkp, Fj, Fjp;
-        kern_F64(r, P.H, Fk, Fkp);
-        kern_F64(r, QH, Fj, Fjp);
+        kern_F64(r, ir, P.H, P.iH, Fk, Fkp);
+        kern_F64(r, ir, QH, rec[8].x, Fj, Fjp);
         const double Fb = 0.5 * (Fk + Fj), Fbp = 0.5 * (Fkp + Fjp);
         const double vx = I.vx - c4.y, vy = I.vy - c5.x, vz = I.vz - c5.y;
         const double dot = vx * rx + vy * ry + vz * rz;
         const bool appr = r > 0.0 && dot < 0.0;
         const double mu = appr ? dot * ir : 0.0;
-        const double rb = 0.5 * (P.rho + Qrho);
+        const double irb = 2.0 / (P.rho + Qrho);  // 1 / rho_ij
         const double al = 0.5 * (P.at + Qat);
-        const double Pi = -0.5 * al * (P.c + Qc - a.beta * mu) * mu / rb;
-        const double dPi = -0.5 * (al / rb) * (P.c + Qc - 2.0 * a.beta * mu);  // dPi/dmu
+        const double Pi = -0.5 * al * (P.c + Qc - a.beta * mu) * mu * irb;
+        const double dPi = -0.5 * (al * irb) * (P.c + Qc - 2.0 * a.beta * mu);  // dPi/dmu
         const double S = P.A * Fk + QA * Fj + Pi * Fb;
         const double abjx = c6.x, abjy = c6.y, abjz = c7.x;
         const double wx = I.mk * abjx - mj * I.abx, wy = I.mk * abjy - mj * I.aby, wz = I.mk * abjz - mj * I.abz;
@@ -318,8 +325,8 @@ __device__ __forceinline__ void adj_pair(const AdjArgs &a, const IAdj &I, int64_
             s[5] += rw * cP * ez;
         }
         s[6] += S * (rx * abjx + ry * abjy + rz * abjz);
-        s[7] += rw * (Fk * (-P.A / P.om) - Fb * Pi / (2.0 * rb));
-        s[8] += rw * Fk * (-P.A * (I.hk / 3.0) / P.om);
+        s[7] += rw * (Fk * -P.Aom - 0.5 * Fb * Pi * irb);
+        s[8] += rw * Fk * (-(I.hk / 3.0) * P.Aom);
     } else {
         const double Hk = I.H, Hj = rec[1].y;
         const double2 c2 = rec[2];
@@ -328,7 +335,7 @@ __device__ __forceinline__ void adj_pair(const AdjArgs &a, const IAdj &I, int64_
         const double ir = r > 0.0 ? 1.0 / r : 0.0;
         double g = 0.0;  // radial derivative collected over both directions
         if (r < Hk) {    // rho_k's term m_j W(r, h_k)
-            const double iH = 1.0 / Hk, q = r * iH;
+            const double iH = I.iH, q = r * iH;
             double w, dw, d2w;
             spl64(q, w, dw, d2w);
             const double iH4 = iH * iH * iH * iH;
@@ -337,7 +344,7 @@ __device__ __forceinline__ void adj_pair(const AdjArgs &a, const IAdj &I, int64_
             g += mj * (I.rbk * Wr + I.dbk * Whr);
         }
         if (r < Hj) {  // rho_j's term m_k W(r, h_j)
-            const double iH = 1.0 / Hj, q = r * iH;
+            const double iH = rec[3].y, q = r * iH;
             double w, dw, d2w;
             spl64(q, w, dw, d2w);
             const double iH3 = iH * iH * iH, iH4 = iH3 * iH;
