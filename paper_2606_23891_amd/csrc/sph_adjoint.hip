@@ -129,28 +129,29 @@ __device__ __forceinline__ Q64 q64(const AdjArgs &a, int64_t i)
 // Kinds: 0 density, 1 force, 2 force adjoint, 3 density adjoint.  A staged
 // candidate takes NF doubles: its position translated into the tile's frame,
 // then its support gamma h_j (its mass for the density), then what the pair
-// term reads of it.  WIN candidates per window, NACC sums per particle.  MIXED
-// kinds interact within max(H_i, H_j), the density within H_i.
+// term reads of it.  WIN candidates per window, NACC sums per particle, WAVES
+// resident waves per SIMD the register allocation must allow.  MIXED kinds
+// interact within max(H_i, H_j), the density within H_i.
 template <int KIND>
 struct AdjKind;
 template <>
 struct AdjKind<0> {
-    static constexpr int NF = 4, WIN = 128, NACC = 2;
+    static constexpr int NF = 4, WIN = 128, NACC = 2, WAVES = 6;
     static constexpr bool MIXED = false;
 };
 template <>
 struct AdjKind<1> {  // x y | z H | A c | rho u | at ad | m vx | vy vz | j 1/H
-    static constexpr int NF = 16, WIN = 64, NACC = 4;
+    static constexpr int NF = 16, WIN = 64, NACC = 4, WAVES = 4;
     static constexpr bool MIXED = true;
 };
 template <>
 struct AdjKind<2> {  // x y | z H | A c | rho at | m vx | vy vz | abx aby | abz j | 1/H -
-    static constexpr int NF = 18, WIN = 64, NACC = 9;
+    static constexpr int NF = 18, WIN = 64, NACC = 9, WAVES = 3;
     static constexpr bool MIXED = true;
 };
 template <>
 struct AdjKind<3> {  // x y | z H | m rhobar | rhodhbar 1/H
-    static constexpr int NF = 8, WIN = 128, NACC = 4;
+    static constexpr int NF = 8, WIN = 128, NACC = 4, WAVES = 4;
     static constexpr bool MIXED = true;
 };
 
@@ -403,16 +404,25 @@ __device__ __forceinline__ void adj_wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// a value every lane holds, moved to scalar registers
+__device__ __forceinline__ double uniform64(double v)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 __device__ __forceinline__ double wave_min64(double v)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
+    return uniform64(v);
 }
 
 __device__ __forceinline__ double wave_max64(double v)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    return uniform64(v);
 }
 
 // test the nc staged candidates against every lane's particle (one bit per
@@ -429,6 +439,7 @@ __device__ __forceinline__ void adj_flush(const AdjArgs &a, const IAdj &I, int64
     for (int w = 0; w < NW; ++w) {
         m[w] = 0;
         const int n = nc - 64 * w < 64 ? nc - 64 * w : 64;
+#pragma unroll 2
         for (int c = 0; c < n; ++c) {
             double rx, ry, rz;
             const double r2 = adj_r2(I, L[64 * w + c], rx, ry, rz);
@@ -468,7 +479,8 @@ __device__ __forceinline__ void adj_flush(const AdjArgs &a, const IAdj &I, int64
 // stay active to the end (ballots and shuffles); lanes beyond the tile hold a
 // copy of its first particle and record no hits.
 template <int KIND>
-__global__ __launch_bounds__(64) void k_adj_pairs(AdjArgs a, AdjIO io)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(AdjKind<KIND>::WAVES))) void k_adj_pairs(
+    AdjArgs a, AdjIO io)
 {
     using K = AdjKind<KIND>;
     constexpr int NF2 = K::NF / 2;
