@@ -122,7 +122,6 @@ __device__ __forceinline__ Q64 q64(const AdjArgs &a, int64_t i)
     return p;
 }
 
-
 // ---------------------------------------------------------------------------
 // pair kinds and candidate windows
 // ---------------------------------------------------------------------------

@@ -33,10 +33,16 @@ JSON_BEGIN = "<!-- traffic-json"
 JSON_END = "-->"
 
 
+# translation units no kernel of the step comes from
+NOT_STEP = ("sph_adjoint.hip",)
+
+
 def source_hash() -> str:
-    """sha256 over the kernel sources and the build flags"""
+    """sha256 over the sources of the step's kernels (every kernel source but
+    the adjoint's translation unit) and the build flags"""
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.hpp")))
+    files = sorted(p for p in glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.hpp"))
+                   if os.path.basename(p) not in NOT_STEP)
     files.append(os.path.join(HERE, "build.py"))
     for p in files:
         h.update(os.path.basename(p).encode())
