@@ -102,16 +102,19 @@ def parse():
 TRAFFIC_SUMMARY = "hbm_traffic_gresho256.md"
 
 
-def stage_kernels(stage, layout, tuning):
+def stage_kernels(stage, layout, tuning, mixed=False):
     """the kernels a stage of the staged batched step launches (demangled
     names; the queue reset of the interaction stages, a one-thread kernel, is
-    left out)"""
+    left out); mixed: the plan's cells differ in width, so the force loop runs
+    its mixed-support kernel"""
     if stage == "writeback":
         return [f"void sph::k_writeback<{layout}>(sph::UnpackArgs)"]
     for L, nm in LOOP_NAME.items():
         if stage == f"pack_{nm}":
             return [f"void sph::k_pack<{layout}, {L}, true>(sph::PackArgs)"]
         if stage == nm:
+            if L == 2 and mixed:
+                return [f"void sph::k_interact_mixed<1, {tuning.window[L]}, false>(sph::InteractArgs)"]
             return [f"void sph::k_interact<{L}, 1, {tuning.window[L]}, false>(sph::InteractArgs)"]
     raise KeyError(stage)
 
@@ -280,7 +283,7 @@ def main():
 
     wl = f"{workload_name(a.config, ps)}; {a.layout}"
     tr = profiling.load_traffic(os.path.join(ROOT, "profiles", TRAFFIC_SUMMARY), wl)
-    knames = stage_kernels(dom, layout, tuning)
+    knames = stage_kernels(dom, layout, tuning, mixed=bool(info.mixed_widths))
     roof["kernels"] = knames
     roof["traffic"] = (sum(tr["kernels"][k]["bytes"] for k in knames)
                        if tr and all(k in tr["kernels"] for k in knames) else None)

@@ -157,6 +157,9 @@ typedef struct sph_plan_info {
     int32_t max_cell;     /* largest cell                                        */
     int32_t max_nbr;      /* most neighbour cells of one cell (incl. itself)     */
     int32_t batched_ok;   /* cells tile the store in order (batched form usable) */
+    int32_t mixed_widths; /* cells of more than one width: the force loop then  */
+                          /* tests mixed supports with two matrix-core products */
+    int32_t pad;
 } sph_plan_info;
 
 /* ---------------------------------------------------------------------- */

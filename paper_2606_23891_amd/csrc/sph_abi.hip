@@ -515,6 +515,8 @@ sph_status sph_plan_create(const sph_cell *cells, int32_t ncell, const sph_task 
     }
     if (acc != n) ok = false;
     p->batched_ok = ok;
+    for (int32_t c = 1; c < ncell; ++c)
+        if (cells[c].width != cells[0].width) p->mixed_widths = true;
     std::vector<Chunk> tiles;
     std::vector<CellRange> cr(ncell);
     std::vector<int32_t> nbr_off(ncell + 1, 0);
@@ -675,6 +677,8 @@ sph_status sph_plan_get_info(const sph_plan *p, sph_plan_info *info)
     info->max_cell = p->max_cell;
     info->max_nbr = p->max_nbr;
     info->batched_ok = p->batched_ok ? 1 : 0;
+    info->mixed_widths = p->mixed_widths ? 1 : 0;
+    info->pad = 0;
     return SPH_OK;
 }
 

@@ -422,14 +422,21 @@ __device__ __forceinline__ uint32_t sign_bits(const f32x16 &d)
 // lane holds its own particle's bits with candidate kb + b at bit b, as the
 // VALU test leaves them.  The products are accumulated in FP32 with no more
 // roundings than the VALU form, which the margin delta covers.
-template <int LOOP, int WIN, bool CNT>
-__device__ __forceinline__ void test_words_mfma(Lds<LOOP, WIN, CNT> &L, int nc, int nw, const IData &dd, bool valid)
+// DUAL (force loop, mixed supports): a second product shares the first four
+// columns and takes -H_j^2 of each candidate in its sixth column (against a 1
+// in the particle's) with t1 = |x_i|^2 - delta in the fifth; a candidate is a
+// hit when either product is negative, r^2 < H_i^2 or r^2 < H_j^2 (t0 then
+// holds t1 - H_i^2).
+template <int LOOP, int WIN, bool CNT, bool DUAL = false>
+__device__ __forceinline__ void test_words_mfma(Lds<LOOP, WIN, CNT> &L, int nc, int nw, const IData &dd, bool valid,
+                                                float t1 = 0.f)
 {
     const int lane = threadIdx.x & 63;
     // B operands of the particle halves 0-31 ([0]) and 32-63 ([1])
     const auto bxy = __builtin_amdgcn_permlane32_swap(__float_as_uint(dd.nx2), __float_as_uint(dd.ny2), false, false);
     const auto bzw = __builtin_amdgcn_permlane32_swap(__float_as_uint(dd.nz2), __float_as_uint(-1.0f), false, false);
     const auto bt = __builtin_amdgcn_permlane32_swap(__float_as_uint(dd.t0), 0u, false, false);
+    const auto bt1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(t1), __float_as_uint(1.0f), false, false);
     const float one = lane < 32 ? 1.0f : 0.0f;
     const int i = lane & 31;
     const int slot = 16 * ((i >> 2) & 1) + 4 * (i >> 3) + (i & 3);
@@ -446,16 +453,40 @@ __device__ __forceinline__ void test_words_mfma(Lds<LOOP, WIN, CNT> &L, int nc, 
             axy = q[comp];
             azw = q[2 + comp];
         }
-        // one half at a time: 16 accumulator registers live, not 32
+        // sixth column of the second product: -H_j^2 of the row's candidate
+        float hj = one;
+        if constexpr (DUAL) {
+            if (comp) {
+                const float ih = L.c1[kb + slot].w;
+                hj = -__builtin_amdgcn_rcpf(ih * ih);
+            }
+        }
+        // one half at a time: 16 accumulator registers live, not 32 (the
+        // second product is recomputed rather than kept beside the first)
         f32x16 d = __builtin_amdgcn_mfma_f32_32x32x2f32(axy, __uint_as_float(bxy[0]), f32x16{}, 0, 0, 0);
         d = __builtin_amdgcn_mfma_f32_32x32x2f32(azw, __uint_as_float(bzw[0]), d, 0, 0, 0);
         d = __builtin_amdgcn_mfma_f32_32x32x2f32(one, __uint_as_float(bt[0]), d, 0, 0, 0);
-        const uint32_t m0 = sign_bits(d);
+        uint32_t m0 = sign_bits(d);
+        if constexpr (DUAL) {
+            __builtin_amdgcn_sched_barrier(0);
+            d = __builtin_amdgcn_mfma_f32_32x32x2f32(axy, __uint_as_float(bxy[0]), f32x16{}, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_32x32x2f32(azw, __uint_as_float(bzw[0]), d, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_32x32x2f32(hj, __uint_as_float(bt1[0]), d, 0, 0, 0);
+            m0 |= sign_bits(d);
+        }
         __builtin_amdgcn_sched_barrier(0);
         d = __builtin_amdgcn_mfma_f32_32x32x2f32(axy, __uint_as_float(bxy[1]), f32x16{}, 0, 0, 0);
         d = __builtin_amdgcn_mfma_f32_32x32x2f32(azw, __uint_as_float(bzw[1]), d, 0, 0, 0);
         d = __builtin_amdgcn_mfma_f32_32x32x2f32(one, __uint_as_float(bt[1]), d, 0, 0, 0);
-        const auto h = __builtin_amdgcn_permlane32_swap(m0, sign_bits(d), false, false);
+        uint32_t m1 = sign_bits(d);
+        if constexpr (DUAL) {
+            __builtin_amdgcn_sched_barrier(0);
+            d = __builtin_amdgcn_mfma_f32_32x32x2f32(axy, __uint_as_float(bxy[1]), f32x16{}, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_32x32x2f32(azw, __uint_as_float(bzw[1]), d, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_32x32x2f32(hj, __uint_as_float(bt1[1]), d, 0, 0, 0);
+            m1 |= sign_bits(d);
+        }
+        const auto h = __builtin_amdgcn_permlane32_swap(m0, m1, false, false);
         uint32_t m = h[0] | (h[1] << 16);
         const int kn = __builtin_amdgcn_readfirstlane(min(32, nc - kb));
         if (kn < 32) m &= (1u << kn) - 1u;  // slots beyond the window's count
@@ -636,7 +667,7 @@ __device__ __forceinline__ void write_out(const InteractArgs &a, const IData &d,
 
 // test every staged candidate against every lane (phase 1: one bit per lane
 // and candidate, in LDS), then let each lane walk its own hits (phase 2)
-template <int LOOP, int WIN, bool CNT>
+template <int LOOP, int WIN, bool CNT, bool DUAL>
 __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN, CNT> &L, int nc, float hw, const IData &d,
                                       bool valid, Acc &acc)
 {
@@ -649,11 +680,18 @@ __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN, CNT>
         // the force loop's support is max(H_i, H_j): when no lane's support is
         // much below the window's largest Hw, max(H_i, Hw) costs nothing in
         // extra hits and saves a per-candidate maximum; otherwise (mixed
-        // scales) the test takes each candidate's own H_j
+        // scales) the test takes each candidate's own H_j, on the VALU or
+        // (DUAL) as a second matrix-core product -- the kernel variant for
+        // plans whose cells differ in width, where such windows are common
+        // (its extra registers would make the other variant spill)
         dd.t0 = dd.xi2 - test_delta(dd.ri, dd.rj);
         if (hw <= 1.02f * dd.hmin) {
             dd.t0 -= fmaxf(dd.H2, hw * hw);
             test_words_mfma<LOOP, WIN, CNT>(L, nc, nw, dd, valid);
+        } else if constexpr (DUAL) {
+            const float t1 = dd.t0;
+            dd.t0 -= dd.H2;
+            test_words_mfma<LOOP, WIN, CNT, true>(L, nc, nw, dd, valid, t1);
         } else {
             test_words<LOOP, WIN, CNT, true>(L, nc, nw, dd, valid);
         }
@@ -720,7 +758,7 @@ __device__ __forceinline__ bool tile_keep(const TileInfo &t, const R &r, const f
 // stage the kept particles of a batch of B loaded tiles, in tile order,
 // flushing the window whenever the next tile's survivors do not fit (one
 // flush call site, so the batch stays in registers)
-template <int LOOP, bool PREP, int WIN, int B, bool CNT>
+template <int LOOP, bool PREP, int WIN, int B, bool CNT, bool DUAL>
 __device__ __forceinline__ void stage_batch(const InteractArgs &a, Lds<LOOP, WIN, CNT> &L, int &nc, float &hw,
                                             const TileInfo (&tb)[B], const JRec<LOOP, PREP> (&rb)[B], const IData &d,
                                             bool valid, const float4 &lo, const float4 &hi, const float4 &cen,
@@ -764,7 +802,7 @@ __device__ __forceinline__ void stage_batch(const InteractArgs &a, Lds<LOOP, WIN
             return s;
         });
         if (!__builtin_amdgcn_readfirstlane(st.stop)) break;
-        flush<LOOP, WIN, CNT>(a, L, st.nc, st.hw, d, valid, acc);
+        flush<LOOP, WIN, CNT, DUAL>(a, L, st.nc, st.hw, d, valid, acc);
         st.nc = 0;
         st.hw = 0.f;
     }
@@ -778,7 +816,7 @@ template <int LOOP>
 constexpr int kJBatch = LOOP == 0 ? 4 : 2;
 
 // gather the candidates of one item's j-tile list (nj tiles) into the window
-template <int LOOP, int MODE, int WIN, bool CNT>
+template <int LOOP, int MODE, int WIN, bool CNT, bool DUAL>
 __device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN, CNT> &L, int &nc, float &hw,
                                           const Chunk &ch,
                                           IData &d, bool valid, const float4 &lo, const float4 &hi,
@@ -850,7 +888,7 @@ __device__ __forceinline__ void scan_item(const InteractArgs &a, Lds<LOOP, WIN, 
                 }
                 load_j<LOOP, PREP>(a, tb[b].js0 + (lane < tb[b].jn ? lane : 0), rb[b]);
             });
-            stage_batch<LOOP, PREP, WIN, B, CNT>(a, L, nc, hw, tb, rb, d, valid, lo, hi, cen, acc);
+            stage_batch<LOOP, PREP, WIN, B, CNT, DUAL>(a, L, nc, hw, tb, rb, d, valid, lo, hi, cen, acc);
         }
     }
 }
@@ -862,9 +900,8 @@ constexpr int kMinWaves = LOOP == 0 ? 5 : 4;
 // One wave per workgroup: the waves share nothing, and one-wave workgroups
 // let the CU pack as many LDS windows as fit (a wave's window is its only
 // LDS), instead of rounding down to whole four-window groups.
-template <int LOOP, int MODE, int WIN, bool CNT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<LOOP>))) void k_interact(
-    InteractArgs a)
+template <int LOOP, int MODE, int WIN, bool CNT, bool DUAL>
+__device__ __forceinline__ void interact_waves(const InteractArgs &a)
 {
     __shared__ Lds<LOOP, WIN, CNT> L;
     const int lane = threadIdx.x & 63;
@@ -941,10 +978,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<LO
         Acc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0};
         int nc = 0;
         float hw = 0.f;
-        scan_item<LOOP, MODE, WIN, CNT>(a, L, nc, hw, ch, d, valid, lo, hi, cen, halfdiag, acc);
-        if (nc > 0) flush<LOOP, WIN, CNT>(a, L, nc, hw, d, valid, acc);
+        scan_item<LOOP, MODE, WIN, CNT, DUAL>(a, L, nc, hw, ch, d, valid, lo, hi, cen, halfdiag, acc);
+        if (nc > 0) flush<LOOP, WIN, CNT, DUAL>(a, L, nc, hw, d, valid, acc);
         if (valid) write_out<LOOP, CNT>(a, d, acc);
     }
+}
+
+template <int LOOP, int MODE, int WIN, bool CNT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<LOOP>))) void k_interact(
+    InteractArgs a)
+{
+    interact_waves<LOOP, MODE, WIN, CNT, false>(a);
+}
+
+// the force loop for plans whose cells differ in width: mixed supports tested
+// as two matrix-core products
+template <int MODE, int WIN, bool CNT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<2>))) void k_interact_mixed(
+    InteractArgs a)
+{
+    interact_waves<2, MODE, WIN, CNT, true>(a);
 }
 
 __global__ void k_reset_queue(int32_t *q)
@@ -981,21 +1034,28 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
 
 // the counting variant runs only when the caller asks for pair counts
 template <int LOOP, int MODE, int WIN>
-static void launch_one(const InteractArgs &a, unsigned grid, hipStream_t st)
+static void launch_one(const InteractArgs &a, unsigned grid, hipStream_t st, bool mixed)
 {
+    if constexpr (LOOP == 2) {
+        if (mixed) {
+            if (a.counts) hipLaunchKernelGGL((k_interact_mixed<MODE, WIN, true>), dim3(grid), dim3(64), 0, st, a);
+            else hipLaunchKernelGGL((k_interact_mixed<MODE, WIN, false>), dim3(grid), dim3(64), 0, st, a);
+            return;
+        }
+    }
     if (a.counts) hipLaunchKernelGGL((k_interact<LOOP, MODE, WIN, true>), dim3(grid), dim3(64), 0, st, a);
     else hipLaunchKernelGGL((k_interact<LOOP, MODE, WIN, false>), dim3(grid), dim3(64), 0, st, a);
 }
 
 template <int LOOP, int MODE>
-static sph_status launch_win(const InteractArgs &a, int win, unsigned grid, hipStream_t st)
+static sph_status launch_win(const InteractArgs &a, int win, unsigned grid, hipStream_t st, bool mixed)
 {
     switch (win) {
-    case 128: launch_one<LOOP, MODE, 128>(a, grid, st); break;
-    case 256: launch_one<LOOP, MODE, 256>(a, grid, st); break;
+    case 128: launch_one<LOOP, MODE, 128>(a, grid, st, mixed); break;
+    case 256: launch_one<LOOP, MODE, 256>(a, grid, st, mixed); break;
     case 512:
         if constexpr (LOOP == 2) return fail(SPH_E_ARG, "force window is at most 256");
-        else launch_one<LOOP, MODE, 512>(a, grid, st);
+        else launch_one<LOOP, MODE, 512>(a, grid, st, false);
         break;
     default: return fail(SPH_E_ARG, "bad window");
     }
@@ -1078,9 +1138,9 @@ sph_status launch_interact(const sph_plan *p, int loop, bool cells, int32_t t0, 
             SPH_CHECK_LAUNCH("derived-plane launch");
         }
     }
-    if (loop == 0) return cells ? launch_win<0, 1>(a, win, grid, st) : launch_win<0, 0>(a, win, grid, st);
-    if (loop == 1) return cells ? launch_win<1, 1>(a, win, grid, st) : launch_win<1, 0>(a, win, grid, st);
-    return cells ? launch_win<2, 1>(a, win, grid, st) : launch_win<2, 0>(a, win, grid, st);
+    if (loop == 0) return cells ? launch_win<0, 1>(a, win, grid, st, false) : launch_win<0, 0>(a, win, grid, st, false);
+    if (loop == 1) return cells ? launch_win<1, 1>(a, win, grid, st, false) : launch_win<1, 0>(a, win, grid, st, false);
+    return cells ? launch_win<2, 1>(a, win, grid, st, p->mixed_widths) : launch_win<2, 0>(a, win, grid, st, p->mixed_widths);
 }
 
 }  // namespace sph

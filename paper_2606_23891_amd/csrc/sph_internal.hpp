@@ -120,6 +120,7 @@ struct sph_plan {
     int64_t nslot = 0, nchunk = 0;
     int32_t ntile = 0, max_cell = 0, max_nbr = 0;
     bool batched_ok = false;
+    bool mixed_widths = false;  // cells of more than one width (an octree)
     // device tables
     sph_cell *d_cells = nullptr;
     sph_task *d_tasks = nullptr;

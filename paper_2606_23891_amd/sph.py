@@ -48,7 +48,8 @@ class sph_tuning(C.Structure):
 class sph_plan_info(C.Structure):
     _fields_ = [("n", C.c_int64), ("ncell", C.c_int32), ("ntask", C.c_int32), ("nslot", C.c_int64),
                 ("nchunk", C.c_int64), ("ntile", C.c_int32), ("max_cell", C.c_int32),
-                ("max_nbr", C.c_int32), ("batched_ok", C.c_int32)]
+                ("max_nbr", C.c_int32), ("batched_ok", C.c_int32), ("mixed_widths", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class SphError(RuntimeError):

@@ -240,6 +240,9 @@ def _check_loops(ps, layout, mode, rows=None, bundle=1, tuning=None):
     """density -> gradient -> force on the GPU; each loop compared with the oracle
     fed the GPU's own previous-loop outputs (loop isolation)."""
     plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    # cells of several widths select the force kernel that tests mixed
+    # supports as two matrix-core products
+    assert plan.info().mixed_widths == int(np.unique(ps.cells["width"]).size > 1)
     st = device_store(ps, layout)
     prev = {}
     worst = {}
@@ -299,7 +302,7 @@ def test_loops_multitile_cells(mode):
 def test_loops_octree_uneven(mode):
     """the clustered set's octree at 64^3: cells of six widths holding 10 to
     2000 particles, supports wider than the smaller cells, tasks between cells
-    that are not adjacent"""
+    that are not adjacent; the force loop runs its mixed-support kernel"""
     ps = inputs.make_config(3, n_side=64)
     assert np.unique(ps.cells["width"]).size > 1
     rows = np.random.default_rng(4).choice(ps.n, 8192, replace=False)

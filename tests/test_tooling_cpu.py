@@ -95,6 +95,8 @@ def test_bench_stage_kernel_names():
     assert bench.stage_kernels("pack_force", 4, t) == ["void sph::k_pack<4, 2, true>(sph::PackArgs)"]
     assert bench.stage_kernels("writeback", 4, t) == ["void sph::k_writeback<4>(sph::UnpackArgs)"]
     assert bench.stage_kernels("force", 4, t) == ["void sph::k_interact<2, 1, 128, false>(sph::InteractArgs)"]
+    assert bench.stage_kernels("force", 4, t, mixed=True) == [
+        "void sph::k_interact_mixed<1, 128, false>(sph::InteractArgs)"]
     assert bench.stage_kernels("density", 8, t) == ["void sph::k_interact<0, 1, 256, false>(sph::InteractArgs)"]
     # algorithmic bytes per particle: the staged packs read earlier outputs
     # from the result planes and write the derived planes
