@@ -992,9 +992,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<LO
 }
 
 // the force loop for plans whose cells differ in width: mixed supports tested
-// as two matrix-core products
+// as two matrix-core products; three waves per SIMD leave it the registers of
+// the second product without spills (as fast as four waves with spills)
 template <int MODE, int WIN, bool CNT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<2>))) void k_interact_mixed(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_interact_mixed(
     InteractArgs a)
 {
     interact_waves<2, MODE, WIN, CNT, true>(a);
