@@ -665,6 +665,13 @@ __device__ __forceinline__ void write_out(const InteractArgs &a, const IData &d,
     if constexpr (CNT) a.counts[s] = acc.n;
 }
 
+// hits of the same mask word a lane takes per trip of the walk: the trip's
+// bookkeeping (word advance, lowest set bit, exit test) is shared by two pair
+// terms (density 2.86 -> 2.68 ms, gradient 3.76 -> 3.56, force 4.13 -> 4.01 at
+// 256^3; three or four per trip measure the same)
+template <int LOOP>
+constexpr int kHitsPerTrip = 2;
+
 // test every staged candidate against every lane (phase 1: one bit per lane
 // and candidate, in LDS), then let each lane walk its own hits (phase 2)
 template <int LOOP, int WIN, bool CNT, bool DUAL>
@@ -713,6 +720,15 @@ __device__ __forceinline__ void flush(const InteractArgs &a, Lds<LOOP, WIN, CNT>
             const int b = __builtin_ctz(cur);  // lowest slot first
             cur &= cur - 1u;
             pair<LOOP, CNT>(a, cand_load<LOOP, WIN, CNT>(L, 32 * w + b), d, acc);
+            // the lane's next hits of the same word, in slot order (a lane's
+            // sum keeps the order of its hits)
+            unroll<1, kHitsPerTrip<LOOP>>([&](auto) {
+                if (cur != 0) {
+                    const int b2 = __builtin_ctz(cur);
+                    cur &= cur - 1u;
+                    pair<LOOP, CNT>(a, cand_load<LOOP, WIN, CNT>(L, 32 * w + b2), d, acc);
+                }
+            });
         }
     }
     wave_sync();
