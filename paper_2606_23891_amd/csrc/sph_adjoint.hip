@@ -469,6 +469,11 @@ __device__ __forceinline__ void adj_flush(const AdjArgs &a, const IAdj &I, int64
             const int c = __builtin_ctzll(cur);
             cur &= cur - 1;
             adj_pair<KIND>(a, I, k, L[base + c], s);
+            if (cur != 0) {  // a second hit of the same word shares the trip
+                const int c2 = __builtin_ctzll(cur);
+                cur &= cur - 1;
+                adj_pair<KIND>(a, I, k, L[base + c2], s);
+            }
         }
     }
     adj_wave_sync();
