@@ -245,6 +245,40 @@ def layouts_markdown(bench_out: str, title: str, command: str) -> str:
     return "\n".join(lines)
 
 
+def fission_markdown(bench_out: str, title: str, command: str) -> str:
+    """the loop-fission table of one bench.py --fission run (its JSON line):
+    pack + unpack per step for every schedule, then each loop's pack and
+    unpack times"""
+    with open(bench_out) as f:
+        d = json.loads([ln for ln in f.read().splitlines() if ln.strip().startswith("{")][-1])
+    fis = d["fission"]
+    scheds = list(next(iter(fis.values())).keys())
+    label = lambda k: k.replace("_", " ")
+    lines = [f"# {title}", "", "Command (one MI355X, repository root):", "", "```", command, "```", "",
+             "`sph_tuning.pack_schedule` per column; each group of members (`sph_fission_passes`) is its own "
+             "kernel launch.",
+             "Entries: pack + unpack of all three loops per step, ms (relative to the fused kernels; pack + "
+             "unpack kernel launches).", "",
+             "| layout | " + " | ".join(label(k) for k in scheds) + " |",
+             "|---|" + "---|" * len(scheds)]
+    for name, rows in fis.items():
+        cells = []
+        for k in scheds:
+            r = rows[k]
+            npk = sum(v[0] for v in r["kernels"].values())
+            nup = sum(v[1] for v in r["kernels"].values())
+            cells.append(f"{r['total_ms']:.3f} ({r['vs_by_particle']:.2f}×; {npk}+{nup})")
+        lines.append(f"| {name} | " + " | ".join(cells) + " |")
+    lines += ["", "Per loop (pack ms / unpack ms):", "", "| layout | schedule | density | gradient | force |",
+              "|---|---|---|---|---|"]
+    for name, rows in fis.items():
+        for k in scheds:
+            r = rows[k]
+            cells = [f"{r[lp]['pack_ms']:.3f} / {r[lp]['unpack_ms']:.3f}" for lp in ("density", "gradient", "force")]
+            lines.append(f"| {name} | {label(k)} | " + " | ".join(cells) + " |")
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -268,6 +302,11 @@ def main():
     q.add_argument("--out", required=True)
     q.add_argument("--title", required=True)
     q.add_argument("--command", action="append", required=True)
+    fz = sub.add_parser("fission")
+    fz.add_argument("bench_out")
+    fz.add_argument("--out", required=True)
+    fz.add_argument("--title", required=True)
+    fz.add_argument("--command", required=True)
     y = sub.add_parser("layouts")
     y.add_argument("bench_out")
     y.add_argument("--out", required=True)
@@ -282,6 +321,8 @@ def main():
                                a.command_fetch, a.command_write, algo)
     elif a.cmd == "layouts":
         txt = layouts_markdown(a.bench_out, a.title, a.command)
+    elif a.cmd == "fission":
+        txt = fission_markdown(a.bench_out, a.title, a.command)
     else:
         txt = sq_markdown(a.dirs, a.title, a.command)
     with open(a.out, "w") as f:
