@@ -106,3 +106,18 @@ def test_bench_stage_kernel_names():
     assert bench.stage_bytes("force", 1, shared) == 68 + 32 + 0.5 + 16
     assert bench.stage_bytes("writeback", 1, shared) == 8 * 7
     assert bench.stage_bytes("writeback", 1, [3] * 13) == 104
+
+
+def test_fission_table(tmp_path):
+    row = lambda tot, rel, pk: {"density": {"pack_ms": 0.1, "unpack_ms": 0.2}, "gradient": {"pack_ms": 0.3,
+                                "unpack_ms": 0.4}, "force": {"pack_ms": 0.5, "unpack_ms": 0.6}, "total_ms": tot,
+                                "vs_by_particle": rel, "kernels": {"density": [pk, 1], "gradient": [pk, 2],
+                                                                   "force": [pk, 3]}}
+    out = {"fission": {"SOA": {"by_particle": row(2.1, 1.0, 1), "by_element": row(4.2, 2.0, 5)}}}
+    p = tmp_path / "b.log"
+    p.write_text("[bench] log line\n" + json.dumps(out) + "\n")
+    txt = profiling.fission_markdown(str(p), "T", "python bench.py --fission SOA")
+    assert "| layout | by particle | by element |" in txt
+    # totals, ratio to the fused kernels, and pack + unpack kernel launches over the three loops
+    assert "| SOA | 2.100 (1.00×; 3+6) | 4.200 (2.00×; 15+6) |" in txt
+    assert "| SOA | by element | 0.100 / 0.200 | 0.300 / 0.400 | 0.500 / 0.600 |" in txt
