@@ -309,6 +309,30 @@ def test_loops_octree_uneven(mode):
     _check_loops(ps, 4, mode, rows=rows, bundle=64)
 
 
+def _clustered_uniform_grid(n_side=32):
+    """the clustered set (supports spanning 90x) on a uniform grid whose cells
+    are as wide as the largest support"""
+    ps = inputs.make_config(3, n_side=n_side)
+    hs = inputs.SUPPORT_PER_H * float(ps.fields["h"].max())
+    nc = 4
+    while 1.0 / (2 * nc) >= hs:
+        nc *= 2
+    f, cells, tasks = inputs.uniform_grid(dict(ps.fields), nc)
+    return inputs.ParticleSet(f, cells, tasks, {"config": -1, "n_side": n_side, "grid": nc})
+
+
+@pytest.mark.parametrize("mode", ["per_task", "batched"])
+def test_loops_mixed_supports_uniform_grid(mode):
+    """mixed supports in the cells of a uniform grid: the force kernel of
+    single-width plans then tests each candidate's own support on the VALU"""
+    ps = _clustered_uniform_grid()
+    assert 1.0 / ps.meta["grid"] >= inputs.SUPPORT_PER_H * float(ps.fields["h"].max())
+    h = ps.fields["h"]
+    assert h.max() / h.min() > 50
+    rows = np.random.default_rng(6).choice(ps.n, 8192, replace=False)
+    _check_loops(ps, 4, mode, rows=rows, bundle=64)
+
+
 def _coincident_set(seed=5):
     """a 16^3 jittered lattice in which 48 particles are moved onto 48 others:
     distinct particles at r = 0, the method's degenerate pair (each keeps its
