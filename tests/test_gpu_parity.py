@@ -292,8 +292,11 @@ def test_loops_lattice(mode):
 
 
 @pytest.mark.parametrize("mode", ["per_task", "batched"])
-def test_loops_multitile_cells(mode):
-    ps = inputs.make_config(2, n_side=32, grid=4)
+@pytest.mark.parametrize("n_side", [32, 64])
+def test_loops_multitile_cells(mode, n_side):
+    """4^3 cells of 512 (8 tiles each, 216 j-tiles per cell) and of 4 096
+    particles (64 tiles each, 1 728 j-tiles per cell: 27 cull rounds per item)"""
+    ps = inputs.make_config(2, n_side=n_side, grid=4)
     rows = np.random.default_rng(1).choice(ps.n, 2048, replace=False)
     _check_loops(ps, 0, mode, rows=rows, bundle=64)
 
