@@ -250,20 +250,29 @@ def h_newton_step(h, m, rho, rho_dh, reach, eta, tol):
     return out, moved
 
 
-def h_iterate(x, m, h, reach, eta=1.2348, tol=1e-4, max_iter=30) -> Dict[str, np.ndarray]:
+def h_iterate(x, m, h, reach, eta=1.2348, tol=1e-4, max_iter=30, rows=None,
+              grid=False) -> Dict[str, np.ndarray]:
     """The smoothing-length iteration: the FP64 brute-force density of the
     particles whose h moved (all on the first pass), then one h_newton_step
     for them, until none moves or max_iter passes.  Returns the final h, the
     density outputs belonging to it, the passes run and the particles that
-    still moved in the last pass."""
+    still moved in the last pass.
+
+    rows: iterate only these particles.  A particle's density depends on its
+    own h alone, so each row ends exactly as in the iteration of the whole
+    set; the other particles keep their h (and zero density outputs), and
+    passes / unconverged count the rows only.  grid: the density's candidate
+    grid mode (the same sums)."""
     h = np.asarray(h, np.float32).copy()
     n = h.size
     width = np.asarray(reach, np.float64)
     rho, rdh, wc = np.zeros(n), np.zeros(n), np.zeros(n)
-    rows = np.arange(n)
+    rows = np.arange(n) if rows is None else np.unique(np.asarray(rows, np.int64))
     passes, still = 0, 0
     for _ in range(max_iter):
-        d = density(x, m, h, rows=rows)
+        if rows.size == 0:
+            break
+        d = density(x, m, h, rows=rows, grid=grid)
         rho[rows], rdh[rows], wc[rows] = d["rho"], d["rho_dh"], d["wcount"]
         hn, moved = h_newton_step(h[rows], np.asarray(m)[rows], rho[rows], rdh[rows], width[rows], eta, tol)
         h[rows] = hn

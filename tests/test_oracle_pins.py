@@ -472,6 +472,27 @@ def test_h_iteration_fixed_point_perfect_lattice(start):
     np.testing.assert_array_equal(d["rho"], out["rho"])
 
 
+def test_h_iteration_rows_and_grid_match_whole_set():
+    """A particle's density depends on its own h alone, so iterating a subset
+    of rows (in the candidate-grid mode) must end every row exactly where the
+    whole-set brute-force iteration ends it, while the other rows keep their h"""
+    ps = inputs.make_config(2, n_side=16, grid=4)
+    rng = np.random.default_rng(4)
+    h0 = (ps.fields["h"] * rng.uniform(0.8, 1.25, ps.n)).astype(np.float32)
+    reach = oracle.particle_reach(ps.cells, ps.tasks, ps.n)
+    full = oracle.h_iterate(ps.fields["x"], ps.fields["mass"], h0, reach, tol=1e-4)
+    rows = np.sort(rng.choice(ps.n, 300, replace=False))
+    sub = oracle.h_iterate(ps.fields["x"], ps.fields["mass"], h0, reach, tol=1e-4, rows=rows, grid=True)
+    assert full["unconverged"] == 0 and sub["unconverged"] == 0
+    assert 2 <= sub["passes"] <= full["passes"]
+    assert sub["h"][rows].tobytes() == full["h"][rows].tobytes()
+    for k in ("rho", "rho_dh", "wcount"):
+        np.testing.assert_array_equal(sub[k][rows], full[k][rows])
+    rest = np.setdiff1d(np.arange(ps.n), rows)
+    assert sub["h"][rest].tobytes() == h0[rest].tobytes()
+    assert not sub["rho"][rest].any()
+
+
 # --------------------------------------------------------------------------
 # time integration
 # --------------------------------------------------------------------------
