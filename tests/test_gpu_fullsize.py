@@ -5,12 +5,24 @@ counts; the counting kernels are checked too.  Sampled particles are compared
 with the oracle (candidate-grid mode, bit for bit its brute force), each loop
 fed the GPU's previous-loop outputs: 256^3 Gresho on 32^3 cells and the 188^3
 clustered set on its octree.  Besides the tolerance of the parity tests, the
-plain scaled error |q_gpu - q_ref| / max(|q_ref|, S) is logged."""
+plain scaled error |q_gpu - q_ref| / max(|q_ref|, S) is logged.  At 256^3 the
+smoothing-length iteration and a kick-drift-kick step are checked the same
+way, as the benchmark's --hiter and --kdk runs launch them."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2606_23891_amd import inputs, sph
+
+_SETS = {}
+
+
+def _workload(k):
+    """the full-size particle set (built once per test session)"""
+    if k not in _SETS:
+        log(f"building workload {k}")
+        _SETS[k] = inputs.make_config(k)
+    return _SETS[k]
 
 from gpuhelp import (LOOP_OUT, bench_tuning, compare_loop, device_store, log, oracle_loop, outputs,
                      run_batched_loop)
@@ -19,8 +31,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _run(k, nrows, layout_name, convert_to=None):
-    log(f"building workload {k}")
-    ps = inputs.make_config(k)
+    ps = _workload(k)
     log(f"n={ps.n} cells={len(ps.cells)} tasks={len(ps.tasks)} {inputs.cell_stats(ps.cells)}")
     tuning, cached = bench_tuning(ps, layout_name)
     log(f"tuning ({'benchmark cache entry' if cached else 'defaults'}): windows {list(tuning.window)} "
@@ -74,3 +85,97 @@ def test_gresho256_sampled():
 
 def test_clustered188_sampled():
     _run(3, 16384, "SAOS_SHARED")
+
+
+def _sample(ps, nrows, seed):
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(ps.n, nrows, replace=False)
+    order = np.argsort(ps.fields["h"])
+    return np.unique(np.r_[rows, order[:64], order[-64:]])
+
+
+def test_gresho256_h_iteration_sampled():
+    """The smoothing-length iteration from every h scaled by a seeded factor in
+    [0.9, 1.1] (the benchmark's start): sampled rows' final h within 3 tol of
+    the oracle's iteration of the same rows, each side's h solving
+    rho(h) h^3 = m eta^3 to 5 tol on the FP64 density, and the densities left
+    in the store those of the GPU's final h (1e-5)."""
+    import torch
+    eta, tol = 1.2348, 1e-4
+    ps = _workload(2)
+    tuning, cached = bench_tuning(ps, "SAOS_SHARED")
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    h0 = (ps.fields["h"] * np.random.default_rng(17).uniform(0.9, 1.1, ps.n)).astype(np.float32)
+    st = device_store(ps, sph.LAYOUTS.index("SAOS_SHARED"), extra={"h": h0})
+    ws = torch.zeros(sph.sph_h_iterate_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    log(f"h iteration n={ps.n} ({'benchmark cache entry' if cached else 'default'} tuning)")
+    passes, still = sph.sph_h_iterate(plan, st, ws, eta=eta, tol=tol, max_iter=30, tuning=tuning)
+    torch.cuda.synchronize()
+    hg = st.get("h")
+    log(f"GPU: {passes} passes, {still} unconverged")
+    rows = _sample(ps, 8192, 23)
+    x, m = ps.fields["x"], ps.fields["mass"]
+    reach = oracle.particle_reach(ps.cells, ps.tasks, ps.n)
+    ref = oracle.h_iterate(x, m, h0, reach, eta=eta, tol=tol, rows=rows, grid=True)
+    log(f"oracle on {rows.size} rows: {ref['passes']} passes, {ref['unconverged']} unconverged")
+    assert still == 0 and ref["unconverged"] == 0
+    assert 2 <= passes <= 30
+    hr = ref["h"][rows].astype(np.float64)
+    dh = float(np.max(np.abs(hg[rows] - hr) / hr))
+    log(f"final h: worst relative difference {dh:.2e}")
+    assert dh <= 3 * tol
+    mr = m[rows].astype(np.float64)
+    for name, h in (("GPU", hg), ("oracle", ref["h"])):
+        d = oracle.density(x, m, h, rows=rows, grid=True)
+        res = np.abs(d["rho"] * h[rows].astype(np.float64) ** 3 - mr * eta ** 3) / (mr * eta ** 3)
+        log(f"{name}: worst residual {res.max():.2e}")
+        assert res.max() <= 5 * tol
+    ref_d = oracle.density(x, m, hg, rows=rows, epsx=oracle.pack_resolution(ps.cells), grid=True)
+    errs = compare_loop(0, outputs(st, 0), ref_d, rows=rows)
+    log(f"density at the final h, worst {max(errs.values()):.2e}")
+    assert max(errs.values()) <= 1e-5, errs
+    plan.close()
+
+
+def test_gresho256_kdk_step_sampled():
+    """One kick-drift-kick step with dt from the CFL condition (C = 0.1, the
+    benchmark's): positions after the drift bit for bit on every particle, the
+    loops at the drifted state on sampled rows within the tolerance (each fed
+    the GPU's previous-loop outputs), and the second half kick bit for bit on
+    every particle given the GPU's accelerations."""
+    import torch
+    ps = _workload(2)
+    tuning, _ = bench_tuning(ps, "SAOS_SHARED")
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    st = device_store(ps, sph.LAYOUTS.index("SAOS_SHARED"))
+    sws = torch.zeros(sph.sph_batched_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    sph.sph_step_batched(plan, st, sws, tuning=tuning)   # a, u_dt and V of the starting state
+    iws = torch.zeros(sph.sph_integrate_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    dt = sph.sph_cfl_dt(plan, st, iws, cfl=0.1)
+    log(f"kdk step n={ps.n} dt={dt:.3e}")
+    names = ("x", "v", "a", "mass", "h", "u", "u_dt", "alpha_v", "alpha_d")
+    f0 = {k: st.get(k) for k in names}
+    del sws, iws
+    ws = torch.zeros(sph.kdk_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    assert sph.sph_step_kdk(plan, st, ws, dt, tuning=tuning) == 0
+    torch.cuda.synchronize()
+    half = np.float32(0.5) * np.float32(dt)
+    vh, uh = oracle.kick(f0["v"], f0["a"], f0["u"], f0["u_dt"], half)
+    xn, _ = oracle.drift(f0["x"], vh, np.float64(np.float32(dt)), ps.cells)
+    assert st.get("x").tobytes() == xn.tobytes()
+    rows = _sample(ps, 16384, 29)
+    f1 = dict(f0, x=xn, v=vh, u=uh)
+    eps = oracle.pack_resolution(ps.cells)
+    prev = {}
+    for loop in range(3):
+        g = outputs(st, loop)
+        ref = oracle_loop(f1, loop, prev, rows=rows, epsx=eps, grid=True)
+        errs = compare_loop(loop, g, ref, rows=rows)
+        log(f"kdk step: loop {loop} on {rows.size} rows, worst {max(errs.values()):.2e}")
+        assert max(errs.values()) <= 1e-5, errs
+        for kk in LOOP_OUT[loop]:
+            prev[kk] = g[kk].astype(np.float64)
+    v2, u2 = oracle.kick(vh, st.get("a"), uh, st.get("u_dt"), half)
+    assert st.get("v").tobytes() == v2.tobytes()
+    assert st.get("u").tobytes() == u2.tobytes()
+    plan.close()
