@@ -6,8 +6,9 @@ with the oracle (candidate-grid mode, bit for bit its brute force), each loop
 fed the GPU's previous-loop outputs: 256^3 Gresho on 32^3 cells and the 188^3
 clustered set on its octree.  Besides the tolerance of the parity tests, the
 plain scaled error |q_gpu - q_ref| / max(|q_ref|, S) is logged.  At 256^3 the
-smoothing-length iteration and a kick-drift-kick step are checked the same
-way, as the benchmark's --hiter and --kdk runs launch them."""
+smoothing-length iteration, a kick-drift-kick step and the offload forms are
+checked the same way, as the benchmark's --hiter, --kdk and --offload runs
+launch them."""
 import numpy as np
 import pytest
 
@@ -178,4 +179,54 @@ def test_gresho256_kdk_step_sampled():
     v2, u2 = oracle.kick(vh, st.get("a"), uh, st.get("u_dt"), half)
     assert st.get("v").tobytes() == v2.tobytes()
     assert st.get("u").tobytes() == u2.tobytes()
+    plan.close()
+
+
+@pytest.mark.parametrize("form", ["offload", "offload_async4"])
+def test_gresho256_offload_sampled(form):
+    """The offload step as the benchmark times it (SAOS_SHARED store in pinned
+    host memory, per-loop copies; the pipelined form with 4 bundles of cells on
+    two copy streams; the benchmark's launch parameters): the host store read
+    through the oracle's layout tables holds, on sampled rows, the loops'
+    outputs within the tolerance of the oracle (each loop fed the previous
+    loop's outputs as the host store holds them), and every input field byte
+    for byte as it was, on every particle."""
+    import torch
+
+    ps = _workload(2)
+    tuning, _ = bench_tuning(ps, "SAOS_SHARED")
+    lay = sph.LAYOUTS.index("SAOS_SHARED")
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    ws = torch.zeros(sph.sph_batched_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    dev = sph.Store(lay, ps.n)
+    dev.put_all(ps.fields)
+    host = sph.Store(lay, ps.n, device="pinned")
+    for hsub, dsub in zip(host.subs, dev.subs):
+        hsub.copy_(dsub.cpu())
+    log(f"{form} n={ps.n}")
+    if form == "offload":
+        sph.sph_offload_step(plan, host, dev, ws, tuning=tuning)
+    else:
+        sph.sph_offload_step_async(plan, host, dev, ws, nbundle=4, tuning=tuning)
+    torch.cuda.synchronize()
+    del dev, ws
+    hv = oracle.HostStore(lay, ps.n)
+    for dst, src, b in zip(hv.subs, host.subs, hv.sub_bytes):
+        dst[:] = src[: ps.n * b].numpy()
+    del host
+    rows = _sample(ps, 16384, 31)
+    eps = oracle.pack_resolution(ps.cells)
+    prev = {}
+    for loop in range(3):
+        got = {k: hv.get(k) for k in LOOP_OUT[loop]}
+        ref = oracle_loop(ps.fields, loop, prev, rows=rows, epsx=eps, grid=True)
+        errs = compare_loop(loop, got, ref, rows=rows)
+        log(f"{form} loop {loop} on {rows.size} rows: worst {max(errs.values()):.2e}")
+        assert max(errs.values()) <= 1e-5, (form, loop, errs)
+        for kk in LOOP_OUT[loop]:
+            prev[kk] = got[kk].astype(np.float64)
+    for k, want in ps.fields.items():
+        if k in sph.FIELDS:
+            got = hv.get(k)
+            assert got.tobytes() == np.ascontiguousarray(want).astype(got.dtype).tobytes(), (form, k)
     plan.close()
