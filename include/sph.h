@@ -48,7 +48,8 @@ extern "C" {
 typedef enum sph_status {
     SPH_OK = 0,
     SPH_E_ARG = -1,         /* null / misaligned pointer, bad enum, bad range        */
-    SPH_E_LAYOUT = -2,      /* store does not match the layout's substruct count     */
+    SPH_E_LAYOUT = -2,      /* unknown layout, or a store that does not match the   */
+                            /* layout's substruct count                            */
     SPH_E_CAPACITY = -3,    /* a caller buffer is smaller than the call needs        */
     SPH_E_PLAN = -4,        /* cells / tasks inconsistent (index out of range, ...)  */
     SPH_E_HIP = -5,         /* a HIP runtime call failed                             */
