@@ -13,6 +13,10 @@
  *       density -> gradient -> force step (sph_step_batched, default launch
  *       parameters and physics constants) and writes every output field to
  *       OUT.
+ *   sph_abi_client per_task IN OUT BUNDLE
+ *       The same through the per-task calls: for each loop in turn,
+ *       sph_zero_outputs, then for every bundle of BUNDLE consecutive tasks
+ *       sph_pack -> sph_density / sph_gradient / sph_force -> sph_unpack.
  *
  * IN (little endian): int64 n, int32 ncell, int32 ntask, int32 layout,
  * int32 0; ncell sph_cell records; ntask sph_task records; then x (n x 3
@@ -123,7 +127,44 @@ static int tables(void)
     return 0;
 }
 
-static int step(const char *in_path, const char *out_path)
+/* the loops through the per-task calls, `bundle` tasks per pack / launch / unpack */
+static void per_task(const sph_plan *plan, const sph_store *store, int32_t ntask, int32_t bundle,
+                     const sph_params *params)
+{
+    int32_t loop, t0;
+    for (loop = 0; loop < 3; ++loop) {
+        size_t pmax = 256, rmax = 256;
+        void *pack = NULL, *res = NULL;
+        /* buffers for the largest bundle */
+        for (t0 = 0; t0 < ntask; t0 += bundle) {
+            const int32_t t1 = t0 + bundle < ntask ? t0 + bundle : ntask;
+            int64_t nslot = 0;
+            size_t pb = 0, rb = 0;
+            CHECK(sph_plan_buffer_bytes(plan, (sph_loop)loop, t0, t1, &nslot, &pb, &rb));
+            if (pb > pmax) pmax = pb;
+            if (rb > rmax) rmax = rb;
+        }
+        HIPCHECK(hipMalloc(&pack, pmax));
+        HIPCHECK(hipMalloc(&res, rmax));
+        CHECK(sph_zero_outputs(plan, (sph_loop)loop, store, NULL));
+        for (t0 = 0; t0 < ntask; t0 += bundle) {
+            const int32_t t1 = t0 + bundle < ntask ? t0 + bundle : ntask;
+            CHECK(sph_pack(plan, (sph_loop)loop, store, t0, t1, pack, pmax, NULL));
+            if (loop == SPH_DENSITY)
+                CHECK(sph_density(plan, pack, pmax, t0, t1, params, res, rmax, NULL, NULL));
+            else if (loop == SPH_GRADIENT)
+                CHECK(sph_gradient(plan, pack, pmax, t0, t1, params, res, rmax, NULL, NULL));
+            else
+                CHECK(sph_force(plan, pack, pmax, t0, t1, params, res, rmax, NULL, NULL));
+            CHECK(sph_unpack(plan, (sph_loop)loop, res, rmax, t0, t1, store, NULL));
+        }
+        HIPCHECK(hipDeviceSynchronize());
+        HIPCHECK(hipFree(pack));
+        HIPCHECK(hipFree(res));
+    }
+}
+
+static int step(const char *in_path, const char *out_path, int32_t bundle)
 {
     FILE *fin = fopen(in_path, "rb"), *fout;
     int64_t n;
@@ -180,15 +221,19 @@ static int step(const char *in_path, const char *out_path)
     fclose(fin);
 
     CHECK(sph_plan_create(cells, hdr[0], tasks, hdr[1], n, &plan));
-    CHECK(sph_batched_ws_bytes(plan, &ws_bytes));
-    HIPCHECK(hipMalloc(&ws, ws_bytes));
     params.gamma_ad = 5.0f / 3.0f;
     params.beta_visc = 3.0f;
     params.balsara_eps = 1e-4f;
     params.pad = 0.0f;
-    sph_tuning_default(&tuning);
-    CHECK(sph_step_batched(plan, &store, &params, &tuning, ws, ws_bytes, NULL));
-    HIPCHECK(hipDeviceSynchronize());
+    if (bundle > 0) {
+        per_task(plan, &store, hdr[1], bundle, &params);
+    } else {
+        CHECK(sph_batched_ws_bytes(plan, &ws_bytes));
+        HIPCHECK(hipMalloc(&ws, ws_bytes));
+        sph_tuning_default(&tuning);
+        CHECK(sph_step_batched(plan, &store, &params, &tuning, ws, ws_bytes, NULL));
+        HIPCHECK(hipDeviceSynchronize());
+    }
 
     fout = fopen(out_path, "wb");
     if (!fout) {
@@ -209,20 +254,23 @@ static int step(const char *in_path, const char *out_path)
     }
     fclose(fout);
     sph_plan_destroy(plan);
-    HIPCHECK(hipFree(ws));
+    if (ws) HIPCHECK(hipFree(ws));
     HIPCHECK(hipFree(dbuf));
     for (s = 0; s < nsub; ++s) HIPCHECK(hipFree(store.sub[s]));
     free(hbuf);
     free(cells);
     free(tasks);
-    printf("step n=%lld cells=%d tasks=%d layout=%d ok\n", (long long)n, hdr[0], hdr[1], hdr[2]);
+    printf("%s n=%lld cells=%d tasks=%d layout=%d ok\n", bundle > 0 ? "per_task" : "step", (long long)n, hdr[0],
+           hdr[1], hdr[2]);
     return 0;
 }
 
 int main(int argc, char **argv)
 {
     if (argc == 2 && strcmp(argv[1], "tables") == 0) return tables();
-    if (argc == 4 && strcmp(argv[1], "step") == 0) return step(argv[2], argv[3]);
-    fprintf(stderr, "usage: %s tables | step IN OUT\n", argv[0]);
+    if (argc == 4 && strcmp(argv[1], "step") == 0) return step(argv[2], argv[3], 0);
+    if (argc == 5 && strcmp(argv[1], "per_task") == 0 && atoi(argv[4]) > 0)
+        return step(argv[2], argv[3], (int32_t)atoi(argv[4]));
+    fprintf(stderr, "usage: %s tables | step IN OUT | per_task IN OUT BUNDLE\n", argv[0]);
     return 2;
 }

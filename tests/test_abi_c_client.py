@@ -5,9 +5,10 @@ On the CPU: the header and client compile under gcc -std=c99 -pedantic
 -Werror; the client's view of the layout, field and packed-record tables
 matches the oracle's own tables and the Python binding's; invalid arguments
 fail with the documented codes before any device is touched.  On the GPU: the
-client's batched step over a particle set read from a file gives outputs bit
-for bit equal to the same step through the Python binding, and within the
-parity tolerance of the oracle."""
+client's batched step, and its per-task pack -> interact -> unpack calls, over
+a particle set read from a file give outputs bit for bit equal to the same
+calls through the Python binding, and within the parity tolerance of the
+oracle."""
 import os
 import subprocess
 import sys
@@ -86,27 +87,39 @@ def _read_output(path, n):
     return out
 
 
+BUNDLE = 8
+
+
 @pytest.mark.gpu
-@pytest.mark.parametrize("layout", ["SAOS_SHARED", "AOS", "SOA"])
-def test_client_step_matches_binding_and_oracle(layout, tmp_path):
+@pytest.mark.parametrize("mode,layout", [("step", "SAOS_SHARED"), ("step", "AOS"), ("step", "SOA"),
+                                         ("per_task", "SAOS_SHARED"), ("per_task", "SOA")])
+def test_client_step_matches_binding_and_oracle(mode, layout, tmp_path):
+    """step: sph_step_batched; per_task: the five per-task calls (pack,
+    density / gradient / force, unpack) over bundles of 8 tasks"""
     import torch
 
-    from gpuhelp import LOOP_OUT, compare_loop, device_store, log, oracle_loop
+    from gpuhelp import LOOP_OUT, compare_loop, device_store, log, oracle_loop, run_per_task
     binary = build_client.BIN
     assert os.path.exists(binary), "the C client is built by __graft_entry__.build()"
     ps = inputs.make_config(1, n_side=24, grid=4)   # 216 particles per cell: ragged tiles
     lay = sph.LAYOUTS.index(layout)
     _write_input(tmp_path / "in.bin", ps, lay)
-    log(f"C client step {layout} n={ps.n}")
-    r = subprocess.run([binary, "step", str(tmp_path / "in.bin"), str(tmp_path / "out.bin")], capture_output=True,
-                       text=True, timeout=120)
+    log(f"C client {mode} {layout} n={ps.n} tasks={len(ps.tasks)}")
+    args = [binary, mode, str(tmp_path / "in.bin"), str(tmp_path / "out.bin")]
+    if mode == "per_task":
+        args.append(str(BUNDLE))
+    r = subprocess.run(args, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     got = _read_output(tmp_path / "out.bin", ps.n)
-    # the same step through the Python binding: bit for bit
+    # the same through the Python binding: bit for bit
     plan = sph.Plan(ps.cells, ps.tasks, ps.n)
     st = device_store(ps, lay)
-    ws = torch.zeros(sph.sph_batched_ws_bytes(plan), dtype=torch.uint8, device="cuda")
-    sph.sph_step_batched(plan, st, ws)
+    if mode == "step":
+        ws = torch.zeros(sph.sph_batched_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+        sph.sph_step_batched(plan, st, ws)
+    else:
+        for loop in range(3):
+            run_per_task(plan, st, loop, len(ps.tasks), bundle=BUNDLE)
     torch.cuda.synchronize()
     for name, _ in OUT_FIELDS:
         assert st.get(name).tobytes() == got[name].tobytes(), name
@@ -116,7 +129,7 @@ def test_client_step_matches_binding_and_oracle(layout, tmp_path):
     for loop in range(3):
         ref = oracle_loop(ps.fields, loop, prev, epsx=eps, grid=True)
         errs = compare_loop(loop, {k: got[k] for k in LOOP_OUT[loop]}, ref)
-        log(f"C client {layout} loop {loop}: worst {max(errs.values()):.2e}")
+        log(f"C client {mode} {layout} loop {loop}: worst {max(errs.values()):.2e}")
         assert max(errs.values()) <= 1e-5, errs
         for k in LOOP_OUT[loop]:
             prev[k] = got[k].astype(np.float64)
