@@ -8,7 +8,7 @@ clustered set on its octree.  Besides the tolerance of the parity tests, the
 plain scaled error |q_gpu - q_ref| / max(|q_ref|, S) is logged.  At 256^3 the
 smoothing-length iteration, a kick-drift-kick step and the offload forms are
 checked the same way, as the benchmark's --hiter, --kdk and --offload runs
-launch them."""
+launch them, and the graph-captured step against the eager one."""
 import numpy as np
 import pytest
 
@@ -229,4 +229,33 @@ def test_gresho256_offload_sampled(form):
         if k in sph.FIELDS:
             got = hv.get(k)
             assert got.tobytes() == np.ascontiguousarray(want).astype(got.dtype).tobytes(), (form, k)
+    plan.close()
+
+
+def test_gresho256_graph_replays_match_eager():
+    """The staged step captured as one HIP graph with the benchmark's launch
+    parameters (the benchmark's graph line): three replays at 256^3, with eager
+    writes into the store's outputs between them, each leave the whole store
+    byte for byte as the eager step does."""
+    import torch
+    ps = _workload(2)
+    tuning, _ = bench_tuning(ps, "SAOS_SHARED")
+    plan = sph.Plan(ps.cells, ps.tasks, ps.n)
+    st = device_store(ps, sph.LAYOUTS.index("SAOS_SHARED"))
+    ws = torch.zeros(sph.sph_batched_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    sph.sph_step_batched(plan, st, ws, tuning=tuning)
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in st.subs]
+    g = sph.Graph(plan, st, ws, tuning=tuning)
+    for rep in range(3):
+        log(f"graph replay {rep} n={ps.n}")
+        st.put("rho", np.zeros(ps.n, np.float32))           # eager work between replays
+        st.put("a", np.full((ps.n, 3), 7.0, np.float32))
+        torch.cuda.synchronize()
+        assert not all(torch.equal(a, b) for a, b in zip(st.subs, ref))
+        g.launch()
+        torch.cuda.synchronize()
+        for s, (a, b) in enumerate(zip(st.subs, ref)):
+            assert torch.equal(a, b), (rep, s)
+    g.close()
     plan.close()
