@@ -1030,18 +1030,28 @@ struct KickArgs {
     float dt;
 };
 
-// v += a dt and u += u_dt dt, each a float32 product rounded, then a sum
+// v += a dt and u += u_dt dt, each a float32 product rounded, then a sum.
+// Every load is issued before the first store: loads and stores complete
+// through one in-order counter, so a load placed after a store would wait for
+// that store too, and the particle would take one memory round trip per field
+// instead of one in all.
 template <int L>
 __global__ __launch_bounds__(256) void k_kick(KickArgs a)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n) return;
+    float v[3], acc[3];
     static_for<0, 3>([&](auto cc) {
         constexpr int C = decltype(cc)::value;
-        const float v = ld<L, FV, C, float>(a.store, p), acc = ld<L, FA, C, float>(a.store, p);
-        st<L, FV, C, float>(a.store, p, v + acc * a.dt);
+        v[C] = ld<L, FV, C, float>(a.store, p);
+        acc[C] = ld<L, FA, C, float>(a.store, p);
     });
     const float u = ld<L, FU, 0, float>(a.store, p), udt = ld<L, FUDT, 0, float>(a.store, p);
+    __builtin_amdgcn_sched_barrier(0);
+    static_for<0, 3>([&](auto cc) {
+        constexpr int C = decltype(cc)::value;
+        st<L, FV, C, float>(a.store, p, v[C] + acc[C] * a.dt);
+    });
     st<L, FU, 0, float>(a.store, p, u + udt * a.dt);
 }
 
@@ -1083,7 +1093,7 @@ __global__ __launch_bounds__(256) void k_drift(DriftArgs a)
 {
     __shared__ double so[4];
     __shared__ float sh[4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     double out = 0.0;
     float hm = 0.0f;
     for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv; c < a.ntile;
@@ -1091,27 +1101,37 @@ __global__ __launch_bounds__(256) void k_drift(DriftArgs a)
         const Chunk ch = a.tiles[c];
         if (lane < ch.n) {
             const int64_t p = ch.part0 + lane;
-            const sph_cell &cl = a.cells[ch.cell];
+            const sph_cell cl = a.cells[ch.cell];
+            // every load before the first store (one memory round trip per
+            // tile, as in k_kick)
+            float v[3], acc[3], u = 0.0f, udt = 0.0f;
+            double x[3];
+            static_for<0, 3>([&](auto cc) {
+                constexpr int C = decltype(cc)::value;
+                v[C] = ld<L, FV, C, float>(a.store, p);
+                if constexpr (KICK) acc[C] = ld<L, FA, C, float>(a.store, p);
+                x[C] = ld<L, FX, C, double>(a.store, p);
+            });
             if constexpr (KICK) {
-                const float u = ld<L, FU, 0, float>(a.store, p), udt = ld<L, FUDT, 0, float>(a.store, p);
-                st<L, FU, 0, float>(a.store, p, u + udt * a.kick_dt);
+                u = ld<L, FU, 0, float>(a.store, p);
+                udt = ld<L, FUDT, 0, float>(a.store, p);
             }
+            hm = fmaxf(hm, ld<L, FH, 0, float>(a.store, p));
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (KICK) st<L, FU, 0, float>(a.store, p, u + udt * a.kick_dt);
             double e2 = 0.0;
             static_for<0, 3>([&](auto cc) {
                 constexpr int C = decltype(cc)::value;
-                float v = ld<L, FV, C, float>(a.store, p);
                 if constexpr (KICK) {
-                    v = v + ld<L, FA, C, float>(a.store, p) * a.kick_dt;
-                    st<L, FV, C, float>(a.store, p, v);
+                    v[C] = v[C] + acc[C] * a.kick_dt;
+                    st<L, FV, C, float>(a.store, p, v[C]);
                 }
-                const double x = ld<L, FX, C, double>(a.store, p);
-                const double xn = x + (double)v * a.dt;
+                const double xn = x[C] + (double)v[C] * a.dt;
                 st<L, FX, C, double>(a.store, p, xn);
                 const double e = fmax(fmax(cl.loc[C] - xn, xn - (cl.loc[C] + cl.width)), 0.0);
                 e2 = e2 + e * e;
             });
             out = fmax(out, sqrt(e2));
-            hm = fmaxf(hm, ld<L, FH, 0, float>(a.store, p));
         }
     }
     out = wave_max_d(out);
