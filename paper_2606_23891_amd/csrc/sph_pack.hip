@@ -487,14 +487,27 @@ __global__ __launch_bounds__(512) void k_unpack_chunks(UnpackArgs a)
     if (lane >= ch.n) return;
     const int64_t p = ch.part0 + lane;
     const int64_t slot = ch.slot0 - a.slot_base + lane;
+    // every load before the first store: loads and stores retire through one
+    // in-order counter, so a load behind a store would wait for it (one
+    // memory round trip per output instead of one in all)
+    float r[kResPlanes[LOOP]], cur[kResPlanes[LOOP]];
+    static_for<0, kResPlanes[LOOP]>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int F = kOutF[LOOP][k], C = kOutC[LOOP][k];
+        r[k] = 0.0f;
+        cur[k] = 0.0f;
+        if constexpr (MASKED)
+            if (!((a.mask >> k) & 1u)) return;
+        r[k] = a.res[k * a.P + slot];
+        if constexpr (!CELLS) cur[k] = ld<L, F, C, float>(a.store, p);
+    });
+    __builtin_amdgcn_sched_barrier(0);
     static_for<0, kResPlanes[LOOP]>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         constexpr int F = kOutF[LOOP][k], C = kOutC[LOOP][k];
         if constexpr (MASKED)
             if (!((a.mask >> k) & 1u)) return;
-        const float r = a.res[k * a.P + slot];
-        const float cur = CELLS ? 0.0f : ld<L, F, C, float>(a.store, p);
-        st<L, F, C, float>(a.store, p, reduce_one<LOOP, k>(cur, r));
+        st<L, F, C, float>(a.store, p, reduce_one<LOOP, k>(cur[k], r[k]));
     });
 }
 
@@ -508,13 +521,25 @@ __global__ __launch_bounds__(256) void k_unpack_csr(UnpackArgs a)
     const int64_t e = a.csr_off[p + 1];
     while (b < e && a.csr[b] < a.slot_lo) ++b;
     if (b == e || a.csr[b] >= a.slot_hi) return;
+    // every output's current value and every partial read before the first
+    // store (a load behind a store waits for it); each output still takes its
+    // partials in ascending slot order
+    float cur[kResPlanes[LOOP]];
     static_for<0, kResPlanes[LOOP]>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        constexpr int F = kOutF[LOOP][k], C = kOutC[LOOP][k];
-        float cur = ld<L, F, C, float>(a.store, p);
-        for (int64_t q = b; q < e && a.csr[q] < a.slot_hi; ++q)
-            cur = reduce_one<LOOP, k>(cur, a.res[k * a.P + (a.csr[q] - a.slot_lo)]);
-        st<L, F, C, float>(a.store, p, cur);
+        cur[k] = ld<L, kOutF[LOOP][k], kOutC[LOOP][k], float>(a.store, p);
+    });
+    for (int64_t q = b; q < e && a.csr[q] < a.slot_hi; ++q) {
+        const int64_t s = a.csr[q] - a.slot_lo;
+        static_for<0, kResPlanes[LOOP]>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            cur[k] = reduce_one<LOOP, k>(cur[k], a.res[k * a.P + s]);
+        });
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    static_for<0, kResPlanes[LOOP]>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        st<L, kOutF[LOOP][k], kOutC[LOOP][k], float>(a.store, p, cur[k]);
     });
 }
 
